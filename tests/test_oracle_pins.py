@@ -1,0 +1,426 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each check below is computed independently of the oracle's own code (NumPy
+brute force, closed forms, the paper's worked example, invariants), so that a
+dropped term, a wrong index or a transposed operand in the oracle fails one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers --
+def np_knn(X, q, k, ids=None):
+    """Exact k-NN by (squared distance, id), NumPy FP64."""
+    X64 = X.astype(np.float64)
+    d2 = ((X64 - q.astype(np.float64)) ** 2).sum(axis=1)
+    if ids is None:
+        ids = np.arange(X.shape[0])
+    else:
+        d2 = d2[ids]
+    order = np.lexsort((ids, d2))[:k]
+    return np.asarray(ids)[order], np.sqrt(d2[order])
+
+
+def small_index(n=600, d=16, ns=4, sk=4, seed=3, kind="clustered", iters=10):
+    X = synth.tiny(n, d, seed, kind, levels=4)
+    c64, c32, asg, obj = oracle.build_index(X, ns, sk, iters=iters, seed=seed)
+    return X, oracle.Index(X, ns, sk, c32, asg), (c64, c32, asg, obj)
+
+
+def grid_index(sk, sizes):
+    """An oracle index whose IMI cell c = a1*sk + a2 holds sizes[c] points."""
+    a1, a2 = [], []
+    for c, m in enumerate(sizes):
+        a1 += [c // sk] * m
+        a2 += [c % sk] * m
+    n = len(a1)
+    X = np.zeros((n, 2), np.float32)
+    asg = np.stack([np.array(a1, np.int32), np.array(a2, np.int32)])
+    cent = np.zeros(sk * 2, np.float32)
+    return oracle.Index(X, 1, sk, cent, asg)
+
+
+# ------------------------------------------------------------- counts/layout
+def test_counts_A_B():
+    # Alg. 3 stop rule and Alg. 1/4 candidate loop at the workloads' settings
+    assert oracle.count_A(0.03, 1_000_000) == 30_000        # 0.03*1e6 is 30000.000000000004 in FP64
+    assert oracle.count_A(0.05, 10_000) == 500
+    assert oracle.count_A(0.01, 1_000_000) == 10_000
+    assert oracle.count_A(0.02, 10_000_000) == 200_000
+    assert oracle.count_A(1e-9, 100) == 1                  # at least one point
+    assert oracle.count_A(1.0, 77) == 77
+    assert oracle.count_A(0.0301, 1000) == 31              # ceiling
+    assert oracle.count_B(0.005, 1_000_000, 10) == 5_000
+    assert oracle.count_B(0.005, 10_000, 10) == 50
+    assert oracle.count_B(0.001, 10_000, 50) == 50         # raised to k
+    assert oracle.count_B(0.0059, 1000, 1) == 5            # floor
+    assert oracle.count_B(1.0, 123, 5) == 123
+
+
+def test_layout_contiguous_division():
+    # Sec. 3.2 contiguous division; Def. 3: the last subspace takes the remainder
+    d0, w = oracle.layout(128, 8)
+    assert list(d0) == [8 * g for g in range(16)] and set(w) == {8}
+    d0, w = oracle.layout(10, 3)
+    assert list(d0) == [0, 1, 3, 4, 6, 8] and list(w) == [1, 2, 1, 2, 2, 2]
+    d0, w = oracle.layout(960, 20)
+    assert set(w) == {24} and d0[-1] == 960 - 24
+    d0, w = oracle.layout(96, 8)
+    assert set(w) == {6}
+
+
+# ------------------------------------------------------- Dynamic Activation --
+def test_da_worked_example_fig5():
+    g = json.load(open(os.path.join(GOLDEN, "da_fig5.json")))
+    ix = grid_index(3, [1] * 9)
+    d1, d2 = np.array(g["dists1"]), np.array(g["dists2"])
+    ident = np.arange(3, dtype=np.int32)
+    cells, ap, trace = ix.da_trace(0, d1, ident, d2, ident, A=9)
+    for r, (a, b, key) in enumerate(g["first_rounds"]):
+        assert divmod(int(cells[r]), 3) == (a, b)
+        assert abs(d1[a] + d2[b] - key) < 1e-12
+    assert list(trace[:3]) == g["active_rows_after_round"]
+    assert ap == 9 and len(cells) == 9 and sorted(cells) == list(range(9))
+    # stop rule: A=2 stops after round 2 (two unit cells)
+    cells2, ap2, _ = ix.da_trace(0, d1, ident, d2, ident, A=2)
+    assert list(cells2) == [0, 3] and ap2 == 2
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_da_three_forms_agree_with_numpy_prefix(seed):
+    rng = np.random.default_rng(seed)
+    sk = int(rng.integers(1, 9))
+    sizes = rng.integers(0, 5, size=sk * sk)
+    sizes[rng.integers(0, sk * sk)] += 1                  # n >= 1
+    ix = grid_index(sk, sizes.tolist())
+    n = int(sizes.sum())
+    if seed % 2:
+        d1 = rng.integers(0, 4, size=sk).astype(np.float64)   # forces key ties
+        d2 = rng.integers(0, 4, size=sk).astype(np.float64)
+    else:
+        d1, d2 = rng.random(sk), rng.random(sk)
+    i1 = np.lexsort((np.arange(sk), d1)).astype(np.int32)
+    i2 = np.lexsort((np.arange(sk), d2)).astype(np.int32)
+    for A in sorted({1, max(1, n // 3), max(1, n // 2), n}):
+        res = [ix.da(0, d1, i1, d2, i2, A, form=f) for f in (0, 1, 2)]
+        for cells, ap in res[1:]:
+            assert np.array_equal(cells, res[0][0]) and ap == res[0][1]
+        # independent: lexicographic (key, r1, r2) order, shortest prefix reaching A
+        r1, r2 = np.meshgrid(np.arange(sk), np.arange(sk), indexing="ij")
+        key = d1[i1][r1] + d2[i2][r2]
+        order = np.lexsort((r2.ravel(), r1.ravel(), key.ravel()))
+        cellid = (i1[r1] * sk + i2[r2]).ravel()[order]
+        cum = np.cumsum(sizes[cellid])
+        m = int(np.searchsorted(cum, A) + 1)
+        assert np.array_equal(res[0][0], cellid[:m])
+        assert res[0][1] == cum[m - 1] >= A
+        assert m == 1 or cum[m - 2] < A
+
+
+# ------------------------------------------------------ SC-Linear (Alg. 1) --
+@pytest.mark.parametrize("seed,kind", [(1, "gauss"), (2, "int"), (3, "clustered")])
+def test_sclinear_scores_equal_def4_rank_count(seed, kind):
+    X = synth.tiny(300, 12, seed, kind, levels=3)
+    Q = synth.tiny(4, 12, seed + 100, kind, levels=3)
+    ns, alpha = 3, 0.1
+    A = oracle.count_A(alpha, 300)
+    _, _, sc = oracle.sclinear(X, ns, Q, 5, alpha, 0.05, want_scores=True)
+    d0, w = oracle.layout(12, ns)
+    for qi, q in enumerate(Q):
+        expect = np.zeros(300, np.int64)
+        for i in range(ns):
+            lo, hi = d0[2 * i], d0[2 * i] + w[2 * i] + w[2 * i + 1]
+            dsub = ((X[:, lo:hi].astype(np.float64) - q[lo:hi]) ** 2).sum(axis=1)
+            # rank_i(o) = #{o' : (d(o'), id') < (d(o), id)}, by pairwise comparison
+            less = (dsub[None, :] < dsub[:, None]) | ((dsub[None, :] == dsub[:, None]) &
+                                                      (np.arange(300)[None, :] < np.arange(300)[:, None]))
+            rank = less.sum(axis=1)
+            expect += rank < A
+        assert np.array_equal(sc[qi].astype(np.int64), expect)
+
+
+def test_sclinear_single_subspace_is_exact_knn():
+    # Def. 1: with one subspace covering all d dims and A = B = k, the k colliding
+    # points are exactly the k nearest
+    X = synth.tiny(500, 10, 7, "gauss")
+    Q = synth.tiny(5, 10, 8, "gauss")
+    k = 7
+    ids, dist = oracle.sclinear(X, 1, Q, k, k / 500, k / 500)
+    for qi, q in enumerate(Q):
+        e_ids, e_d = np_knn(X, q, k)
+        assert np.array_equal(ids[qi], e_ids)
+        assert np.allclose(dist[qi], e_d, rtol=1e-12)
+
+
+# ----------------------------------------------------- SuCo (Alg. 2, 3, 4) --
+@pytest.mark.parametrize("kind", ["gauss", "int", "clustered"])
+def test_alpha_beta_one_reduces_to_exact_search(kind):
+    X, ix, _ = small_index(kind=kind)
+    Q = synth.tiny(6, 16, 99, kind, levels=4)
+    k = 8
+    out = ix.query(Q, k, 1.0, 1.0)
+    ids_l, d_l = oracle.sclinear(X, 4, Q, k, 1.0, 1.0)
+    for qi, q in enumerate(Q):
+        e_ids, e_d = np_knn(X, q, k)
+        assert np.array_equal(out["ids"][qi], e_ids)
+        assert np.array_equal(ids_l[qi], e_ids)
+        assert np.allclose(out["dists"][qi], e_d, rtol=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [0.01, 0.1, 0.4])
+def test_beta_one_exact_for_any_alpha(alpha):
+    X, ix, _ = small_index(kind="gauss", seed=5)
+    Q = synth.tiny(4, 16, 55, "gauss")
+    out = ix.query(Q, 5, alpha, 1.0)
+    for qi, q in enumerate(Q):
+        assert np.array_equal(out["ids"][qi], np_knn(X, q, 5)[0])
+
+
+def test_alpha_one_all_scores_ns_and_lowest_ids_selected():
+    X, ix, _ = small_index(kind="clustered", seed=9)
+    Q = synth.tiny(3, 16, 77, "clustered")
+    beta, k = 0.05, 4
+    B = oracle.count_B(beta, 600, k)
+    out = ix.query(Q, k, 1.0, beta, want_scores=True, want_cand=True)
+    assert (out["scores"] == 4).all()
+    for qi, q in enumerate(Q):
+        assert list(out["cand"][qi]) == list(range(B))
+        assert np.array_equal(out["ids"][qi], np_knn(X, q, k, ids=np.arange(B))[0])
+
+
+def test_single_cell_index_degenerates_like_alpha_one():
+    X = synth.tiny(200, 8, 4, "gauss")
+    c64, c32, asg, _ = oracle.build_index(X, 2, 1, iters=3)
+    assert (asg == 0).all()
+    ix = oracle.Index(X, 2, 1, c32, asg)
+    out = ix.query(synth.tiny(2, 8, 5, "gauss"), 3, 0.05, 0.1, want_scores=True, want_cand=True)
+    assert (out["scores"] == 2).all()
+    assert list(out["cand"][0]) == list(range(20))
+
+
+@pytest.mark.parametrize("kind", ["gauss", "int"])
+def test_suco_scores_count_activated_cells(kind):
+    X, ix, (c64, c32, asg, _) = small_index(kind=kind, seed=11)
+    Q = synth.tiny(5, 16, 12, kind, levels=4)
+    ns, sk, n = 4, 4, 600
+    d0, w = oracle.layout(16, ns)
+    cent = c32.astype(np.float64)
+    prev = None
+    for alpha in (0.02, 0.1, 0.3):
+        A = oracle.count_A(alpha, n)
+        out = ix.query(Q, 5, alpha, 0.05, want_scores=True)
+        assert (out["scores"].sum(axis=1) == out["aprime"].sum(axis=1)).all()
+        for qi, q in enumerate(Q):
+            expect = np.zeros(n, np.int64)
+            for i in range(ns):
+                # independent DA: centre distances, rank, lexicographic prefix
+                dh = []
+                for h in range(2):
+                    g = 2 * i + h
+                    C = cent[sk * d0[g]: sk * (d0[g] + w[g])].reshape(sk, w[g])
+                    dh.append(((C - q[d0[g]:d0[g] + w[g]].astype(np.float64)) ** 2).sum(axis=1))
+                cell = asg[2 * i] * sk + asg[2 * i + 1]
+                size = np.bincount(cell, minlength=sk * sk)
+                o1 = np.lexsort((np.arange(sk), dh[0]))
+                o2 = np.lexsort((np.arange(sk), dh[1]))
+                r1, r2 = np.meshgrid(np.arange(sk), np.arange(sk), indexing="ij")
+                key = dh[0][o1][r1] + dh[1][o2][r2]
+                order = np.lexsort((r2.ravel(), r1.ravel(), key.ravel()))
+                cid = (o1[r1] * sk + o2[r2]).ravel()[order]
+                cum = np.cumsum(size[cid])
+                m = int(np.searchsorted(cum, A) + 1)
+                act = np.zeros(sk * sk, bool)
+                act[cid[:m]] = True
+                expect += act[cell]
+                assert out["aprime"][qi, i] == cum[m - 1] >= A
+                assert cum[m - 1] - size[cid[m - 1]] < A
+            assert np.array_equal(out["scores"][qi].astype(np.int64), expect)
+        if prev is not None:
+            assert (out["scores"] >= prev).all()          # non-decreasing in alpha
+        prev = out["scores"]
+
+
+def test_da_forms_give_identical_queries():
+    X, ix, _ = small_index(kind="int", seed=21)
+    Q = synth.tiny(6, 16, 22, "int", levels=4)
+    outs = [ix.query(Q, 5, 0.07, 0.05, form=f, want_scores=True) for f in (0, 1, 2)]
+    for o in outs[1:]:
+        assert np.array_equal(o["scores"], outs[0]["scores"])
+        assert np.array_equal(o["ids"], outs[0]["ids"])
+
+
+# ------------------------------------------------------- select / re-rank --
+@pytest.mark.parametrize("seed", range(5))
+def test_select_properties(seed):
+    rng = np.random.default_rng(seed)
+    n, ns = 997, 6
+    s = rng.integers(0, ns + 1, size=n).astype(np.uint8)
+    for B in (1, 10, 100, 500, n):
+        c = oracle.select(s, B)
+        assert len(c) == B == len(set(c.tolist()))
+        inside = np.zeros(n, bool)
+        inside[c] = True
+        if B < n:
+            T = s[inside].min()
+            assert T >= s[~inside].max()
+            # among points scoring exactly T, the lowest ids are taken
+            eq = np.flatnonzero(s == T)
+            take = inside[eq]
+            assert take[: take.sum()].all() and not take[take.sum():].any()
+
+
+def test_rerank_is_bruteforce_over_candidates():
+    X = synth.tiny(400, 9, 31, "int", levels=3)          # many exact distance ties
+    q = synth.tiny(1, 9, 32, "int", levels=3)[0]
+    cand = np.random.default_rng(0).choice(400, 120, replace=False).astype(np.int32)
+    ids, dist = oracle.rerank(X, q, cand, 15)
+    e_ids, e_d = np_knn(X, q, 15, ids=cand)
+    assert np.array_equal(ids, e_ids)
+    assert np.array_equal(dist, e_d)
+
+
+def test_bruteforce_matches_numpy():
+    X = synth.tiny(300, 7, 41, "gauss")
+    Q = synth.tiny(4, 7, 42, "gauss")
+    ids, dist = oracle.bruteforce(X, Q, 6)
+    for qi, q in enumerate(Q):
+        e_ids, e_d = np_knn(X, q, 6)
+        assert np.array_equal(ids[qi], e_ids)
+        assert np.allclose(dist[qi], e_d, rtol=1e-13)
+
+
+# --------------------------------------------------------- index (Alg. 2) --
+def test_kmeans_invariants():
+    X = synth.tiny(800, 6, 51, "clustered")
+    d0, w = oracle.layout(6, 1)
+    init = oracle.init_ids(X, 1, 5, 1, 0)
+    assert len(set(init.tolist())) == 5
+    cent, asg, obj = oracle.kmeans(X, int(d0[0]), int(w[0]), 5, 30, init)
+    # Lloyd never increases the objective
+    assert (np.diff(obj) <= 1e-9 * obj[0]).all()
+    # final assignment is the argmin with lowest-id ties
+    H = X[:, d0[0]:d0[0] + w[0]].astype(np.float64)
+    D = ((H[:, None, :] - cent[None, :, :]) ** 2).sum(axis=2)
+    assert np.array_equal(asg, np.argmin(D, axis=1))
+    assert np.bincount(asg, minlength=5).sum() == 800
+    assert abs(obj[-1] - D.min(axis=1).sum()) <= 1e-9 * obj[-1]
+    # at a fixed point every centre is the mean of its members
+    if obj[-1] == obj[-2]:
+        for c in range(5):
+            m = asg == c
+            if m.any():
+                assert np.allclose(cent[c], H[m].mean(axis=0), rtol=1e-12, atol=1e-12)
+
+
+def test_kmeans_separates_obvious_clusters():
+    rng = np.random.default_rng(0)
+    centres = np.array([[-10.0, 0.0], [0.0, 10.0], [10.0, 0.0]])
+    lab = rng.integers(0, 3, 600)
+    X = (centres[lab] + 0.1 * rng.normal(size=(600, 2))).astype(np.float32)
+    # one initial centre inside each cluster: Lloyd must then recover the labels
+    init = np.array([np.flatnonzero(lab == c)[0] for c in (2, 0, 1)], np.int64)
+    cent, a, obj = oracle.kmeans(X, 0, 2, 3, 20, init)
+    assert np.array_equal(a, np.array([1, 2, 0])[lab])
+    assert np.allclose(cent, centres[[2, 0, 1]], atol=0.05)
+
+
+def test_imi_invariants():
+    X, ix, (c64, c32, asg, obj) = small_index(kind="gauss", seed=61)
+    offs, ids = ix.offs(), ix.ids()
+    sk, ns, n = 4, 4, 600
+    assert np.array_equal(c32, c64.astype(np.float32))
+    for i in range(ns):
+        assert offs[i, 0] == 0 and offs[i, -1] == n and (np.diff(offs[i]) >= 0).all()
+        assert np.array_equal(np.sort(ids[i]), np.arange(n))
+        cell = asg[2 * i] * sk + asg[2 * i + 1]
+        for c in range(sk * sk):
+            mem = ids[i, offs[i, c]:offs[i, c + 1]]
+            assert (np.diff(mem) > 0).all()
+            assert (cell[mem] == c).all()
+            assert len(mem) == (cell == c).sum()
+
+
+def test_centroid_dists_closed_form():
+    X, ix, (c64, c32, asg, _) = small_index(kind="gauss", seed=71)
+    q = synth.tiny(1, 16, 72, "gauss")[0]
+    d0, w = oracle.layout(16, 4)
+    for g in range(8):
+        C = c32[4 * d0[g]: 4 * (d0[g] + w[g])].reshape(4, w[g]).astype(np.float64)
+        e = ((C - q[d0[g]:d0[g] + w[g]]) ** 2).sum(axis=1)
+        assert np.allclose(ix.centroid_dists(q, g), e, rtol=1e-14)
+
+
+# ------------------------------------------------- paper's qualitative claim
+def test_scores_favour_true_neighbours():
+    # Sec. 3.3: points closer to the query tend to have larger SC-scores
+    W = synth.Workload(1)
+    X = W.data(3000)
+    Q = W.queries(8)
+    _, c32, asg, _ = oracle.build_index(X, 8, 8, iters=8)
+    ix = oracle.Index(X, 8, 8, c32, asg)
+    out = ix.query(Q, 10, 0.1, 0.02, want_scores=True)
+    for qi, q in enumerate(Q):
+        nn, _ = np_knn(X, q, 10)
+        assert out["scores"][qi][nn].mean() > out["scores"][qi].mean() + 2.0
+
+
+# ------------------------------------------------------------- MLP / BF16 --
+def test_gelu_values():
+    assert oracle.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(oracle.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15     # Phi(1)
+    assert abs(oracle.gelu(np.array([-1.0]))[0] + 0.15865525393145707) < 1e-15   # -Phi(-1)
+
+
+def test_mlp_gradient_matches_central_differences():
+    from oracle.mlp import MLP64, init_params, PARAM_NAMES
+    rng = np.random.default_rng(0)
+    p = init_params(5, 7, seed=3)
+    for k in p:
+        p[k] = p[k] + 0.1 * rng.normal(size=p[k].shape)   # non-zero biases too
+    net = MLP64(p, mu=rng.normal(size=5), sigma=1.0 + rng.random(5))
+    F = rng.normal(size=(9, 5))
+    t = rng.normal(size=9)
+    _, g = net.loss_and_grad(F, t)
+    h = 1e-6
+    for name in PARAM_NAMES:
+        flat = net.p[name].reshape(-1)
+        for j in range(flat.size):
+            old = flat[j]
+            flat[j] = old + h
+            lp, _ = net.loss_and_grad(F, t)
+            flat[j] = old - h
+            lm, _ = net.loss_and_grad(F, t)
+            flat[j] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[j]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_adam_first_step_moves_by_lr():
+    # Kingma & Ba: with bias correction the first step is lr * sign(g) (up to eps)
+    from oracle.mlp import MLP64, init_params
+    net = MLP64(init_params(3, 4, seed=1))
+    before = {k: v.copy() for k, v in net.p.items()}
+    g = {k: np.full_like(v, 0.5) for k, v in net.p.items()}
+    net.adam_step(g, {}, lr=1e-3)
+    for k in net.p:
+        assert np.allclose(before[k] - net.p[k], 1e-3, rtol=1e-6)
+
+
+def test_bf16_round_to_nearest_even():
+    import torch
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5, 3.14159, 1e-30, 65504.0, 0.0], np.float32)
+    r = oracle.bf16_round(vals)
+    assert r[1] == 1.0 and r[2] == np.float32(1.015625)
+    t = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(r, t)
+    x = np.random.default_rng(0).normal(size=10000).astype(np.float32) * 100
+    assert np.array_equal(oracle.bf16_round(x),
+                          torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy())
