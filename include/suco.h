@@ -1,0 +1,191 @@
+/*
+ * suco.h -- C ABI of the MI355X (gfx950) SuCo query library.
+ *
+ * SuCo answers k-approximate-nearest-neighbour queries with the Subspace
+ * Collision framework (arXiv 2411.14754).  The problem (Sec. 1): given a
+ * dataset D of n points in R^d, a query q and k, return k points of D close
+ * to q; quality is recall |R intersect R*|/k against the exact k-NN R*.
+ *
+ * Conventions for every call:
+ *  - Return value: SUCO_OK (0) or a negative SUCO_E_* code.  On error nothing
+ *    is enqueued and no output is written; suco_last_error() (thread-local)
+ *    describes the failure.  No C++ exception crosses this boundary.
+ *  - Arguments are validated synchronously, before any GPU work is enqueued.
+ *  - "device" pointers are HIP device memory on the index's device (for
+ *    example torch.cuda tensors' data_ptr()); "host" pointers are ordinary
+ *    CPU memory.  The caller owns every pointer it passes; the library never
+ *    frees or keeps a caller pointer after the call returns (the dataset is
+ *    copied into the index).
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Query
+ *    calls are asynchronous on that stream: outputs are valid once the stream
+ *    has been synchronised.  Build calls synchronise before returning.
+ *  - An index is read-only after it is built and may be queried from several
+ *    host threads, but queries on one index share its workspace: the library
+ *    serialises them (a query on a new stream waits for the previous query's
+ *    stream), so concurrent queries on one index do not overlap on the GPU.
+ *  - Results are deterministic: identical inputs give bitwise identical
+ *    outputs, on any stream and any batching.
+ *  - Row-major layouts everywhere: D [n][d], Q [nq][d], ids/dists [nq][k].
+ */
+#ifndef SUCO_H
+#define SUCO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SUCO_API __attribute__((visibility("default")))
+#else
+#define SUCO_API
+#endif
+
+#define SUCO_OK 0
+#define SUCO_E_INVAL -1        /* an argument is out of range or NULL          */
+#define SUCO_E_NOMEM -2        /* device or host allocation failed             */
+#define SUCO_E_HIP -3          /* a HIP runtime call or kernel launch failed    */
+#define SUCO_E_STATE -4        /* wrong device, freed or unusable handle       */
+#define SUCO_E_UNSUPPORTED -5  /* valid but outside what the GPU path handles  */
+
+typedef struct suco_index suco_index;
+
+/* Optional build parameters (pass NULL for the defaults). */
+typedef struct suco_build_params {
+    int32_t iters;      /* k-means iterations t (Table 1, Alg. 2); <= 0 means 25      */
+    uint64_t seed;      /* k-means initialisation seed; 0 means 1                      */
+    int32_t tile_max;   /* most point ids per collision tile, a multiple of 256 in
+                           [256, 65536]; 0 means 65536.  Each query's SC-scores are
+                           counted tile by tile in on-chip memory.                    */
+    int32_t query_chunk;/* queries processed per internal pass; 0 means automatic    */
+} suco_build_params;
+
+SUCO_API int suco_version(void);
+SUCO_API const char *suco_last_error(void);
+
+/* Number of points activated per subspace, A = max(1, ceil(alpha*n)) capped at n
+ * (Alg. 3 stops once alpha*n points are retrieved), and the number of
+ * candidates re-ranked, B = max(k, floor(beta*n)) capped at n (Alg. 4 re-ranks
+ * beta*n points; raised to k so that a top-k exists).  Both are evaluated in
+ * FP64 with a 1e-9 guard against representation error. */
+SUCO_API int64_t suco_count_A(double alpha, int64_t n);
+SUCO_API int64_t suco_count_B(double beta, int64_t n, int32_t k);
+
+/* ---------------------------------------------------------------- build --
+ * Create Index (Alg. 2).  The d dimensions are divided into n_s contiguous
+ * subspaces (Sec. 3.2; the last takes the remainder, Def. 3), each split into
+ * two halves (first floor(s/2) dims, then the rest).  Each half is clustered
+ * by Lloyd's k-means into sqrt_k centres with FP64 sums (t iterations from a
+ * SplitMix64-drawn set of distinct rows, then a final assignment); the
+ * inverted multi-index of subspace i maps cell a1*sqrt_k + a2 to its point
+ * ids in ascending order.  Centres are stored in FP32 (rounded once).
+ *
+ *  D      device [n][d] float32, copied into the index.
+ *  limits 1 <= n < 2^31; 2 <= d; 1 <= n_s <= min(127, d/2);
+ *         1 <= sqrt_k <= 128 and sqrt_k <= n.
+ *  out    receives the new handle (unchanged on error).
+ */
+SUCO_API int suco_build(const float *D, int64_t n, int32_t d, int32_t n_s, int32_t sqrt_k,
+               const suco_build_params *p, void *stream, suco_index **out);
+
+/* Create an index from given centres and assignments instead of running
+ * k-means (for example an index saved earlier, or one computed elsewhere).
+ *  centroids  host float32, the 2*n_s halves one after another: half g
+ *             (g = 2*i + h) is sqrt_k rows of its width, starting at element
+ *             sqrt_k * (first dimension of the half).  Total sqrt_k*d values.
+ *  assign     host int32 [2*n_s][n], values in [0, sqrt_k).
+ */
+SUCO_API int suco_build_from_index(const float *D, int64_t n, int32_t d, int32_t n_s, int32_t sqrt_k,
+                          const float *centroids, const int32_t *assign,
+                          const suco_build_params *p, void *stream, suco_index **out);
+
+/* Copy the canonical index out: FP32 centres (layout as above) and the
+ * assignments, both host memory; either may be NULL. */
+SUCO_API int suco_index_export(const suco_index *ix, float *centroids, int32_t *assign);
+
+/* Shape of an index; any output may be NULL. */
+SUCO_API int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, int32_t *sqrt_k);
+
+/* Release an index (NULL is accepted).  Waits for its pending queries. */
+SUCO_API int suco_index_free(suco_index *ix);
+
+/* ---------------------------------------------------------------- query --
+ * k-ANN Query (Alg. 4 with Dynamic Activation, Alg. 3), one batch:
+ *  1. per subspace, squared distances from each query half to the sqrt_k
+ *     centres of that half, sorted ascending (ties by centre id);
+ *  2. Dynamic Activation: cells are taken in ascending order of
+ *     dist1 + dist2 (ties by the two ranks) until at least A points are
+ *     retrieved -- the shortest such prefix, whole cells;
+ *  3. every point in an activated cell gets +1 SC-score (Def. 4);
+ *  4. the B points with the highest SC-scores (ties: lowest ids) are kept;
+ *  5. they are re-ranked by exact squared L2 in FP32 and the k nearest are
+ *     returned by (distance, id).
+ *
+ *  Q      device [nq][d] float32 queries.
+ *  ids    device [nq][k] int32 result point ids, nearest first.
+ *  dists  device [nq][k] float32 Euclidean (not squared) distances.
+ *  limits nq >= 0 (0 is a no-op), 1 <= k <= 64, k <= n, 0 < alpha <= 1,
+ *         0 < beta <= 1.
+ */
+SUCO_API int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
+               double beta, int32_t *ids, float *dists, void *stream);
+
+/* As suco_query with one collision ratio per query: alpha_q device [nq]
+ * float32, each in (0, 1]; query j activates A_j = max(1, ceil(alpha_q[j]*n))
+ * points per subspace (the value is widened to FP64 before the product). */
+SUCO_API int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, int32_t k,
+                     const float *alpha_q, double beta, int32_t *ids, float *dists, void *stream);
+
+/* As suco_query_alpha (alpha_q may be NULL, then `alpha` is used for every
+ * query), also exporting the intermediate results of every step; each extra
+ * output is device memory and may be NULL:
+ *  scores  uint8 [nq][n]      SC-scores after step 3
+ *  cand    int32 [nq][B]      step-4 candidates in ascending id order
+ *  ncells  int32 [nq][n_s]    number of cells activated per subspace
+ *  aprime  int32 [nq][n_s]    points in those cells (>= A)
+ *  cells   uint16 [nq][n_s][sqrt_k^2]  activated cell ids (a1*sqrt_k + a2),
+ *                             the first ncells entries of each row are valid
+ *  feat    float32 [nq][2*n_s] distance from each query half to its nearest
+ *                             centre (sqrt of the smallest step-1 value)
+ */
+SUCO_API int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k,
+                     const float *alpha_q, double alpha, double beta, int32_t *ids, float *dists,
+                     uint8_t *scores, int32_t *cand, int32_t *ncells, int32_t *aprime,
+                     uint16_t *cells, float *feat, void *stream);
+
+/* ------------------------------------------------------- single steps --
+ * The steps of the query path on their own, fed by the caller; they let each
+ * step be checked in isolation and let other activation rules reuse the rest.
+ *
+ * Collision counting and selection (steps 3-4) from given activated cells:
+ *  cells   device uint16 [nq][n_s][sqrt_k^2], ncells device int32 [nq][n_s]
+ *  scores  device uint8 [nq][n] (may be NULL), cand device int32 [nq][B]
+ *          with B = suco_count_B(beta, n, k).
+ */
+SUCO_API int suco_collide_select(const suco_index *ix, int64_t nq, const uint16_t *cells,
+                        const int32_t *ncells, int32_t k, double beta, uint8_t *scores,
+                        int32_t *cand, void *stream);
+
+/* Re-rank (step 5) given candidate lists: cand device int32 [nq][B] of ids
+ * in [0, n) (repeats not allowed); returns the k nearest by (distance, id). */
+SUCO_API int suco_rerank(const suco_index *ix, const float *Q, int64_t nq, const int32_t *cand,
+                int64_t B, int32_t k, int32_t *ids, float *dists, void *stream);
+
+/* ----------------------------------------------------------- timing --
+ * Per-step timing for measurement: while enabled, every launch of a query
+ * call is bracketed by a pair of HIP events on the query stream (a few
+ * microseconds per launch).  suco_profile_read waits for the recorded work
+ * and returns, per step, the summed milliseconds and launch counts since the
+ * last read, then resets.  Steps, in order: 0 activate (centre distances and
+ * Dynamic Activation), 1 collide (SC-score counting), 2 select (top-B by
+ * score), 3 rerank (candidate distances, partial top-k), 4 merge (final top-k).
+ *  ms        host double [5]
+ *  launches  host int64 [5] */
+SUCO_API int suco_profile(suco_index *ix, int enable);
+SUCO_API int suco_profile_read(suco_index *ix, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUCO_H */

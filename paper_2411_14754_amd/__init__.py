@@ -1,0 +1,254 @@
+"""SuCo on MI355X: Python binding of the C ABI in include/suco.h.
+
+Argument marshalling only: tensors are checked for device, dtype and layout
+and their data pointers are handed to libsuco.so; every step of the search
+runs in the library's HIP kernels.  PyTorch provides device memory and the
+current stream.  There is no fallback: if the compiled library is missing,
+loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsuco.so")
+
+SUCO_OK, SUCO_E_INVAL, SUCO_E_NOMEM, SUCO_E_HIP, SUCO_E_STATE, SUCO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+EXPORTED = (
+    "suco_version", "suco_last_error", "suco_count_A", "suco_count_B", "suco_build",
+    "suco_build_from_index", "suco_index_export", "suco_index_info", "suco_index_free", "suco_query",
+    "suco_query_alpha", "suco_query_debug", "suco_collide_select", "suco_rerank", "suco_profile",
+    "suco_profile_read",
+)
+
+STAGES = ("activate", "collide", "select", "rerank", "merge")
+
+
+class SucoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"suco error {code}: {msg}")
+        self.code = code
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("seed", C.c_uint64), ("tile_max", C.c_int32),
+                ("query_chunk", C.c_int32)]
+
+
+_lib = None
+P = C.c_void_p
+i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
+
+
+def lib():
+    """Load libsuco.so (built by __graft_entry__.build() or paper_2411_14754_amd._build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        L.suco_version.restype = C.c_int
+        L.suco_last_error.restype = C.c_char_p
+        L.suco_count_A.restype = i64
+        L.suco_count_A.argtypes = [dbl, i64]
+        L.suco_count_B.restype = i64
+        L.suco_count_B.argtypes = [dbl, i64, i32]
+        L.suco_build.argtypes = [P, i64, i32, i32, i32, C.POINTER(BuildParams), P, C.POINTER(P)]
+        L.suco_build_from_index.argtypes = [P, i64, i32, i32, i32, P, P, C.POINTER(BuildParams), P,
+                                            C.POINTER(P)]
+        L.suco_index_export.argtypes = [P, P, P]
+        L.suco_index_info.argtypes = [P, P, P, P, P]
+        L.suco_index_free.argtypes = [P]
+        L.suco_query.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
+        L.suco_query_alpha.argtypes = [P, P, i64, i32, P, dbl, P, P, P]
+        L.suco_query_debug.argtypes = [P, P, i64, i32, P, dbl, dbl, P, P, P, P, P, P, P, P, P]
+        L.suco_collide_select.argtypes = [P, i64, P, P, i32, dbl, P, P, P]
+        L.suco_rerank.argtypes = [P, P, i64, P, i64, i32, P, P, P]
+        L.suco_profile.argtypes = [P, C.c_int]
+        L.suco_profile_read.argtypes = [P, P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SUCO_OK:
+        raise SucoError(rc, lib().suco_last_error().decode(errors="replace"))
+
+
+def count_A(alpha: float, n: int) -> int:
+    return int(lib().suco_count_A(float(alpha), int(n)))
+
+
+def count_B(beta: float, n: int, k: int) -> int:
+    return int(lib().suco_count_B(float(beta), int(n), int(k)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _opt(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Index:
+    """A SuCo index resident on one GPU (Create Index, Alg. 2)."""
+
+    def __init__(self, handle: int, n: int, d: int, ns: int, sqrt_k: int):
+        self._h = C.c_void_p(handle)
+        self.n, self.d, self.ns, self.sqrt_k = n, d, ns, sqrt_k
+        self.K = sqrt_k * sqrt_k
+
+    @staticmethod
+    def _params(iters, seed, tile_max, query_chunk):
+        return BuildParams(iters, seed, tile_max, query_chunk)
+
+    @classmethod
+    def build(cls, X, n_s: int, sqrt_k: int, iters: int = 25, seed: int = 1, tile_max: int = 0,
+              query_chunk: int = 0, stream=None) -> "Index":
+        torch = _torch()
+        n, d = X.shape
+        px = _dev(X, torch.float32, name="X")
+        prm = cls._params(iters, seed, tile_max, query_chunk)
+        h = C.c_void_p()
+        _check(lib().suco_build(px, n, d, n_s, sqrt_k, C.byref(prm), _stream(stream), C.byref(h)))
+        return cls(h.value, n, d, n_s, sqrt_k)
+
+    @classmethod
+    def from_index(cls, X, n_s: int, sqrt_k: int, centroids: np.ndarray, assign: np.ndarray,
+                   tile_max: int = 0, query_chunk: int = 0, stream=None) -> "Index":
+        torch = _torch()
+        n, d = X.shape
+        px = _dev(X, torch.float32, name="X")
+        cent = np.ascontiguousarray(centroids, np.float32).reshape(-1)
+        asg = np.ascontiguousarray(assign, np.int32).reshape(-1)
+        if cent.size != sqrt_k * d or asg.size != 2 * n_s * n:
+            raise ValueError("centroids must hold sqrt_k*d values and assign 2*n_s*n values")
+        prm = cls._params(0, 0, tile_max, query_chunk)
+        h = C.c_void_p()
+        _check(lib().suco_build_from_index(px, n, d, n_s, sqrt_k, cent.ctypes.data_as(P),
+                                           asg.ctypes.data_as(P), C.byref(prm), _stream(stream), C.byref(h)))
+        return cls(h.value, n, d, n_s, sqrt_k)
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().suco_index_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if _lib is not None and getattr(self, "_h", None) is not None and self._h.value:
+                _lib.suco_index_free(self._h)
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        """Bracket every launch with HIP events on the query stream (see suco_profile)."""
+        _check(lib().suco_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{step: (total ms, launches)} since the last read (waits for the recorded work)."""
+        ms = np.zeros(len(STAGES), np.float64)
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().suco_profile_read(self._h, ms.ctypes.data_as(P), cnt.ctypes.data_as(P)))
+        return {s: (float(ms[j]), int(cnt[j])) for j, s in enumerate(STAGES)}
+
+    def export(self):
+        cent = np.zeros(self.sqrt_k * self.d, np.float32)
+        asg = np.zeros((2 * self.ns, self.n), np.int32)
+        _check(lib().suco_index_export(self._h, cent.ctypes.data_as(P), asg.ctypes.data_as(P)))
+        return cent, asg
+
+    def _out(self, nq, k):
+        torch = _torch()
+        return (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
+                torch.empty((nq, k), dtype=torch.float32, device="cuda"))
+
+    def query(self, Q, k: int, alpha: float, beta: float, out=None, stream=None):
+        """k-ANN Query (Alg. 4): returns (ids int32 [nq,k], dists float32 [nq,k])."""
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        ids, dists = out if out is not None else self._out(nq, k)
+        _check(lib().suco_query(self._h, pq, nq, k, float(alpha), float(beta), _dev(ids, torch.int32),
+                                _dev(dists, torch.float32), _stream(stream)))
+        return ids, dists
+
+    def query_alpha(self, Q, k: int, alpha_q, beta: float, out=None, stream=None):
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        pa = _dev(alpha_q, torch.float32, (nq,), "alpha_q")
+        ids, dists = out if out is not None else self._out(nq, k)
+        _check(lib().suco_query_alpha(self._h, pq, nq, k, pa, float(beta), _dev(ids, torch.int32),
+                                      _dev(dists, torch.float32), _stream(stream)))
+        return ids, dists
+
+    def query_debug(self, Q, k: int, alpha: float, beta: float, alpha_q=None, stream=None,
+                    scores=True, cand=True, cells=True, feat=True):
+        """Alg. 4 with every intermediate exported (see suco_query_debug)."""
+        torch = _torch()
+        nq = Q.shape[0]
+        B = count_B(beta, self.n, k)
+        dev = "cuda"
+        ids, dists = self._out(nq, k)
+        o = dict(ids=ids, dists=dists)
+        o["scores"] = torch.empty((nq, self.n), dtype=torch.uint8, device=dev) if scores else None
+        o["cand"] = torch.empty((nq, B), dtype=torch.int32, device=dev) if cand else None
+        o["ncells"] = torch.empty((nq, self.ns), dtype=torch.int32, device=dev)
+        o["aprime"] = torch.empty((nq, self.ns), dtype=torch.int32, device=dev)
+        o["cells"] = torch.empty((nq, self.ns, self.K), dtype=torch.uint16, device=dev) if cells else None
+        o["feat"] = torch.empty((nq, 2 * self.ns), dtype=torch.float32, device=dev) if feat else None
+        pa = _dev(alpha_q, torch.float32, (nq,), "alpha_q") if alpha_q is not None else None
+        _check(lib().suco_query_debug(self._h, _dev(Q, torch.float32, (nq, self.d), "Q"), nq, k, pa,
+                                      float(alpha), float(beta), _opt(ids), _opt(dists), _opt(o["scores"]),
+                                      _opt(o["cand"]), _opt(o["ncells"]), _opt(o["aprime"]), _opt(o["cells"]),
+                                      _opt(o["feat"]), _stream(stream)))
+        return o
+
+    def collide_select(self, cells, ncells, k: int, beta: float, want_scores=True, stream=None):
+        """Steps 3-4 from given activated cells: returns (cand int32 [nq,B], scores uint8 [nq,n])."""
+        torch = _torch()
+        nq = cells.shape[0]
+        B = count_B(beta, self.n, k)
+        pc = _dev(cells, torch.uint16, (nq, self.ns, self.K), "cells")
+        pn = _dev(ncells, torch.int32, (nq, self.ns), "ncells")
+        cand = torch.empty((nq, B), dtype=torch.int32, device="cuda")
+        sc = torch.empty((nq, self.n), dtype=torch.uint8, device="cuda") if want_scores else None
+        _check(lib().suco_collide_select(self._h, nq, pc, pn, k, float(beta), _opt(sc), _dev(cand, torch.int32),
+                                         _stream(stream)))
+        return cand, sc
+
+    def rerank(self, Q, cand, k: int, stream=None):
+        """Step 5 on given candidates: returns (ids, dists)."""
+        torch = _torch()
+        nq, B = cand.shape
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        ids, dists = self._out(nq, k)
+        _check(lib().suco_rerank(self._h, pq, nq, _dev(cand, torch.int32), B, k, _dev(ids, torch.int32),
+                                 _dev(dists, torch.float32), _stream(stream)))
+        return ids, dists

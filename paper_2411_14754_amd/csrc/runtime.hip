@@ -1,0 +1,675 @@
+// Host side of the SuCo library: argument validation, the index object, the
+// query workspace and the launch sequences behind the C ABI in suco.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "suco.h"
+#include "suco_impl.h"
+
+using namespace suco;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(SUCO_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint64_t kMagic = 0x5375436f49647831ULL;
+
+int64_t count_A_host(double alpha, int64_t n) {
+#pragma clang fp contract(off)
+    double prod = alpha * (double)n;
+    int64_t a = (int64_t)std::ceil(prod - 1e-9);
+    return std::min<int64_t>(std::max<int64_t>(a, 1), n);
+}
+
+int64_t count_B_host(double beta, int64_t n, int k) {
+#pragma clang fp contract(off)
+    double prod = beta * (double)n;
+    int64_t b = (int64_t)std::floor(prod + 1e-9);
+    return std::min<int64_t>(std::max<int64_t>(b, k), n);
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014), counter form: output m of a
+// stream with the given base.
+uint64_t splitmix64_at(uint64_t base, uint64_t m) {
+    uint64_t z = base + (m + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+int dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, sizeof(T) * count) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(SUCO_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
+    }
+    return SUCO_OK;
+}
+
+}  // namespace
+
+struct suco_index {
+    uint64_t magic = kMagic;
+    int device = 0;
+    int64_t n = 0;
+    int d = 0, ns = 0, sk = 0, K = 0, P = 0, TILE = 0, chunk = 0;
+    std::vector<HalfDims> halves_h;
+    std::vector<float> cent_h;
+    float *X = nullptr;
+    float *cent = nullptr;
+    HalfDims *halves = nullptr;
+    uint32_t *toffs = nullptr;
+    uint16_t *ids16 = nullptr;
+    uint32_t *csize = nullptr;
+    uint8_t *assign = nullptr;
+    // query workspace (one arena, grown on demand)
+    std::mutex mu;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    // optional per-step timing: event pairs around every launch
+    struct EvPair { hipEvent_t a, b; int stage; };
+    bool prof_on = false;
+    std::vector<EvPair> prof_pool;
+    size_t prof_used = 0;
+
+    IndexView view() const {
+        IndexView v;
+        v.X = X; v.cent = cent; v.halves = halves; v.toffs = toffs; v.ids16 = ids16; v.csize = csize;
+        v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE;
+        return v;
+    }
+
+    void release() {
+        if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
+        for (auto &e : prof_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        prof_pool.clear();
+        prof_used = 0;
+        for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
+                        (void *)assign, (void *)arena})
+            if (p) (void)hipFree(p);
+        X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
+        assign = nullptr; arena = nullptr; arena_bytes = 0;
+        magic = 0;
+    }
+};
+
+namespace {
+
+bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
+
+enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kStages };
+
+// Launch through `fn`, bracketed by a pair of timing events when profiling is on.
+template <class F>
+hipError_t timed(suco_index *ix, int stage, hipStream_t st, F &&fn) {
+    if (!ix->prof_on) return fn();
+    if (ix->prof_used == ix->prof_pool.size()) {
+        suco_index::EvPair e{};
+        if (hipEventCreate(&e.a) != hipSuccess) return hipErrorOutOfMemory;
+        if (hipEventCreate(&e.b) != hipSuccess) { (void)hipEventDestroy(e.a); return hipErrorOutOfMemory; }
+        ix->prof_pool.push_back(e);
+    }
+    auto &ev = ix->prof_pool[ix->prof_used++];
+    ev.stage = stage;
+    hipError_t e = hipEventRecord(ev.a, st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(ev.b, st);
+}
+
+int check_shape(int64_t n, int32_t d, int32_t ns, int32_t sk) {
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(SUCO_E_INVAL, "n must be in [1, 2^31)");
+    if (d < 2) return fail(SUCO_E_INVAL, "d must be >= 2");
+    if (ns < 1 || ns > kMaxNs || ns > d / 2) return fail(SUCO_E_INVAL, "n_s must be in [1, min(127, d/2)]");
+    if (sk < 1 || sk > kMaxSqrtK) return fail(SUCO_E_INVAL, "sqrt_k must be in [1, 128]");
+    if (sk > n) return fail(SUCO_E_INVAL, "sqrt_k must not exceed n");
+    return SUCO_OK;
+}
+
+// Contiguous division into ns subspaces (the last takes the remainder), each
+// split into halves of floor(s/2) and the rest.
+std::vector<HalfDims> make_layout(int d, int ns) {
+    std::vector<HalfDims> h(2 * ns);
+    const int s = d / ns;
+    for (int i = 0; i < ns; ++i) {
+        const int start = i * s, si = (i == ns - 1) ? d - (ns - 1) * s : s, h1 = si / 2;
+        h[2 * i] = {start, h1};
+        h[2 * i + 1] = {start + h1, si - h1};
+    }
+    return h;
+}
+
+// Allocate the index object and copy the dataset; tiles are chosen so that a
+// multiple of 8 tiles (one group per XCD) covers the ids when n is large.
+int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_build_params *p,
+                 hipStream_t st, suco_index **out) {
+    int rc = check_shape(n, d, ns, sk);
+    if (rc) return rc;
+    int tile_max = p && p->tile_max ? p->tile_max : 65536;
+    if (tile_max < 256 || tile_max > 65536 || tile_max % 256)
+        return fail(SUCO_E_INVAL, "tile_max must be a multiple of 256 in [256, 65536]");
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return fail(SUCO_E_HIP, "no usable HIP device");
+    // the collision step keeps a tile of byte scores in LDS next to ~1 KB of counters
+    tile_max = std::min(tile_max, (max_lds - 1024) / 256 * 256);
+    if (tile_max < 256 || (int64_t)sk * sk * 4 > max_lds || (int64_t)sk * (sk + 1) * 4 + 4096 > max_lds)
+        return fail(SUCO_E_UNSUPPORTED, "the device has too little LDS per work-group for this shape");
+    suco_index *ix = new (std::nothrow) suco_index();
+    if (!ix) return fail(SUCO_E_NOMEM, "host allocation failed");
+    ix->device = dev;
+    ix->n = n; ix->d = d; ix->ns = ns; ix->sk = sk; ix->K = sk * sk;
+    const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
+    const int64_t per = (n + P0 - 1) / P0;
+    ix->TILE = (int)((per + 255) / 256 * 256);
+    ix->P = (int)((n + ix->TILE - 1) / ix->TILE);
+    const int64_t span = (int64_t)ix->P * ix->TILE;
+    if (p && p->query_chunk > 0) ix->chunk = p->query_chunk;
+    else ix->chunk = (int)std::clamp<int64_t>((int64_t(128) << 20) / span, 16, 1024);
+    ix->halves_h = make_layout(d, ns);
+    if ((rc = dev_alloc(&ix->X, (size_t)n * d)) || (rc = dev_alloc(&ix->cent, (size_t)sk * d)) ||
+        (rc = dev_alloc(&ix->halves, (size_t)2 * ns)) ||
+        (rc = dev_alloc(&ix->toffs, (size_t)ns * ix->P * (ix->K + 1))) ||
+        (rc = dev_alloc(&ix->ids16, (size_t)ns * span)) || (rc = dev_alloc(&ix->csize, (size_t)ns * ix->K)) ||
+        (rc = dev_alloc(&ix->assign, (size_t)2 * ns * n))) {
+        ix->release();
+        delete ix;
+        return rc;
+    }
+    if (hipEventCreateWithFlags(&ix->done, hipEventDisableTiming) != hipSuccess) {
+        ix->release(); delete ix;
+        return fail(SUCO_E_HIP, "hipEventCreate failed");
+    }
+    hipError_t e = hipMemcpyAsync(ix->X, D, sizeof(float) * n * d, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ix->halves, ix->halves_h.data(), sizeof(HalfDims) * 2 * ns, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ix->csize, 0, sizeof(uint32_t) * ns * ix->K, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ix->ids16, 0, sizeof(uint16_t) * ns * span, st);
+    if (e != hipSuccess) {
+        ix->release(); delete ix;
+        return fail(SUCO_E_HIP, std::string("index upload: ") + hipGetErrorString(e));
+    }
+    *out = ix;
+    return SUCO_OK;
+}
+
+int finish_index(suco_index *ix, hipStream_t st) {
+    HIPCHECK(launch_imi_build(ix->assign, ix->n, ix->ns, ix->sk, ix->P, ix->TILE, ix->toffs, ix->ids16,
+                              ix->csize, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return SUCO_OK;
+}
+
+// Lloyd's k-means on every half, FP64, on the GPU.
+int run_kmeans(suco_index *ix, int iters, uint64_t seed, hipStream_t st) {
+    const int64_t n = ix->n;
+    const int d = ix->d, ns = ix->ns, sk = ix->sk;
+    int wmax = 0;
+    for (const auto &h : ix->halves_h) wmax = std::max(wmax, h.w);
+    // initial centres: SplitMix64 draws, first sk rows with distinct half-vectors
+    const int64_t limit = 16LL * sk + 1024, M = limit + sk;
+    std::vector<double> c64((size_t)sk * d);
+    int64_t *cand_d = nullptr;
+    float *rows_d = nullptr;
+    int rc;
+    if ((rc = dev_alloc(&cand_d, (size_t)M)) || (rc = dev_alloc(&rows_d, (size_t)M * wmax))) {
+        if (cand_d) (void)hipFree(cand_d);
+        return rc;
+    }
+    std::vector<int64_t> cand(M);
+    std::vector<float> rows((size_t)M * wmax);
+    for (int g = 0; g < 2 * ns && rc == SUCO_OK; ++g) {
+        const HalfDims hd = ix->halves_h[g];
+        const uint64_t base = seed ^ (0x632BE59BD9B4E019ULL * (uint64_t)(g + 1));
+        for (int64_t m = 0; m < M; ++m) cand[m] = (int64_t)(splitmix64_at(base, (uint64_t)m) % (uint64_t)n);
+        hipError_t e = hipMemcpyAsync(cand_d, cand.data(), sizeof(int64_t) * M, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = launch_gather_rows(ix->X, d, cand_d, (int)M, hd.dim0, hd.w, rows_d, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rows.data(), rows_d, sizeof(float) * M * hd.w, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = fail(SUCO_E_HIP, std::string("k-means init: ") + hipGetErrorString(e)); break; }
+        std::vector<int64_t> chosen;
+        for (int64_t m = 0; (int)chosen.size() < sk; ++m) {
+            bool ok = true;
+            if (m < limit) {
+                // distinct by value (a repeated id is a repeated row)
+                for (size_t c = 0; c < chosen.size() && ok; ++c) {
+                    bool same = true;
+                    for (int j = 0; j < hd.w; ++j)
+                        if (!(rows[(size_t)chosen[c] * hd.w + j] == rows[(size_t)m * hd.w + j])) { same = false; break; }
+                    if (same) ok = false;
+                }
+            }
+            if (ok) chosen.push_back(m);
+        }
+        for (int c = 0; c < sk; ++c)
+            for (int j = 0; j < hd.w; ++j)
+                c64[(size_t)sk * hd.dim0 + (size_t)c * hd.w + j] = (double)rows[(size_t)chosen[c] * hd.w + j];
+    }
+    (void)hipFree(cand_d);
+    (void)hipFree(rows_d);
+    if (rc) return rc;
+
+    KmeansPass kp{};
+    kp.X = ix->X; kp.n = n; kp.d = d; kp.ns = ns; kp.sk = sk; kp.nb = (int)((n + 255) / 256); kp.wmax = wmax;
+    kp.halves = ix->halves; kp.assign = ix->assign;
+    double *cent64 = nullptr;
+    uint32_t *bh = nullptr, *cbase = nullptr, *order = nullptr;
+    if ((rc = dev_alloc(&cent64, (size_t)sk * d)) || (rc = dev_alloc(&bh, (size_t)2 * ns * kp.nb * sk)) ||
+        (rc = dev_alloc(&cbase, (size_t)2 * ns * (sk + 1))) || (rc = dev_alloc(&order, (size_t)2 * ns * n))) {
+        for (void *q : {(void *)cent64, (void *)bh, (void *)cbase, (void *)order}) if (q) (void)hipFree(q);
+        return rc;
+    }
+    kp.cent64 = cent64; kp.bh = bh; kp.cbase = cbase; kp.order = order;
+    hipError_t e = hipMemcpyAsync(cent64, c64.data(), sizeof(double) * sk * d, hipMemcpyHostToDevice, st);
+    for (int it = 0; it <= iters && e == hipSuccess; ++it) {
+        e = launch_km_assign(kp, it < iters, st);
+        if (it == iters || e != hipSuccess) break;
+        if ((e = launch_km_scan(kp, st)) != hipSuccess) break;
+        if ((e = launch_km_scatter(kp, st)) != hipSuccess) break;
+        e = launch_km_update(kp, st);
+    }
+    if (e == hipSuccess) e = launch_cent_to_f32(cent64, ix->cent, (int64_t)sk * d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c64.data(), cent64, sizeof(double) * sk * d, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (void *q : {(void *)cent64, (void *)bh, (void *)cbase, (void *)order}) (void)hipFree(q);
+    if (e != hipSuccess) return fail(SUCO_E_HIP, std::string("k-means: ") + hipGetErrorString(e));
+    ix->cent_h.resize((size_t)sk * d);
+    for (size_t t = 0; t < c64.size(); ++t) ix->cent_h[t] = (float)c64[t];
+    return SUCO_OK;
+}
+
+// ------------------------------------------------------------ workspace --
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * std::max<size_t>(count, 1);
+        return p;
+    }
+};
+
+struct Work {
+    uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint8_t *scores;
+    uint32_t *cand; uint64_t *part_keys;
+};
+
+Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int parts, size_t *bytes) {
+    Carve c{base};
+    Work w;
+    w.cells = c.take<uint16_t>(C * ix->ns * ix->K);
+    w.ncells = c.take<int32_t>(C * ix->ns);
+    w.aprime = c.take<int32_t>(C * ix->ns);
+    w.feat = c.take<float>(C * 2 * ix->ns);
+    w.hist = c.take<uint32_t>(C * ix->P * (ix->ns + 2));
+    w.scores = c.take<uint8_t>(C * (size_t)ix->P * ix->TILE);
+    w.cand = c.take<uint32_t>(C * (size_t)B);
+    w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
+    if (bytes) *bytes = c.off;
+    return w;
+}
+
+int ensure_arena(suco_index *ix, size_t bytes) {
+    if (bytes <= ix->arena_bytes) return SUCO_OK;
+    if (ix->pending) HIPCHECK(hipEventSynchronize(ix->done));
+    if (ix->arena) (void)hipFree(ix->arena);
+    ix->arena = nullptr;
+    ix->arena_bytes = 0;
+    int rc = dev_alloc(&ix->arena, bytes);
+    if (rc) return rc;
+    ix->arena_bytes = bytes;
+    return SUCO_OK;
+}
+
+struct RerankCfg { int G, U, parts; int64_t rpp; };
+
+int rerank_cfg(int d, int64_t B, RerankCfg *c) {
+    if (d % 4) return fail(SUCO_E_UNSUPPORTED, "the re-rank needs d to be a multiple of 4");
+    const int d4 = d / 4;
+    int G = 1;
+    while (G * 2 <= std::max(1, d4 / 2) && G < kWave) G *= 2;
+    const int U = (d4 + G - 1) / G;
+    if (U > kMaxU) return fail(SUCO_E_UNSUPPORTED, "the re-rank supports d <= 2048");
+    c->G = G; c->U = U;
+    c->rpp = 512;
+    c->parts = (int)((B + c->rpp - 1) / c->rpp);
+    return SUCO_OK;
+}
+
+struct DebugOut {
+    uint8_t *scores = nullptr; int32_t *cand = nullptr; int32_t *ncells = nullptr; int32_t *aprime = nullptr;
+    uint16_t *cells = nullptr; float *feat = nullptr;
+};
+
+int check_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double beta, int32_t *ids,
+                float *dists) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (nq < 0) return fail(SUCO_E_INVAL, "nq must be >= 0");
+    if (k < 1 || k > kMaxK || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, min(64, n)]");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
+    if (nq > 0 && (!Q || !ids || !dists)) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
+    return SUCO_OK;
+}
+
+int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, const float *alpha_q, double alpha,
+              double beta, int32_t *ids, float *dists, const DebugOut *dbg, hipStream_t st) {
+    int rc = check_query(cix, Q, nq, k, beta, ids, dists);
+    if (rc) return rc;
+    if (!alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (nq == 0) return SUCO_OK;
+    suco_index *ix = const_cast<suco_index *>(cix);
+    const int64_t B = count_B_host(beta, ix->n, k);
+    RerankCfg rc_cfg;
+    if ((rc = rerank_cfg(ix->d, B, &rc_cfg))) return rc;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    DeviceGuard dg(ix->device);
+    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    size_t bytes = 0;
+    carve(ix, nullptr, C, B, k, rc_cfg.parts, &bytes);
+    if ((rc = ensure_arena(ix, bytes))) return rc;
+    if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
+    Work w = carve(ix, ix->arena, C, B, k, rc_cfg.parts, nullptr);
+    const IndexView v = ix->view();
+    for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
+        const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
+        QueryPass qp{};
+        qp.ix = v;
+        qp.Q = Q + c0 * ix->d;
+        qp.nq = cn;
+        qp.alpha_q = alpha_q ? alpha_q + c0 : nullptr;
+        qp.alpha = alpha;
+        qp.B = B;
+        qp.k = k;
+        qp.cells = w.cells; qp.ncells = w.ncells; qp.aprime = w.aprime;
+        qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
+        qp.hist = w.hist; qp.scores = w.scores; qp.cand = w.cand;
+        HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
+        HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
+        HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
+        RerankPass rp{};
+        rp.X = ix->X; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
+        rp.parts = rc_cfg.parts; rp.rows_per_part = rc_cfg.rpp; rp.G = rc_cfg.G; rp.U = rc_cfg.U;
+        rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
+        HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));
+        HIPCHECK(timed(ix, kMerge, st, [&] { return launch_merge(rp, st); }));
+        if (dbg) {
+            const int ns = ix->ns;
+            if (dbg->ncells)
+                HIPCHECK(hipMemcpyAsync(dbg->ncells + c0 * ns, w.ncells, sizeof(int32_t) * cn * ns,
+                                        hipMemcpyDeviceToDevice, st));
+            if (dbg->aprime)
+                HIPCHECK(hipMemcpyAsync(dbg->aprime + c0 * ns, w.aprime, sizeof(int32_t) * cn * ns,
+                                        hipMemcpyDeviceToDevice, st));
+            if (dbg->cells)
+                HIPCHECK(hipMemcpyAsync(dbg->cells + c0 * ns * ix->K, w.cells, sizeof(uint16_t) * cn * ns * ix->K,
+                                        hipMemcpyDeviceToDevice, st));
+            if (dbg->cand)
+                HIPCHECK(hipMemcpyAsync(dbg->cand + c0 * B, w.cand, sizeof(uint32_t) * cn * B,
+                                        hipMemcpyDeviceToDevice, st));
+            if (dbg->scores)
+                HIPCHECK(hipMemcpy2DAsync(dbg->scores + c0 * ix->n, (size_t)ix->n, w.scores,
+                                          (size_t)ix->P * ix->TILE, (size_t)ix->n, (size_t)cn,
+                                          hipMemcpyDeviceToDevice, st));
+        }
+    }
+    HIPCHECK(hipEventRecord(ix->done, st));
+    ix->pending = true;
+    return SUCO_OK;
+}
+
+}  // namespace
+
+// ================================================================== ABI ==
+extern "C" {
+
+int suco_version(void) { return 1; }
+
+const char *suco_last_error(void) { return g_err.c_str(); }
+
+int64_t suco_count_A(double alpha, int64_t n) { return n < 1 ? 0 : count_A_host(alpha, n); }
+
+int64_t suco_count_B(double beta, int64_t n, int32_t k) { return n < 1 ? 0 : count_B_host(beta, n, k); }
+
+int suco_build(const float *D, int64_t n, int32_t d, int32_t n_s, int32_t sqrt_k, const suco_build_params *p,
+               void *stream, suco_index **out) {
+    if (!D || !out) return fail(SUCO_E_INVAL, "D and out must not be NULL");
+    const int iters = p && p->iters > 0 ? p->iters : 25;
+    const uint64_t seed = p && p->seed ? p->seed : 1;
+    hipStream_t st = (hipStream_t)stream;
+    suco_index *ix = nullptr;
+    int rc = index_common(D, n, d, n_s, sqrt_k, p, st, &ix);
+    if (rc) return rc;
+    if ((rc = run_kmeans(ix, iters, seed, st)) || (rc = finish_index(ix, st))) {
+        (void)hipStreamSynchronize(st);
+        ix->release();
+        delete ix;
+        return rc;
+    }
+    *out = ix;
+    return SUCO_OK;
+}
+
+int suco_build_from_index(const float *D, int64_t n, int32_t d, int32_t n_s, int32_t sqrt_k,
+                          const float *centroids, const int32_t *assign, const suco_build_params *p,
+                          void *stream, suco_index **out) {
+    if (!D || !out || !centroids || !assign) return fail(SUCO_E_INVAL, "NULL argument");
+    int rc = check_shape(n, d, n_s, sqrt_k);
+    if (rc) return rc;
+    std::vector<uint8_t> a8((size_t)2 * n_s * n);
+    for (size_t t = 0; t < a8.size(); ++t) {
+        if (assign[t] < 0 || assign[t] >= sqrt_k) return fail(SUCO_E_INVAL, "assignment out of [0, sqrt_k)");
+        a8[t] = (uint8_t)assign[t];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    suco_index *ix = nullptr;
+    if ((rc = index_common(D, n, d, n_s, sqrt_k, p, st, &ix))) return rc;
+    ix->cent_h.assign(centroids, centroids + (size_t)sqrt_k * d);
+    hipError_t e = hipMemcpyAsync(ix->cent, centroids, sizeof(float) * sqrt_k * d, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ix->assign, a8.data(), a8.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = fail(SUCO_E_HIP, std::string("index upload: ") + hipGetErrorString(e));
+    if (!rc) rc = finish_index(ix, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        ix->release();
+        delete ix;
+        return rc;
+    }
+    *out = ix;
+    return SUCO_OK;
+}
+
+int suco_index_export(const suco_index *ix, float *centroids, int32_t *assign) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (centroids) std::memcpy(centroids, ix->cent_h.data(), sizeof(float) * ix->cent_h.size());
+    if (assign) {
+        DeviceGuard dg(ix->device);
+        std::vector<uint8_t> a8((size_t)2 * ix->ns * ix->n);
+        HIPCHECK(hipMemcpy(a8.data(), ix->assign, a8.size(), hipMemcpyDeviceToHost));
+        for (size_t t = 0; t < a8.size(); ++t) assign[t] = a8[t];
+    }
+    return SUCO_OK;
+}
+
+int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, int32_t *sqrt_k) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (n) *n = ix->n;
+    if (d) *d = ix->d;
+    if (n_s) *n_s = ix->ns;
+    if (sqrt_k) *sqrt_k = ix->sk;
+    return SUCO_OK;
+}
+
+int suco_index_free(suco_index *ix) {
+    if (!ix) return SUCO_OK;
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    {
+        DeviceGuard dg(ix->device);
+        std::lock_guard<std::mutex> lock(ix->mu);
+        ix->release();
+    }
+    delete ix;
+    return SUCO_OK;
+}
+
+int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+               int32_t *ids, float *dists, void *stream) {
+    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, (hipStream_t)stream);
+}
+
+int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, int32_t k, const float *alpha_q,
+                     double beta, int32_t *ids, float *dists, void *stream) {
+    if (nq > 0 && !alpha_q) return fail(SUCO_E_INVAL, "alpha_q must not be NULL");
+    return run_query(ix, Q, nq, k, alpha_q, 0.0, beta, ids, dists, nullptr, (hipStream_t)stream);
+}
+
+int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k, const float *alpha_q,
+                     double alpha, double beta, int32_t *ids, float *dists, uint8_t *scores, int32_t *cand,
+                     int32_t *ncells, int32_t *aprime, uint16_t *cells, float *feat, void *stream) {
+    DebugOut dbg;
+    dbg.scores = scores; dbg.cand = cand; dbg.ncells = ncells; dbg.aprime = aprime; dbg.cells = cells;
+    dbg.feat = feat;
+    return run_query(ix, Q, nq, k, alpha_q, alpha, beta, ids, dists, &dbg, (hipStream_t)stream);
+}
+
+int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells, const int32_t *ncells,
+                        int32_t k, double beta, uint8_t *scores, int32_t *cand, void *stream) {
+    if (!index_ok(cix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (nq < 0) return fail(SUCO_E_INVAL, "nq must be >= 0");
+    if (k < 1 || k > cix->n) return fail(SUCO_E_INVAL, "k must be in [1, n]");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
+    if (nq > 0 && (!cells || !ncells || !cand)) return fail(SUCO_E_INVAL, "cells, ncells, cand must not be NULL");
+    if (nq == 0) return SUCO_OK;
+    suco_index *ix = const_cast<suco_index *>(cix);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t B = count_B_host(beta, ix->n, k);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    DeviceGuard dg(ix->device);
+    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    size_t bytes = 0;
+    carve(ix, nullptr, C, B, k, 1, &bytes);
+    int rc = ensure_arena(ix, bytes);
+    if (rc) return rc;
+    if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
+    Work w = carve(ix, ix->arena, C, B, k, 1, nullptr);
+    for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
+        const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
+        QueryPass qp{};
+        qp.ix = ix->view();
+        qp.nq = cn;
+        qp.B = B;
+        qp.k = k;
+        qp.cells = const_cast<uint16_t *>(cells) + c0 * ix->ns * ix->K;
+        qp.ncells = const_cast<int32_t *>(ncells) + c0 * ix->ns;
+        qp.hist = w.hist; qp.scores = w.scores;
+        qp.cand = reinterpret_cast<uint32_t *>(cand) + c0 * B;
+        HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
+        HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
+        if (scores)
+            HIPCHECK(hipMemcpy2DAsync(scores + c0 * ix->n, (size_t)ix->n, w.scores, (size_t)ix->P * ix->TILE,
+                                      (size_t)ix->n, (size_t)cn, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHECK(hipEventRecord(ix->done, st));
+    ix->pending = true;
+    return SUCO_OK;
+}
+
+int suco_rerank(const suco_index *cix, const float *Q, int64_t nq, const int32_t *cand, int64_t B, int32_t k,
+                int32_t *ids, float *dists, void *stream) {
+    int rc = check_query(cix, Q, nq, k, 1.0, ids, dists);
+    if (rc) return rc;
+    if (B < k || B > cix->n) return fail(SUCO_E_INVAL, "B must be in [k, n]");
+    if (nq > 0 && !cand) return fail(SUCO_E_INVAL, "cand must not be NULL");
+    if (nq == 0) return SUCO_OK;
+    suco_index *ix = const_cast<suco_index *>(cix);
+    hipStream_t st = (hipStream_t)stream;
+    RerankCfg c;
+    if ((rc = rerank_cfg(ix->d, B, &c))) return rc;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    DeviceGuard dg(ix->device);
+    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    size_t bytes = 0;
+    carve(ix, nullptr, C, B, k, c.parts, &bytes);
+    if ((rc = ensure_arena(ix, bytes))) return rc;
+    if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
+    Work w = carve(ix, ix->arena, C, B, k, c.parts, nullptr);
+    for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
+        const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
+        RerankPass rp{};
+        rp.X = ix->X; rp.Q = Q + c0 * ix->d; rp.cand = reinterpret_cast<const uint32_t *>(cand) + c0 * B;
+        rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn; rp.parts = c.parts; rp.rows_per_part = c.rpp;
+        rp.G = c.G; rp.U = c.U; rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
+        HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));
+        HIPCHECK(timed(ix, kMerge, st, [&] { return launch_merge(rp, st); }));
+    }
+    HIPCHECK(hipEventRecord(ix->done, st));
+    ix->pending = true;
+    return SUCO_OK;
+}
+
+int suco_profile(suco_index *ix, int enable) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    ix->prof_on = enable != 0;
+    return SUCO_OK;
+}
+
+int suco_profile_read(suco_index *ix, double *ms, int64_t *launches) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (!ms || !launches) return fail(SUCO_E_INVAL, "ms and launches must not be NULL");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    DeviceGuard dg(ix->device);
+    for (int j = 0; j < kStages; ++j) { ms[j] = 0.0; launches[j] = 0; }
+    for (size_t t = 0; t < ix->prof_used; ++t) {
+        auto &e = ix->prof_pool[t];
+        HIPCHECK(hipEventSynchronize(e.b));
+        float m = 0.f;
+        HIPCHECK(hipEventElapsedTime(&m, e.a, e.b));
+        ms[e.stage] += m;
+        launches[e.stage] += 1;
+    }
+    ix->prof_used = 0;
+    return SUCO_OK;
+}
+
+}  // extern "C"

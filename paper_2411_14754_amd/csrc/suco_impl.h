@@ -1,0 +1,97 @@
+// Internal declarations shared by the SuCo runtime and its gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace suco {
+
+constexpr int kWave = 64;
+constexpr int kMaxSqrtK = 128;   // LDS tables of the activation step are sized for this
+constexpr int kMaxNs = 127;      // SC-scores are bytes counted with 7-bit SWAR compares
+constexpr int kMaxK = 64;        // one result per lane of a wave in the top-k lists
+constexpr int kMaxU = 8;         // float4 slices of a row per lane in the re-rank
+
+struct HalfDims {
+    int dim0;  // first dimension of the half
+    int w;     // width of the half
+};
+
+// Read-only index data resident in HBM.
+struct IndexView {
+    const float *X;          // [n][d] points
+    const float *cent;       // [sqrt_k * d] FP32 centres, half g at sqrt_k*dim0[g]
+    const HalfDims *halves;  // [2*ns]
+    const uint32_t *toffs;   // [ns][P][K+1] start of cell c's ids inside tile p
+    const uint16_t *ids16;   // [ns][P*TILE] tile-local ids, tile-major, cell-major, ascending
+    const uint32_t *csize;   // [ns][K] points per cell
+    int64_t n;
+    int d, ns, sk, K, P, TILE;
+};
+
+// One pass of the query path over a chunk of queries.
+struct QueryPass {
+    IndexView ix;
+    const float *Q;           // [nq][d]
+    int nq;
+    const float *alpha_q;     // [nq] or null
+    double alpha;             // used when alpha_q is null
+    int64_t B;
+    int k;
+    // workspace
+    uint16_t *cells;          // [nq][ns][K]
+    int32_t *ncells;          // [nq][ns]
+    int32_t *aprime;          // [nq][ns]
+    float *feat;              // [nq][2ns] or null
+    uint32_t *hist;           // [nq][P][ns+2] tile counts of score >= t
+    uint8_t *scores;          // [nq][P*TILE]
+    uint32_t *cand;           // [nq][B]
+};
+
+struct RerankPass {
+    const float *X;
+    const float *Q;
+    const uint32_t *cand;     // [nq][B]
+    int64_t B;
+    int64_t n;                // points in X
+    int d, k, nq;
+    int parts;                // work-groups per query
+    int64_t rows_per_part;
+    int G;                    // lanes per row (power of two)
+    int U;                    // float4 slices per lane
+    uint64_t *part_keys;      // [nq][parts][k] (squared distance bits << 32 | id)
+    int32_t *ids;             // [nq][k]
+    float *dists;             // [nq][k]
+};
+
+// Launchers (query_kernels.hip)
+hipError_t launch_activate(const QueryPass &p, hipStream_t s);
+hipError_t launch_collide(const QueryPass &p, hipStream_t s);
+hipError_t launch_select(const QueryPass &p, hipStream_t s);
+hipError_t launch_rerank(const RerankPass &r, hipStream_t s);
+hipError_t launch_merge(const RerankPass &r, hipStream_t s);
+
+// Launchers (build_kernels.hip)
+struct KmeansPass {
+    const float *X;
+    int64_t n;
+    int d, ns, sk, nb;        // nb = blocks of 256 points
+    int wmax;                 // widest half
+    const HalfDims *halves;   // [2ns]
+    double *cent64;           // [sk*d] half g at sk*dim0[g]
+    uint8_t *assign;          // [2ns][n]
+    uint32_t *bh;             // [2ns][nb][sk]  block histograms, then block offsets
+    uint32_t *cbase;          // [2ns][sk+1]    cluster starts
+    uint32_t *order;          // [2ns][n]       point ids grouped by cluster, ascending
+};
+hipError_t launch_gather_rows(const float *X, int d, const int64_t *ids, int m, int dim0, int w,
+                              float *out, hipStream_t s);
+hipError_t launch_km_assign(const KmeansPass &k, bool with_hist, hipStream_t s);
+hipError_t launch_km_scan(const KmeansPass &k, hipStream_t s);
+hipError_t launch_km_scatter(const KmeansPass &k, hipStream_t s);
+hipError_t launch_km_update(const KmeansPass &k, hipStream_t s);
+hipError_t launch_cent_to_f32(const double *c64, float *c32, int64_t m, hipStream_t s);
+hipError_t launch_imi_build(const uint8_t *assign, int64_t n, int ns, int sk, int P, int TILE,
+                            uint32_t *toffs, uint16_t *ids16, uint32_t *csize, hipStream_t s);
+
+}  // namespace suco

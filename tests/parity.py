@@ -1,0 +1,103 @@
+"""Comparison rules between the GPU path and the FP64 oracle.
+
+Integer stages (SC-scores, candidate sets, activated cells) must match
+exactly.  The only tolerated difference is at a floating-point tie: the GPU
+ranks cells by FP32 keys and candidates by FP32 distances, the oracle by FP64.
+
+ * Cells: for a (query, subspace) the two activated sets may differ only in
+   "band" cells, whose FP64 key is within 1e-5 (relative) of the oracle's
+   cutoff key.  Where that happens the scores of the affected points may
+   differ; the comparison then re-runs the oracle's selection and re-rank on
+   the GPU's own scores and checks the GPU's candidates and top-k against that.
+ * Top-k: ids must be identical unless distances tie within 1e-5 relative;
+   in that case the GPU's list must be a valid top-k: its FP64 distances must
+   equal the oracle's sorted top-k distances within 1e-5 relative.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+REL = 1e-5
+
+
+def cells_to_gpu_layout(ref_cells, nq, ns, K):
+    """Oracle activated cells [q][i] -> (uint16 [nq][ns][K], int32 [nq][ns])."""
+    cells = np.zeros((nq, ns, K), np.uint16)
+    ncell = np.zeros((nq, ns), np.int32)
+    for q in range(nq):
+        for i in range(ns):
+            c = ref_cells[q][i]
+            cells[q, i, :len(c)] = c
+            ncell[q, i] = len(c)
+    return cells, ncell
+
+
+def oracle_cells(oix, Q, alpha, form=0):
+    """Per (query, subspace): (cells, A', keys of every cell by id, cutoff key)."""
+    out = []
+    sk = oix.sk
+    al = np.broadcast_to(np.asarray(alpha, np.float64), (Q.shape[0],))
+    for q in range(Q.shape[0]):
+        row = []
+        for i in range(oix.ns):
+            cells, ap, (d1, i1, d2, i2) = oix.cells(Q[q], i, float(al[q]), form)
+            key = (d1[:, None] + d2[None, :]).reshape(-1)     # key of cell c1*sk + c2
+            row.append((cells, ap, key, key[cells[-1]]))
+        out.append(row)
+    return out
+
+
+def check_cells(ref, gpu_cells, gpu_ncells, q, i):
+    """Returns True if identical, False if they differ only in band cells; raises otherwise."""
+    cells, ap, key, kstar = ref[q][i]
+    g = set(gpu_cells[q, i, :gpu_ncells[q, i]].tolist())
+    o = set(cells.tolist())
+    if g == o:
+        return True
+    diff = g ^ o
+    band = np.abs(key[list(diff)] - kstar) <= REL * max(kstar, 1e-30)
+    assert band.all(), f"query {q} subspace {i}: cells differ outside the tie band: {sorted(diff)[:10]}"
+    return False
+
+
+def check_topk(X, Q, ids, dists, ref_ids, ref_dists, k):
+    """Top-k identical, or a valid top-k under distance ties within REL."""
+    X64 = X.astype(np.float64)
+    for q in range(Q.shape[0]):
+        if np.array_equal(ids[q], ref_ids[q]):
+            assert np.allclose(dists[q], ref_dists[q], rtol=REL, atol=1e-6), f"query {q}: distances"
+            continue
+        true = np.sqrt(((X64[ids[q]] - Q[q].astype(np.float64)) ** 2).sum(axis=1))
+        assert len(set(ids[q].tolist())) == k, f"query {q}: repeated ids"
+        assert np.allclose(np.sort(true), np.sort(ref_dists[q]), rtol=REL, atol=1e-6), \
+            f"query {q}: ids {ids[q]} vs {ref_ids[q]} not a tie"
+        assert np.allclose(dists[q], true, rtol=REL, atol=1e-6)
+
+
+def check_query(oix, X, Q, k, alpha, beta, gpu):
+    """Full comparison of a GPU query_debug result with the oracle.  Returns stats."""
+    nq = Q.shape[0]
+    ref = oix.query(Q, k, alpha, beta, want_scores=True, want_cand=True)
+    rc = oracle_cells(oix, Q, alpha)
+    B = oracle.count_B(beta, oix.n, k)
+    g_sc = gpu["scores"]
+    n_band = 0
+    for q in range(nq):
+        exact = all(check_cells(rc, gpu["cells"], gpu["ncells"], q, i) for i in range(oix.ns))
+        assert np.array_equal(gpu["aprime"][q], ref["aprime"][q]) or not exact
+        if exact:
+            assert np.array_equal(g_sc[q], ref["scores"][q]), f"query {q}: SC-scores differ"
+            assert np.array_equal(np.sort(gpu["cand"][q]), np.sort(ref["cand"][q])), f"query {q}: candidates"
+            check_topk(X, Q[q:q + 1], gpu["ids"][q:q + 1], gpu["dists"][q:q + 1], ref["ids"][q:q + 1],
+                       ref["dists"][q:q + 1], k)
+        else:
+            n_band += 1
+            # conditional parity: the oracle's selection and re-rank on the GPU's scores
+            c = oracle.select(g_sc[q], B)
+            assert np.array_equal(np.sort(gpu["cand"][q]), np.sort(c)), f"query {q}: conditional candidates"
+            r_ids, r_d = oracle.rerank(X, Q[q], c, k)
+            check_topk(X, Q[q:q + 1], gpu["ids"][q:q + 1], gpu["dists"][q:q + 1], r_ids[None], r_d[None], k)
+    rec_gpu = oracle.recall(gpu["ids"], ref["ids"])
+    return dict(band_queries=n_band, ref=ref, agree=rec_gpu)

@@ -1,0 +1,262 @@
+"""GPU path vs the FP64 oracle, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import cells_to_gpu_layout, check_query, check_topk, oracle_cells
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def suco():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_14754_amd as m
+    m.lib()
+    return m
+
+
+def to_np(o):
+    out = {}
+    for key, v in o.items():
+        if v is None:
+            continue
+        if v.dtype == torch.uint16:
+            out[key] = v.view(torch.int16).cpu().numpy().view(np.uint16)
+        else:
+            out[key] = v.cpu().numpy()
+    return out
+
+
+def debug(ix, Q, k, alpha, beta, alpha_q=None):
+    Qd = torch.from_numpy(Q).cuda()
+    aq = torch.from_numpy(alpha_q).cuda() if alpha_q is not None else None
+    o = ix.query_debug(Qd, k, alpha, beta, alpha_q=aq)
+    torch.cuda.synchronize()
+    return to_np(o)
+
+
+def make(X, ns, sk, iters=10, seed=1, **kw):
+    import paper_2411_14754_amd as m
+    _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=iters, seed=seed)
+    oix = oracle.Index(X, ns, sk, c32, asg)
+    gix = m.Index.from_index(torch.from_numpy(X).cuda(), ns, sk, c32, asg, **kw)
+    return oix, gix
+
+
+# ------------------------------------------------------------- workloads --
+def test_mixture128_full_parity(suco):
+    """Gaussian mixture n=10,000 d=128, N_s=8, sqrtK=16, 100 queries, k=10,
+    alpha=0.05, beta=0.005: every query compared stage by stage."""
+    W = synth.Workload(1)
+    X, Q = W.data(), W.queries()
+    print("case: mixture128 n=10000 d=128 ns=8 sk=16 nq=100", flush=True)
+    oix, gix = make(X, 8, 16, iters=25)
+    g = debug(gix, Q, 10, 0.05, 0.005)
+    st = check_query(oix, X, Q, 10, 0.05, 0.005, g)
+    assert st["band_queries"] <= 5
+    assert st["agree"] >= 0.999
+    gix.free()
+
+
+def test_stage_collide_select_from_oracle_cells(suco):
+    """Steps 3-4 fed with the oracle's activated cells: bit-exact scores and candidates."""
+    W = synth.Workload(1)
+    X, Q = W.data(), W.queries(40)
+    oix, gix = make(X, 8, 16)
+    for alpha, beta, k in ((0.05, 0.005, 10), (0.2, 0.01, 10), (0.01, 0.001, 5), (1.0, 0.003, 10)):
+        rc = oracle_cells(oix, Q, alpha)
+        cells, nc = cells_to_gpu_layout([[r[0] for r in row] for row in rc], Q.shape[0], 8, 256)
+        ref = oix.query(Q, k, alpha, beta, want_scores=True, want_cand=True)
+        cand, sc = gix.collide_select(torch.from_numpy(cells.view(np.int16)).cuda().view(torch.uint16),
+                                      torch.from_numpy(nc).cuda(), k, beta)
+        torch.cuda.synchronize()
+        assert np.array_equal(sc.cpu().numpy(), ref["scores"]), (alpha, beta)
+        cand = cand.cpu().numpy()
+        assert (np.diff(cand, axis=1) > 0).all()                       # ascending ids
+        assert np.array_equal(cand, np.sort(ref["cand"], axis=1)), (alpha, beta)
+    gix.free()
+
+
+def test_stage_rerank_from_oracle_candidates(suco):
+    W = synth.Workload(1)
+    X, Q = W.data(), W.queries(50)
+    oix, gix = make(X, 8, 16)
+    for beta, k in ((0.005, 10), (0.05, 64), (0.0001, 1), (1.0, 10)):
+        ref = oix.query(Q, k, 0.05, beta, want_cand=True)
+        ids, dists = gix.rerank(torch.from_numpy(Q).cuda(), torch.from_numpy(ref["cand"]).cuda(), k)
+        torch.cuda.synchronize()
+        check_topk(X, Q, ids.cpu().numpy(), dists.cpu().numpy(), ref["ids"], ref["dists"], k)
+    gix.free()
+
+
+def test_integer_data_rerank_is_exact(suco):
+    """SIFT-like integer data: FP32 distances are exact integers, so ids and
+    distances equal the oracle's exactly (ties broken by id on both sides)."""
+    W = synth.Workload(2)
+    X, Q = W.data(20_000), W.queries(30)
+    oix, gix = make(X, 8, 16)
+    ref = oix.query(Q, 10, 0.05, 0.01, want_cand=True)
+    ids, dists = gix.rerank(torch.from_numpy(Q).cuda(), torch.from_numpy(ref["cand"]).cuda(), 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids.cpu().numpy(), ref["ids"])
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref["dists"].astype(np.float32).astype(np.float64))
+    gix.free()
+
+
+def test_gpu_build_equals_oracle_build(suco):
+    """Create Index on the GPU (FP64 k-means, IMI) gives the oracle's centres and assignments."""
+    W = synth.Workload(1)
+    X = W.data(6000)
+    c64, c32, asg, _ = oracle.build_index(X, 8, 16, iters=12, seed=7)
+    gix = suco.Index.build(torch.from_numpy(X).cuda(), 8, 16, iters=12, seed=7)
+    gc, ga = gix.export()
+    assert np.array_equal(ga, asg)
+    assert np.array_equal(gc, c32)
+    # and the GPU-built index answers like the oracle's index
+    oix = oracle.Index(X, 8, 16, c32, asg)
+    Q = W.queries(20)
+    g = debug(gix, Q, 10, 0.05, 0.01)
+    check_query(oix, X, Q, 10, 0.05, 0.01, g)
+    gix.free()
+
+
+def test_gpu_build_integer_data(suco):
+    W = synth.Workload(2)
+    X = W.data(30_000)
+    _, c32, asg, _ = oracle.build_index(X, 8, 20, iters=6, seed=3)
+    gix = suco.Index.build(torch.from_numpy(X).cuda(), 8, 20, iters=6, seed=3)
+    gc, ga = gix.export()
+    assert np.array_equal(ga, asg) and np.array_equal(gc, c32)
+    gix.free()
+
+
+# ------------------------------------------------------------ edge cases --
+def test_alpha_beta_one_is_exact_search(suco):
+    X = synth.tiny(2000, 24, 5, "clustered")
+    Q = synth.tiny(12, 24, 6, "clustered")
+    oix, gix = make(X, 4, 6)
+    ids, dists = gix.query(torch.from_numpy(Q).cuda(), 16, 1.0, 1.0)
+    torch.cuda.synchronize()
+    e_ids, e_d = oracle.bruteforce(X, Q, 16)
+    check_topk(X, Q, ids.cpu().numpy(), dists.cpu().numpy(), e_ids, e_d, 16)
+    gix.free()
+
+
+def test_ragged_tiles_and_chunks(suco):
+    """n not a multiple of the tile, several tiles, queries split in ragged chunks;
+    results bitwise equal across chunkings."""
+    X = synth.tiny(3001, 32, 8, "clustered")
+    Q = synth.tiny(30, 32, 9, "clustered")
+    oix, gix = make(X, 4, 6, tile_max=512, query_chunk=7)
+    g = debug(gix, Q, 8, 0.1, 0.02)
+    check_query(oix, X, Q, 8, 0.1, 0.02, g)
+    _, c32, asg, _ = oracle.build_index(X, 4, 6, iters=10)
+    g2ix = suco.Index.from_index(torch.from_numpy(X).cuda(), 4, 6, c32, asg, query_chunk=1000)
+    g2 = debug(g2ix, Q, 8, 0.1, 0.02)
+    for key in ("ids", "dists", "scores", "cand", "ncells", "aprime"):
+        assert np.array_equal(g[key], g2[key]), key
+    gix.free()
+    g2ix.free()
+
+
+def test_single_cell_index(suco):
+    X = synth.tiny(700, 16, 10, "gauss")
+    Q = synth.tiny(5, 16, 11, "gauss")
+    oix, gix = make(X, 4, 1)
+    g = debug(gix, Q, 5, 0.05, 0.02)
+    assert (g["scores"] == 4).all()
+    assert np.array_equal(g["cand"], np.tile(np.arange(14), (5, 1)))
+    check_query(oix, X, Q, 5, 0.05, 0.02, g)
+    gix.free()
+
+
+@pytest.mark.parametrize("k", [1, 64])
+def test_k_extremes(suco, k):
+    W = synth.Workload(1)
+    X, Q = W.data(5000), W.queries(10)
+    oix, gix = make(X, 8, 8)
+    g = debug(gix, Q, k, 0.1, 0.02)
+    check_query(oix, X, Q, k, 0.1, 0.02, g)
+    gix.free()
+
+
+def test_per_query_alpha(suco):
+    W = synth.Workload(1)
+    X, Q = W.data(8000), W.queries(25)
+    oix, gix = make(X, 8, 12)
+    aq = np.random.default_rng(0).uniform(0.005, 0.3, size=25).astype(np.float32)
+    g = debug(gix, Q, 10, 0.0, 0.01, alpha_q=aq)
+    check_query(oix, X, Q, 10, aq.astype(np.float64), 0.01, g)
+    gix.free()
+
+
+def test_empty_batch_and_errors(suco):
+    W = synth.Workload(1)
+    X = W.data(1000)
+    _, gix = make(X, 8, 4)
+    Q0 = torch.zeros((0, 128), device="cuda")
+    ids, d = gix.query(Q0, 5, 0.1, 0.1)
+    assert ids.shape == (0, 5)
+    Q = torch.zeros((2, 128), device="cuda")
+    with pytest.raises(suco.SucoError) as e:
+        gix.query(Q, 65, 0.1, 0.1)
+    assert e.value.code == suco.SUCO_E_INVAL
+    with pytest.raises(suco.SucoError):
+        gix.query(Q, 5, 0.0, 0.1)
+    with pytest.raises(suco.SucoError):
+        gix.query(Q, 5, 0.1, 1.5)
+    gix.free()
+    with pytest.raises(suco.SucoError):
+        suco.Index.build(torch.zeros((10, 8), device="cuda"), 5, 2)      # n_s > d/2
+    with pytest.raises(suco.SucoError):
+        suco.Index.build(torch.zeros((10, 8), device="cuda"), 2, 11)     # sqrt_k > n
+
+
+def test_deterministic_repeat(suco):
+    W = synth.Workload(1)
+    X, Q = W.data(), W.queries(64)
+    _, gix = make(X, 8, 16)
+    a = debug(gix, Q, 10, 0.05, 0.005)
+    b = debug(gix, Q, 10, 0.05, 0.005)
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    gix.free()
+
+
+# ----------------------------------------------------------- full size --
+def test_sift_like_full_size_sampled(suco):
+    """SIFT-like n=1,000,000 d=128, N_s=8, sqrtK=50, 10,000 queries in one call
+    (the benchmark's launch configuration); 24 sampled queries are compared with
+    the oracle stage by stage."""
+    W = synth.Workload(2)
+    print("case: sift_like n=1e6 generating", flush=True)
+    X, Q = W.data(), W.queries()
+    print("case: sift_like oracle build", flush=True)
+    _, c32, asg, _ = oracle.build_index(X, 8, 50, iters=6, seed=1)
+    oix = oracle.Index(X, 8, 50, c32, asg)
+    gix = suco.Index.from_index(torch.from_numpy(X).cuda(), 8, 50, c32, asg)
+    print("case: sift_like GPU query, full batch", flush=True)
+    o = gix.query_debug(torch.from_numpy(Q).cuda(), 10, 0.03, 0.005, scores=False, cells=False)
+    torch.cuda.synchronize()
+    full = to_np(o)
+    del o
+    sample = np.sort(np.random.default_rng(0).choice(Q.shape[0], 24, replace=False))
+    print("case: sift_like GPU query, sample with every stage exported", flush=True)
+    gs = debug(gix, Q[sample], 10, 0.03, 0.005)
+    for key in ("ids", "dists", "cand", "ncells", "aprime", "feat"):
+        assert np.array_equal(full[key][sample], gs[key]), key        # batching does not change results
+    print("case: sift_like oracle on the sample", flush=True)
+    st = check_query(oix, X, Q[sample], 10, 0.03, 0.005, gs)
+    assert st["band_queries"] <= 3
+    assert (gs["scores"].sum(axis=1, dtype=np.int64) == gs["aprime"].sum(axis=1)).all()
+    # properties that hold for every query of the batch
+    B = oracle.count_B(0.005, X.shape[0], 10)
+    assert (full["aprime"] >= oracle.count_A(0.03, X.shape[0])).all()
+    assert (np.diff(full["cand"], axis=1) > 0).all() and full["cand"].shape[1] == B
+    assert ((full["cand"] >= 0) & (full["cand"] < X.shape[0])).all()
+    gix.free()
