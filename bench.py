@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ALPHA_GRID = (0.005, 0.0075, 0.01, 0.015, 0.02, 0.03, 0.04, 0.05)
+ALPHA_GRID = (0.0005, 0.00075, 0.001, 0.0015, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.02, 0.03, 0.05)
 TARGET_RECALL = 0.95
 
 
@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--tile-max", type=int, default=0, help="largest collision tile (0: library default)")
+    ap.add_argument("--query-chunk", type=int, default=0, help="queries per pass (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
@@ -131,7 +133,7 @@ def main():
     Qd = torch.from_numpy(Q).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
-    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1, tile_max=args.tile_max, query_chunk=args.query_chunk)
     build_s = time.time() - t0
     log(f"index built in {build_s:.2f}s")
     gt = exact_topk(Xd, Qd, k)
@@ -167,14 +169,22 @@ def main():
     if qps_interp is None and sweep[0]["recall"] >= TARGET_RECALL:
         qps_interp = sweep[0]["qps"]
 
-    # per-step algorithmic bytes at the chosen alpha (A' from the activation step)
-    o = ix.query_debug(Qd[:256], k, alpha, beta, scores=False, cand=False, cells=False, feat=False)
+    # per-step algorithmic bytes at the chosen alpha, from a 64-query sample:
+    # A' (points in activated cells), U (points of non-zero score) and the
+    # points at or above the score threshold
+    o = ix.query_debug(Qd[:64], k, alpha, beta, scores=True, cand=False, cells=False, feat=False)
     torch.cuda.synchronize()
     aprime = float(o["aprime"].double().sum(dim=1).mean())
+    sc = o["scores"].to(torch.int32)
+    U = float((sc > 0).sum(dim=1).double().mean())
     B = suco.count_B(beta, n, k)
+    srt = torch.sort(sc, dim=1, descending=True).values
+    T = srt[:, B - 1:B]
+    ge_T = float((sc >= T).sum(dim=1).double().mean())
+    del o, sc, srt
     step_bytes = {
-        "collide": 2.0 * aprime + n,                 # u16 tile-local ids of activated cells + score bytes written
-        "select": float(n) + 4.0 * B,                # score bytes read + candidate ids written
+        "collide": 2.0 * aprime + 2.0 * U,           # u16 ids of activated cells read, non-zero-score ids written
+        "select": 2.0 * ge_T + 4.0 * B,              # ids at or above the threshold read, candidates written
         "rerank": 4.0 * B * d + 4.0 * B,             # candidate rows + candidate ids
     }
 

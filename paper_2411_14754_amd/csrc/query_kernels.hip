@@ -228,39 +228,107 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
 // Block per (query, tile).  The tile's TILE scores live in LDS as bytes packed
 // in 32-bit words; each point id occurs once per subspace, so a 32-bit LDS
 // atomic add of 1 << 8*(id & 3) increments exactly one byte without carry
-// (scores never exceed ns <= 127).  One wave walks one activated cell's run
-// of ids inside the tile (ids are stored tile-major, so the run is contiguous).
-// Afterwards the block counts G[t] = #{score >= t} with 7-bit SWAR compares and
-// writes the scores and the counts out.
+// (scores never exceed ns <= 127).  The activated cells of all subspaces are
+// runs of contiguous ids inside the tile (ids are stored tile-major).  The
+// block loads up to NT run descriptors at once into LDS (one thread per run),
+// scans their lengths, and then the threads take the flattened ids of all
+// those runs, kCollideUnroll at a time with their loads issued together, each
+// finding its run by a binary search over the run prefix.
+// The block then counts G[t] = #{score >= t} with 7-bit SWAR compares and
+// lists every point of non-zero score, as its tile-local id, grouped by score
+// level in descending order: level s occupies [G[s+1], G[s]) of the tile's
+// list.  Points of score 0 are not written; the dense scores are written only
+// when asked for.
+// Words of the tile touched by the counting are listed as they are first
+// incremented (a wave appends its first touches with one atomic), so the two
+// passes after the counting visit only those words; when more than
+// kTouchCap words are touched the passes scan the whole tile instead.
+constexpr int kCollideUnroll = 4;
+constexpr int kTouchCap = 4096;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     extern __shared__ uint32_t sc[];   // TILE/4 words
     __shared__ uint32_t G[kMaxNs + 2];
+    __shared__ uint32_t cur[kMaxNs + 2];
+    __shared__ int64_t rstart[NT];          // start of each run in ids16
+    __shared__ uint32_t rpre[NT];           // ids before each run in the batch
+    __shared__ uint32_t red[NT / kWave + 1];
+    __shared__ uint16_t touched[kTouchCap];
+    __shared__ uint32_t n_touched;
     const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
     const int p = blockIdx.x % P, ql = blockIdx.x / P;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
     const int words = TILE >> 2;
     for (int w = tid; w < words; w += NT) sc[w] = 0u;
     for (int t = tid; t < ns + 2; t += NT) G[t] = 0u;
-    __syncthreads();
-    for (int i = 0; i < ns; ++i) {
-        const int nc = a.ncells[ql * ns + i];
-        const uint16_t *cl = a.cells + ((int64_t)ql * ns + i) * K;
-        const uint32_t *to = a.ix.toffs + ((int64_t)i * P + p) * (K + 1);
-        const uint16_t *idl = a.ix.ids16 + (int64_t)i * P * TILE;
-        for (int j = wv; j < nc; j += NT / kWave) {
-            const int c = cl[j];
-            const uint32_t s = to[c], e = to[c + 1];
-            for (uint32_t m = s + lane; m < e; m += kWave) {
-                const uint32_t lid = idl[m];
-                atomicAdd(&sc[lid >> 2], 1u << ((lid & 3u) << 3));
+    if (tid == 0) n_touched = 0u;
+    // thread -> (subspace i, run slot jj): a batch takes runs jb..jb+RJ-1 of every subspace
+    const int RJ = a.runs_per_sub;
+    const int i = tid / RJ, jj = tid - i * RJ;
+    const bool has_i = i < ns;
+    const int my_nc = has_i ? a.ncells[ql * ns + i] : 0;
+    const uint16_t *my_cells = a.cells + ((int64_t)ql * ns + (has_i ? i : 0)) * K;
+    const uint32_t *to = a.ix.toffs + ((int64_t)(has_i ? i : 0) * P + p) * (K + 1);
+    for (int jb = 0; __syncthreads_or(jb < my_nc); jb += RJ) {
+        const int j = jb + jj;
+        uint32_t len = 0;
+        int64_t st = 0;
+        if (has_i && j < my_nc) {
+            const int c = my_cells[j];
+            const uint32_t s = to[c];
+            len = to[c + 1] - s;
+            st = (int64_t)i * P * TILE + s;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NT>(len, red, &tot);
+        rstart[tid] = st;
+        rpre[tid] = ex;
+        __syncthreads();
+        for (uint32_t e0 = 0; e0 < tot; e0 += NT * kCollideUnroll) {
+            uint32_t lid[kCollideUnroll];
+#pragma unroll
+            for (int u = 0; u < kCollideUnroll; ++u) {
+                const uint32_t e = e0 + (uint32_t)(u * NT + tid);
+                lid[u] = 0xffffffffu;
+                if (e < tot) {
+                    int lo = 0, hi = NT - 1;           // run: largest j with rpre[j] <= e
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (rpre[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    lid[u] = a.ix.ids16[rstart[lo] + (e - rpre[lo])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kCollideUnroll; ++u) {
+                const bool v = lid[u] != 0xffffffffu;
+                uint32_t old = 1u;
+                if (v) old = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
+                const bool first = v && old == 0u;
+                const uint64_t m = __ballot(first);
+                if (m != 0ull) {
+                    const int leader = __ffsll((unsigned long long)m) - 1;
+                    uint32_t base = 0u;
+                    if (lane == leader) base = atomicAdd(&n_touched, (uint32_t)__popcll(m));
+                    base = __shfl(base, leader, kWave);
+                    if (first) {
+                        const uint32_t pos = base + (uint32_t)__popcll(m & lanes_below);
+                        if (pos < (uint32_t)kTouchCap) touched[pos] = (uint16_t)(lid[u] >> 2);
+                    }
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
+    const uint32_t nt = n_touched;
+    const bool sparse = nt <= (uint32_t)kTouchCap;
+    const int nw = sparse ? (int)nt : words;
     for (int t0 = 1; t0 <= ns; t0 += 8) {
         uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int w = tid; w < words; w += NT) {
+        for (int j = tid; j < nw; j += NT) {
+            const int w = sparse ? (int)touched[j] : j;
             const uint32_t x = sc[w];
             if (x == 0u) continue;
 #pragma unroll
@@ -275,30 +343,49 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
             }
         }
     }
+    __syncthreads();
+    for (int t = tid; t <= ns; t += NT) cur[t] = G[t + 1];
+    __syncthreads();
+    uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
+    for (int j = tid; j < nw; j += NT) {
+        const int w = sparse ? (int)touched[j] : j;
+        const uint32_t x = sc[w];
+        if (x == 0u) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t s = (x >> (8 * u)) & 0xffu;
+            if (s != 0u) seg[atomicAdd(&cur[s], 1u)] = (uint16_t)(4 * w + u);
+        }
+    }
+    if (a.scores != nullptr) {
+        uint4 *dst = reinterpret_cast<uint4 *>(a.scores + ((int64_t)ql * P + p) * TILE);
+        const uint4 *src = reinterpret_cast<const uint4 *>(sc);
+        for (int w = tid; w < (words >> 2); w += NT) dst[w] = src[w];
+    }
     const int64_t t0 = (int64_t)p * TILE;
     const int64_t valid = a.ix.n - t0 < TILE ? a.ix.n - t0 : TILE;
-    uint4 *dst = reinterpret_cast<uint4 *>(a.scores + ((int64_t)ql * P + p) * TILE);
-    const uint4 *src = reinterpret_cast<const uint4 *>(sc);
-    for (int w = tid; w < (words >> 2); w += NT) dst[w] = src[w];
-    __syncthreads();
     uint32_t *h = a.hist + ((int64_t)ql * P + p) * (ns + 2);
-    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : (t == ns + 1 ? 0u : G[t]);
+    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : G[t];
 }
 
 // ================================================================ select ==
-// Block per (query, tile).  From all tiles' counts G_p[t] it derives the
-// threshold T = max{t : sum_p G_p[t] >= B}; every point with score > T is a
-// candidate, and of those with score == T the R = B - #{score > T} lowest ids
-// (taken tile by tile in id order).  The block then compacts its tile in id
-// order with a block-wide scan, so the candidates come out in ascending id.
+// One block per query.  The threshold is T = max{t : sum_p G_p[t] >= B};
+// every point with score > T is a candidate and, of those with score == T,
+// the R = B - #{score > T} lowest ids.  Tiles are visited in id order.  For
+// each tile the chosen ids are marked in an LDS bitmap (score > T from the
+// front of the tile's list; the level-T ids in a second bitmap, of which the
+// lowest ones are kept when only some are taken) and the bitmap is scanned in
+// id order, so the candidates come out in ascending id order.  When T == 0
+// the points of score 0 are the ones missing from the tile's list.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
+    extern __shared__ uint32_t bm[];   // two bitmaps of TILE bits
     __shared__ uint32_t Gt[kMaxNs + 2];
-    __shared__ uint32_t s_T, s_taken, s_base, s_any;
-    __shared__ uint32_t red_g[NT / kWave], red_e[NT / kWave];
+    __shared__ uint32_t red[NT / kWave + 1];
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE, H = ns + 2;
-    const int p = blockIdx.x % P, ql = blockIdx.x / P;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int ql = blockIdx.x, tid = threadIdx.x;
+    const int bwords = TILE >> 5;
+    uint32_t *bmA = bm, *bmT = bm + bwords;
     const uint32_t B = (uint32_t)a.B;
     const uint32_t *hq = a.hist + (int64_t)ql * P * H;
     for (int t = tid; t < H; t += NT) {
@@ -307,81 +394,85 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
         Gt[t] = s;
     }
     __syncthreads();
-    if (tid == 0) {
-        int T = 0;
-        for (int t = ns; t >= 0; --t)
-            if (Gt[t] >= B) { T = t; break; }
-        const uint32_t R = B - Gt[T + 1];
-        uint32_t eq_before = 0, base = 0;
-        for (int pp = 0; pp < p; ++pp) {
-            const uint32_t E = hq[pp * H + T] - hq[pp * H + T + 1];
-            const uint32_t left = R > eq_before ? R - eq_before : 0u;
-            base += hq[pp * H + T + 1] + (E < left ? E : left);
-            eq_before += E;
-        }
-        const uint32_t E = hq[p * H + T] - hq[p * H + T + 1];
+    int T = 0;
+    for (int t = ns; t >= 0; --t)
+        if (Gt[t] >= B) { T = t; break; }
+    const uint32_t R = B - Gt[T + 1];
+    uint32_t *out = a.cand + (int64_t)ql * a.B;
+    const int per = (bwords + NT - 1) / NT;
+    const int w0 = tid * per < bwords ? tid * per : bwords;
+    const int w1 = w0 + per < bwords ? w0 + per : bwords;
+    uint32_t base = 0, eq_before = 0;
+    for (int p = 0; p < P; ++p) {
+        const uint32_t *h = hq + p * H;
+        const uint32_t gt = h[T + 1], E = h[T] - h[T + 1];
         const uint32_t left = R > eq_before ? R - eq_before : 0u;
-        s_taken = E < left ? E : left;
-        s_T = (uint32_t)T;
-        s_base = base;
-        s_any = (hq[p * H + T + 1] + s_taken) > 0u;
-    }
-    __syncthreads();
-    if (!s_any) return;
-    const uint32_t T = s_T, taken = s_taken;
-    const int64_t t0 = (int64_t)p * TILE;
-    const int valid = (int)(a.ix.n - t0 < TILE ? a.ix.n - t0 : TILE);
-    const uint8_t *src = a.scores + ((int64_t)ql * P + p) * TILE;
-    uint32_t *out = a.cand + (int64_t)ql * a.B + s_base;
-    uint32_t gt_carry = 0, eq_carry = 0;
-    for (int r0 = 0; r0 < valid; r0 += NT * 16) {
-        const int j0 = r0 + tid * 16;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (j0 < valid) v = *reinterpret_cast<const uint4 *>(src + j0);
-        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-        uint32_t gt = 0, eq = 0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const uint32_t b = (wd[u >> 2] >> ((u & 3) * 8)) & 0xffu;
-            const bool in = j0 + u < valid;
-            gt += (in && b > T);
-            eq += (in && b == T);
-        }
-        // block exclusive scans of gt and eq
-        uint32_t xg = gt, xe = eq;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint32_t yg = __shfl_up(xg, o, kWave), ye = __shfl_up(xe, o, kWave);
-            if (lane >= o) { xg += yg; xe += ye; }
-        }
+        const uint32_t take = E < left ? E : left;
+        eq_before += E;
+        if (gt + take == 0u) continue;
+        const uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
+        const uint32_t id0 = (uint32_t)p * TILE;
+        const int64_t vv = a.ix.n - (int64_t)id0;
+        const int valid = (int)(vv < TILE ? vv : TILE);
+        const bool partial = take > 0u && (take < E || T == 0);
+        for (int w = tid; w < 2 * bwords; w += NT) bm[w] = 0u;
         __syncthreads();
-        if (lane == kWave - 1) { red_g[wv] = xg; red_e[wv] = xe; }
-        __syncthreads();
-        uint32_t bg = 0, be = 0, tg = 0, te = 0;
-#pragma unroll
-        for (int j = 0; j < NT / kWave; ++j) {
-            bg += j < wv ? red_g[j] : 0u;
-            be += j < wv ? red_e[j] : 0u;
-            tg += red_g[j];
-            te += red_e[j];
+        const uint32_t hiA = (T > 0 && !partial) ? gt + take : gt;
+        for (uint32_t j = tid; j < hiA; j += NT) {
+            const uint32_t lid = seg[j];
+            atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
         }
-        uint32_t er = eq_carry + be + xe - eq;              // eq-rank of this thread's first tie
-        uint32_t pos = gt_carry + bg + xg - gt + (er < taken ? er : taken);
-        if (gt + eq > 0) {
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const uint32_t b = (wd[u >> 2] >> ((u & 3) * 8)) & 0xffu;
-                if (j0 + u >= valid) continue;
-                if (b > T) {
-                    out[pos++] = (uint32_t)(t0 + j0 + u);
-                } else if (b == T) {
-                    if (er < taken) out[pos++] = (uint32_t)(t0 + j0 + u);
-                    ++er;
-                }
+        if (partial && T > 0) {
+            for (uint32_t j = gt + tid; j < gt + E; j += NT) {
+                const uint32_t lid = seg[j];
+                atomicOr(&bmT[lid >> 5], 1u << (lid & 31u));
             }
         }
-        gt_carry += tg;
-        eq_carry += te;
+        __syncthreads();
+        if (partial) {
+            // keep the `take` lowest ties: level-T bits, or for T == 0 the ids
+            // below `valid` that have no score
+            uint32_t cnt = 0;
+            for (int w = w0; w < w1; ++w) {
+                uint32_t x;
+                if (T > 0) {
+                    x = bmT[w];
+                } else {
+                    const uint32_t m = (w + 1) * 32 <= valid ? ~0u
+                                       : (w * 32 >= valid ? 0u : (1u << (valid - w * 32)) - 1u);
+                    x = ~bmA[w] & m;
+                }
+                bmT[w] = x;
+                cnt += __popc(x);
+            }
+            uint32_t tot;
+            uint32_t r = block_excl_scan<NT>(cnt, red, &tot);
+            for (int w = w0; w < w1; ++w) {
+                uint32_t x = bmT[w], keep = 0u;
+                while (x != 0u && r < take) {
+                    const uint32_t bit = x & (0u - x);
+                    keep |= bit;
+                    x ^= bit;
+                    ++r;
+                }
+                bmA[w] |= keep;   // this thread owns words w0..w1
+            }
+            __syncthreads();
+        }
+        uint32_t cnt = 0;
+        for (int w = w0; w < w1; ++w) cnt += __popc(bmA[w]);
+        uint32_t tot;
+        uint32_t pos = base + block_excl_scan<NT>(cnt, red, &tot);
+        for (int w = w0; w < w1; ++w) {
+            uint32_t x = bmA[w];
+            while (x != 0u) {
+                const int b = __ffs(x) - 1;
+                out[pos++] = id0 + (uint32_t)(w * 32 + b);
+                x &= x - 1u;
+            }
+        }
+        base += gt + take;
+        __syncthreads();
     }
 }
 
@@ -491,6 +582,12 @@ hipError_t launch_activate(const QueryPass &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+int collide_static_lds() {
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_collide<512>)) != hipSuccess) return -1;
+    return (int)at.sharedSizeBytes;
+}
+
 hipError_t launch_collide(const QueryPass &p, hipStream_t s) {
     const size_t lds = (size_t)p.ix.TILE;
     hipLaunchKernelGGL(k_collide<512>, dim3((unsigned)(p.nq * p.ix.P)), dim3(512), lds, s, p);
@@ -498,7 +595,8 @@ hipError_t launch_collide(const QueryPass &p, hipStream_t s) {
 }
 
 hipError_t launch_select(const QueryPass &p, hipStream_t s) {
-    hipLaunchKernelGGL(k_select<256>, dim3((unsigned)(p.nq * p.ix.P)), dim3(256), 0, s, p);
+    const size_t lds = (size_t)p.ix.TILE / 4;
+    hipLaunchKernelGGL(k_select<256>, dim3((unsigned)p.nq), dim3(256), lds, s, p);
     return hipGetLastError();
 }
 

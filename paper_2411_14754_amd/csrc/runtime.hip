@@ -189,8 +189,10 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return fail(SUCO_E_HIP, "no usable HIP device");
-    // the collision step keeps a tile of byte scores in LDS next to ~1 KB of counters
-    tile_max = std::min(tile_max, (max_lds - 1024) / 256 * 256);
+    // the collision step keeps a tile of byte scores in LDS next to its static arrays
+    const int static_lds = collide_static_lds();
+    if (static_lds < 0) return fail(SUCO_E_HIP, "cannot query the collision kernel's attributes");
+    tile_max = std::min(tile_max, (max_lds - static_lds) / 256 * 256);
     if (tile_max < 256 || (int64_t)sk * sk * 4 > max_lds || (int64_t)sk * (sk + 1) * 4 + 4096 > max_lds)
         return fail(SUCO_E_UNSUPPORTED, "the device has too little LDS per work-group for this shape");
     suco_index *ix = new (std::nothrow) suco_index();
@@ -203,7 +205,7 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->P = (int)((n + ix->TILE - 1) / ix->TILE);
     const int64_t span = (int64_t)ix->P * ix->TILE;
     if (p && p->query_chunk > 0) ix->chunk = p->query_chunk;
-    else ix->chunk = (int)std::clamp<int64_t>((int64_t(128) << 20) / span, 16, 1024);
+    else ix->chunk = (int)std::clamp<int64_t>((int64_t(1) << 31) / (2 * span), 16, 1024);
     ix->halves_h = make_layout(d, ns);
     if ((rc = dev_alloc(&ix->X, (size_t)n * d)) || (rc = dev_alloc(&ix->cent, (size_t)sk * d)) ||
         (rc = dev_alloc(&ix->halves, (size_t)2 * ns)) ||
@@ -331,11 +333,12 @@ struct Carve {
 };
 
 struct Work {
-    uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint8_t *scores;
+    uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint16_t *lvl; uint8_t *scores;
     uint32_t *cand; uint64_t *part_keys;
 };
 
-Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int parts, size_t *bytes) {
+// dense: also room for the dense SC-scores (exported on request only)
+Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int parts, bool dense, size_t *bytes) {
     Carve c{base};
     Work w;
     w.cells = c.take<uint16_t>(C * ix->ns * ix->K);
@@ -343,7 +346,8 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.aprime = c.take<int32_t>(C * ix->ns);
     w.feat = c.take<float>(C * 2 * ix->ns);
     w.hist = c.take<uint32_t>(C * ix->P * (ix->ns + 2));
-    w.scores = c.take<uint8_t>(C * (size_t)ix->P * ix->TILE);
+    w.lvl = c.take<uint16_t>(C * (size_t)ix->P * ix->TILE);
+    w.scores = dense ? c.take<uint8_t>(C * (size_t)ix->P * ix->TILE) : nullptr;
     w.cand = c.take<uint32_t>(C * (size_t)B);
     w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
     if (bytes) *bytes = c.off;
@@ -360,6 +364,13 @@ int ensure_arena(suco_index *ix, size_t bytes) {
     if (rc) return rc;
     ix->arena_bytes = bytes;
     return SUCO_OK;
+}
+
+// the collision kernel (512 threads) takes this many runs of every subspace per batch
+int runs_per_sub(int ns) {
+    int r = 1;
+    while (r * 2 * ns <= 512 && r < 64) r *= 2;
+    return r;
 }
 
 struct RerankCfg { int G, U, parts; int64_t rpp; };
@@ -406,10 +417,11 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
     DeviceGuard dg(ix->device);
     const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
     size_t bytes = 0;
-    carve(ix, nullptr, C, B, k, rc_cfg.parts, &bytes);
+    const bool dense = dbg && dbg->scores;
+    carve(ix, nullptr, C, B, k, rc_cfg.parts, dense, &bytes);
     if ((rc = ensure_arena(ix, bytes))) return rc;
     if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
-    Work w = carve(ix, ix->arena, C, B, k, rc_cfg.parts, nullptr);
+    Work w = carve(ix, ix->arena, C, B, k, rc_cfg.parts, dense, nullptr);
     const IndexView v = ix->view();
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
@@ -420,10 +432,11 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         qp.alpha_q = alpha_q ? alpha_q + c0 : nullptr;
         qp.alpha = alpha;
         qp.B = B;
+        qp.runs_per_sub = runs_per_sub(ix->ns);
         qp.k = k;
         qp.cells = w.cells; qp.ncells = w.ncells; qp.aprime = w.aprime;
         qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
-        qp.hist = w.hist; qp.scores = w.scores; qp.cand = w.cand;
+        qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores; qp.cand = w.cand;
         HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
@@ -587,21 +600,22 @@ int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells
     DeviceGuard dg(ix->device);
     const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
     size_t bytes = 0;
-    carve(ix, nullptr, C, B, k, 1, &bytes);
+    carve(ix, nullptr, C, B, k, 1, scores != nullptr, &bytes);
     int rc = ensure_arena(ix, bytes);
     if (rc) return rc;
     if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
-    Work w = carve(ix, ix->arena, C, B, k, 1, nullptr);
+    Work w = carve(ix, ix->arena, C, B, k, 1, scores != nullptr, nullptr);
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
         QueryPass qp{};
         qp.ix = ix->view();
         qp.nq = cn;
         qp.B = B;
+        qp.runs_per_sub = runs_per_sub(ix->ns);
         qp.k = k;
         qp.cells = const_cast<uint16_t *>(cells) + c0 * ix->ns * ix->K;
         qp.ncells = const_cast<int32_t *>(ncells) + c0 * ix->ns;
-        qp.hist = w.hist; qp.scores = w.scores;
+        qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores;
         qp.cand = reinterpret_cast<uint32_t *>(cand) + c0 * B;
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
@@ -629,10 +643,10 @@ int suco_rerank(const suco_index *cix, const float *Q, int64_t nq, const int32_t
     DeviceGuard dg(ix->device);
     const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
     size_t bytes = 0;
-    carve(ix, nullptr, C, B, k, c.parts, &bytes);
+    carve(ix, nullptr, C, B, k, c.parts, false, &bytes);
     if ((rc = ensure_arena(ix, bytes))) return rc;
     if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
-    Work w = carve(ix, ix->arena, C, B, k, c.parts, nullptr);
+    Work w = carve(ix, ix->arena, C, B, k, c.parts, false, nullptr);
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
         RerankPass rp{};

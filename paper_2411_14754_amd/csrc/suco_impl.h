@@ -38,13 +38,15 @@ struct QueryPass {
     double alpha;             // used when alpha_q is null
     int64_t B;
     int k;
+    int runs_per_sub;         // collision step: runs of each subspace per batch (power of two)
     // workspace
     uint16_t *cells;          // [nq][ns][K]
     int32_t *ncells;          // [nq][ns]
     int32_t *aprime;          // [nq][ns]
     float *feat;              // [nq][2ns] or null
     uint32_t *hist;           // [nq][P][ns+2] tile counts of score >= t
-    uint8_t *scores;          // [nq][P*TILE]
+    uint16_t *lvl;            // [nq][P][TILE] non-zero-score tile-local ids by level
+    uint8_t *scores;          // [nq][P*TILE] dense scores, or null
     uint32_t *cand;           // [nq][B]
 };
 
@@ -65,6 +67,7 @@ struct RerankPass {
 };
 
 // Launchers (query_kernels.hip)
+int collide_static_lds();   // bytes of LDS the collision kernel declares statically
 hipError_t launch_activate(const QueryPass &p, hipStream_t s);
 hipError_t launch_collide(const QueryPass &p, hipStream_t s);
 hipError_t launch_select(const QueryPass &p, hipStream_t s);
