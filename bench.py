@@ -110,7 +110,20 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--tile-max", type=int, default=0, help="largest collision tile (0: library default)")
     ap.add_argument("--query-chunk", type=int, default=0, help="queries per pass (0: library default)")
+    ap.add_argument("--alpha", type=float, default=None, help="time this alpha and skip the sweep")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "
+                         "scale HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
               f"queries with no exchange, see the design notes)", file=sys.stderr)
@@ -147,7 +160,7 @@ def main():
         ix.query(Qd, k, alpha, beta, out=(ids, dists))
 
     sweep = []
-    for a in ALPHA_GRID:
+    for a in (ALPHA_GRID if args.alpha is None else (args.alpha,)):
         run(a)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,7 +173,7 @@ def main():
         sweep.append({"alpha": a, "recall": round(r, 5), "qps": round(nq / (ms / 1e3), 1)})
         log(f"alpha={a}: recall@10={r:.4f} qps={nq / (ms / 1e3):.0f}")
     ok = [s for s in sweep if s["recall"] >= TARGET_RECALL]
-    alpha = ok[0]["alpha"] if ok else ALPHA_GRID[-1]
+    alpha = ok[0]["alpha"] if ok else sweep[-1]["alpha"]
     qps_interp = None
     for lo, hi in zip(sweep, sweep[1:]):
         if lo["recall"] < TARGET_RECALL <= hi["recall"]:
