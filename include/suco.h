@@ -172,6 +172,38 @@ SUCO_API int suco_collide_select(const suco_index *ix, int64_t nq, const uint16_
 SUCO_API int suco_rerank(const suco_index *ix, const float *Q, int64_t nq, const int32_t *cand,
                 int64_t B, int32_t k, int32_t *ids, float *dists, void *stream);
 
+/* ------------------------------------------------------------ batcher --
+ * Batched form of suco_query for streams of batches of uneven size.  A batcher
+ * holds staging buffers and a workspace sized for max_batch queries and, per
+ * power-of-two batch-size bucket, one HIP graph of the whole query path whose
+ * kernels stride over their work and read the batch size on the device.  A call
+ * writes the caller's pointers and nq into a device mailbox (one small kernel)
+ * and launches the bucket's graph.  On a bucket's first use its launch shapes
+ * (re-rank rows per work-group, grid caps) are tuned by timing candidate
+ * graphs on that batch; the choice is appended to `tune_file` when one is given
+ * and read back by later batchers.  Results are bitwise those of
+ * suco_query/suco_query_alpha with the same arguments.
+ *
+ *  ix         the index (must outlive the batcher); not modified.
+ *  max_batch  largest nq, 1..65536 (rounded up to a power of two).
+ *  k, beta    as in suco_query, fixed for the batcher.
+ *  tune_file  host path of the tuning record, or NULL.
+ * suco_batcher_query: Q device [nq][d]; alpha_q device [nq] float32 or NULL
+ *  (then `alpha`); ids/dists device [nq][k]; asynchronous on `stream`; calls on
+ *  one batcher are serialised.  The caller's buffers must stay valid until the
+ *  stream reaches the call.  The first call of a bucket synchronises `stream`
+ *  while it tunes. */
+typedef struct suco_batcher suco_batcher;
+SUCO_API int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, double beta,
+                                 const char *tune_file, suco_batcher **out);
+SUCO_API int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float *alpha_q,
+                                double alpha, int32_t *ids, float *dists, void *stream);
+/* Tuned launch shape of a built bucket: params[3] = {re-rank rows per
+ * work-group, collision grid cap, re-rank grid cap} (0 = one block per item),
+ * ms = the tuned graph's time on its first batch. */
+SUCO_API int suco_batcher_tuning(const suco_batcher *b, int32_t bucket, int32_t *params, double *ms);
+SUCO_API int suco_batcher_free(suco_batcher *b);
+
 /* ----------------------------------------------------------- timing --
  * Per-step timing for measurement: while enabled, every launch of a query
  * call is bracketed by a pair of HIP events on the query stream (a few

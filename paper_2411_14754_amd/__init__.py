@@ -22,7 +22,8 @@ EXPORTED = (
     "suco_version", "suco_last_error", "suco_count_A", "suco_count_B", "suco_build",
     "suco_build_from_index", "suco_index_export", "suco_index_info", "suco_index_free", "suco_query",
     "suco_query_alpha", "suco_query_debug", "suco_collide_select", "suco_rerank", "suco_profile",
-    "suco_profile_read",
+    "suco_profile_read", "suco_batcher_create", "suco_batcher_query", "suco_batcher_tuning",
+    "suco_batcher_free",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge")
@@ -70,6 +71,10 @@ def lib():
         L.suco_rerank.argtypes = [P, P, i64, P, i64, i32, P, P, P]
         L.suco_profile.argtypes = [P, C.c_int]
         L.suco_profile_read.argtypes = [P, P, P]
+        L.suco_batcher_create.argtypes = [P, i32, i32, dbl, C.c_char_p, C.POINTER(P)]
+        L.suco_batcher_query.argtypes = [P, P, i64, P, dbl, P, P, P]
+        L.suco_batcher_tuning.argtypes = [P, i32, P, P]
+        L.suco_batcher_free.argtypes = [P]
         _lib = L
     return _lib
 
@@ -252,3 +257,44 @@ class Index:
         _check(lib().suco_rerank(self._h, pq, nq, _dev(cand, torch.int32), B, k, _dev(ids, torch.int32),
                                  _dev(dists, torch.float32), _stream(stream)))
         return ids, dists
+
+
+class Batcher:
+    """Batched query executor over an Index (see suco_batcher_create): one HIP
+    graph per power-of-two batch-size bucket, tuned on first use."""
+
+    def __init__(self, index: Index, max_batch: int, k: int, beta: float, tune_file: str | None = None):
+        self.index, self.k, self.beta = index, k, beta
+        h = C.c_void_p()
+        _check(lib().suco_batcher_create(index._h, int(max_batch), int(k), float(beta),
+                                         tune_file.encode() if tune_file else None, C.byref(h)))
+        self._h = h
+
+    def query(self, Q, alpha: float = 0.0, alpha_q=None, out=None, stream=None):
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.index.d), "Q")
+        pa = _dev(alpha_q, torch.float32, (nq,), "alpha_q") if alpha_q is not None else None
+        ids, dists = out if out is not None else self.index._out(nq, self.k)
+        _check(lib().suco_batcher_query(self._h, pq, nq, pa, float(alpha), _dev(ids, torch.int32),
+                                        _dev(dists, torch.float32), _stream(stream)))
+        return ids, dists
+
+    def tuning(self, bucket: int):
+        prm = np.zeros(3, np.int32)
+        ms = C.c_double()
+        _check(lib().suco_batcher_tuning(self._h, int(bucket), prm.ctypes.data_as(P), C.byref(ms)))
+        return {"rows_per_part": int(prm[0]), "collide_grid_cap": int(prm[1]), "rerank_grid_cap": int(prm[2]),
+                "ms": ms.value}
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().suco_batcher_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if _lib is not None and getattr(self, "_h", None) is not None and self._h.value:
+                _lib.suco_batcher_free(self._h)
+        except Exception:
+            pass

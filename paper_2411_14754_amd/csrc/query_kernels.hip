@@ -14,6 +14,8 @@
 //             lists, then a per-query merge (Alg. 4 last lines)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "suco_impl.h"
 
 namespace suco {
@@ -105,7 +107,7 @@ __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
 // first ones in (r1, r2) order until A is reached.  The result is exactly the
 // prefix Alg. 3 retrieves, computed without a serial walk.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
+__device__ __forceinline__ void activate_item(const QueryPass &a, const int item) {
     extern __shared__ uint32_t Ptab[];          // [sk][sk+1] row prefix sums of sizes
     __shared__ float Dr[2][kMaxSqrtK];
     __shared__ float Ds[2][kMaxSqrtK];
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
     __shared__ uint32_t red[NT / kWave + 1];
 
     const int sk = a.ix.sk, K = a.ix.K, ns = a.ix.ns;
-    const int ql = blockIdx.x / ns, i = blockIdx.x - ql * ns;
+    const int ql = item / ns, i = item - ql * ns;
     const int tid = threadIdx.x;
     const float *q = a.Q + (int64_t)ql * a.ix.d;
 
@@ -164,7 +166,8 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
     __syncthreads();
     if (a.feat != nullptr && tid < 2) a.feat[(int64_t)ql * 2 * ns + 2 * i + tid] = __fsqrt_rn(Ds[tid][0]);
 
-    const uint32_t A = count_A_dev(a.alpha_q ? (double)a.alpha_q[ql] : a.alpha, a.ix.n);
+    const double alpha = a.alpha_qd ? a.alpha_qd[ql] : (a.alpha_q ? (double)a.alpha_q[ql] : a.alpha);
+    const uint32_t A = count_A_dev(alpha, a.ix.n);
     const bool row = tid < sk;
     const float d1 = row ? Ds[0][tid] : 0.f;
     const uint32_t *prow = Ptab + (row ? tid : 0) * stride;
@@ -224,6 +227,27 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
     }
 }
 
+// Queries in this pass: the pass's own count, or, for a batch whose size is
+// read on the device (captured graphs), what is left of it after q_base,
+// capped at the pass capacity.
+__device__ __forceinline__ int pass_nq(const int *nq_dev, int q_base, int nq) {
+    if (nq_dev == nullptr) return nq;
+    const int left = *nq_dev - q_base;
+    return left <= 0 ? 0 : (left < nq ? left : nq);
+}
+
+// Every kernel walks its work items with a grid stride, so a launch may use
+// fewer blocks than items (a persistent grid) and one launch shape serves any
+// batch up to the pass capacity.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
+    const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * a.ix.ns;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        activate_item<NT>(a, item);
+        __syncthreads();
+    }
+}
+
 // =============================================================== collide ==
 // Block per (query, tile).  The tile's TILE scores live in LDS as bytes packed
 // in 32-bit words; each point id occurs once per subspace, so a 32-bit LDS
@@ -247,7 +271,7 @@ constexpr int kCollideUnroll = 4;
 constexpr int kTouchCap = 4096;
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
+__device__ __forceinline__ void collide_item(const QueryPass &a, const int item) {
     extern __shared__ uint32_t sc[];   // TILE/4 words
     __shared__ uint32_t G[kMaxNs + 2];
     __shared__ uint32_t cur[kMaxNs + 2];
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     __shared__ uint16_t touched[kTouchCap];
     __shared__ uint32_t n_touched;
     const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
-    const int p = blockIdx.x % P, ql = blockIdx.x / P;
+    const int p = item % P, ql = item / P;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
     const int words = TILE >> 2;
@@ -368,6 +392,17 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : G[t];
 }
 
+// Items are (query, tile) with the tile fastest; a grid that is a multiple of
+// P keeps every tile on the same XCD (blocks are dealt to XCDs round-robin).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
+    const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * a.ix.P;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        collide_item<NT>(a, item);
+        __syncthreads();
+    }
+}
+
 // ================================================================ select ==
 // One block per query.  The threshold is T = max{t : sum_p G_p[t] >= B};
 // every point with score > T is a candidate and, of those with score == T,
@@ -378,12 +413,12 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 // id order, so the candidates come out in ascending id order.  When T == 0
 // the points of score 0 are the ones missing from the tile's list.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_select(QueryPass a) {
+__device__ __forceinline__ void select_item(const QueryPass &a, const int ql) {
     extern __shared__ uint32_t bm[];   // two bitmaps of TILE bits
     __shared__ uint32_t Gt[kMaxNs + 2];
     __shared__ uint32_t red[NT / kWave + 1];
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE, H = ns + 2;
-    const int ql = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int bwords = TILE >> 5;
     uint32_t *bmA = bm, *bmT = bm + bwords;
     const uint32_t B = (uint32_t)a.B;
@@ -476,6 +511,15 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
     }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select(QueryPass a) {
+    const int items = pass_nq(a.nq_dev, a.q_base, a.nq);
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        select_item<NT>(a, item);
+        __syncthreads();
+    }
+}
+
 // ================================================================ rerank ==
 // Block of NT threads per (query, part of the candidate list).  G lanes share
 // a row: lane li of the group reads float4 slices li, li+G, ... of the row,
@@ -497,9 +541,9 @@ __device__ __forceinline__ void topk_insert(uint64_t &best, uint64_t kk, int k, 
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
+__device__ __forceinline__ void rerank_item(const RerankPass &r, const int item) {
     __shared__ uint64_t wl[NT / kWave][kMaxK];
-    const int ql = blockIdx.x / r.parts, part = blockIdx.x - ql * r.parts;
+    const int ql = item / r.parts, part = item - ql * r.parts;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int G = r.G, R = kWave / G, li = lane & (G - 1), slot = lane / G;
     const int d4 = r.d >> 2, k = r.k;
@@ -551,9 +595,18 @@ __global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
     }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
+    const int items = pass_nq(r.nq_dev, r.q_base, r.nq) * r.parts;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        rerank_item<NT>(r, item);
+        __syncthreads();
+    }
+}
+
 // One wave per query: merge the parts' lists, write ids and Euclidean distances.
-__global__ __launch_bounds__(kWave) void k_merge(RerankPass r) {
-    const int ql = blockIdx.x, lane = threadIdx.x, k = r.k;
+__device__ __forceinline__ void merge_item(const RerankPass &r, const int ql) {
+    const int lane = threadIdx.x, k = r.k;
     const uint64_t *pk = r.part_keys + (int64_t)ql * r.parts * k;
     uint64_t best = lane < k ? pk[lane] : ~0ull;
     for (int p = 1; p < r.parts; ++p) {
@@ -571,15 +624,73 @@ __global__ __launch_bounds__(kWave) void k_merge(RerankPass r) {
     }
 }
 
+__global__ __launch_bounds__(kWave) void k_merge(RerankPass r) {
+    const int items = pass_nq(r.nq_dev, r.q_base, r.nq);
+    for (int item = blockIdx.x; item < items; item += gridDim.x) merge_item(r, item);
+}
+
 // ============================================================= launchers ==
-hipError_t launch_activate(const QueryPass &p, hipStream_t s) {
-    const size_t lds = sizeof(uint32_t) * (size_t)p.ix.sk * (p.ix.sk + 1);
-    const dim3 grid((unsigned)(p.nq * p.ix.ns));
-    if (p.ix.sk <= 64)
-        hipLaunchKernelGGL(k_activate<64>, grid, dim3(64), lds, s, p);
-    else
-        hipLaunchKernelGGL(k_activate<128>, grid, dim3(128), lds, s, p);
-    return hipGetLastError();
+// A plan names the kernel, its launch shape and dynamic LDS.  `cap` > 0 limits
+// the grid (the kernels stride over their items); 0 launches one block per item
+// of a full pass.
+namespace {
+unsigned grid_for(int64_t items, int cap) {
+    if (items < 1) items = 1;
+    return (unsigned)(cap > 0 && cap < items ? cap : items);
+}
+}  // namespace
+
+Launch plan_activate(const QueryPass &p, int cap) {
+    Launch L;
+    L.lds = sizeof(uint32_t) * (size_t)p.ix.sk * (p.ix.sk + 1);
+    L.grid = dim3(grid_for((int64_t)p.nq * p.ix.ns, cap));
+    if (p.ix.sk <= 64) { L.func = reinterpret_cast<const void *>(&k_activate<64>); L.block = dim3(64); }
+    else { L.func = reinterpret_cast<const void *>(&k_activate<128>); L.block = dim3(128); }
+    return L;
+}
+
+Launch plan_collide(const QueryPass &p, int cap) {
+    Launch L;
+    L.lds = (size_t)p.ix.TILE;
+    const int64_t items = (int64_t)p.nq * p.ix.P;
+    unsigned g = grid_for(items, cap);
+    if ((int64_t)g < items) g = std::max<unsigned>(1u, g / p.ix.P) * p.ix.P;   // whole tile rounds
+    L.grid = dim3(g);
+    L.block = dim3(512);
+    L.func = reinterpret_cast<const void *>(&k_collide<512>);
+    return L;
+}
+
+Launch plan_select(const QueryPass &p, int cap) {
+    Launch L;
+    L.lds = (size_t)p.ix.TILE / 4;
+    L.grid = dim3(grid_for(p.nq, cap));
+    L.block = dim3(256);
+    L.func = reinterpret_cast<const void *>(&k_select<256>);
+    return L;
+}
+
+Launch plan_rerank(const RerankPass &r, int cap) {
+    Launch L;
+    L.lds = 0;
+    L.grid = dim3(grid_for((int64_t)r.nq * r.parts, cap));
+    L.block = dim3(256);
+    L.func = reinterpret_cast<const void *>(&k_rerank<256>);
+    return L;
+}
+
+Launch plan_merge(const RerankPass &r, int cap) {
+    Launch L;
+    L.lds = 0;
+    L.grid = dim3(grid_for(r.nq, cap));
+    L.block = dim3(kWave);
+    L.func = reinterpret_cast<const void *>(&k_merge);
+    return L;
+}
+
+hipError_t launch(const Launch &L, void *arg, hipStream_t s) {
+    void *args[] = {arg};
+    return hipLaunchKernel(L.func, L.grid, L.block, args, L.lds, s);
 }
 
 int collide_static_lds() {
@@ -588,26 +699,29 @@ int collide_static_lds() {
     return (int)at.sharedSizeBytes;
 }
 
+hipError_t launch_activate(const QueryPass &p, hipStream_t s) {
+    QueryPass c = p;
+    return launch(plan_activate(p, 0), &c, s);
+}
+
 hipError_t launch_collide(const QueryPass &p, hipStream_t s) {
-    const size_t lds = (size_t)p.ix.TILE;
-    hipLaunchKernelGGL(k_collide<512>, dim3((unsigned)(p.nq * p.ix.P)), dim3(512), lds, s, p);
-    return hipGetLastError();
+    QueryPass c = p;
+    return launch(plan_collide(p, 0), &c, s);
 }
 
 hipError_t launch_select(const QueryPass &p, hipStream_t s) {
-    const size_t lds = (size_t)p.ix.TILE / 4;
-    hipLaunchKernelGGL(k_select<256>, dim3((unsigned)p.nq), dim3(256), lds, s, p);
-    return hipGetLastError();
+    QueryPass c = p;
+    return launch(plan_select(p, 0), &c, s);
 }
 
 hipError_t launch_rerank(const RerankPass &r, hipStream_t s) {
-    hipLaunchKernelGGL(k_rerank<256>, dim3((unsigned)(r.nq * r.parts)), dim3(256), 0, s, r);
-    return hipGetLastError();
+    RerankPass c = r;
+    return launch(plan_rerank(r, 0), &c, s);
 }
 
 hipError_t launch_merge(const RerankPass &r, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)r.nq), dim3(kWave), 0, s, r);
-    return hipGetLastError();
+    RerankPass c = r;
+    return launch(plan_merge(r, 0), &c, s);
 }
 
 }  // namespace suco

@@ -1,158 +1,10 @@
 // Host side of the SuCo library: argument validation, the index object, the
 // query workspace and the launch sequences behind the C ABI in suco.h.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <mutex>
-#include <new>
-#include <string>
-#include <vector>
-
-#include "suco.h"
-#include "suco_impl.h"
+#include "runtime_impl.h"
 
 using namespace suco;
 
 namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const std::string &msg) {
-    g_err = msg;
-    return code;
-}
-
-#define HIPCHECK(expr)                                                                        \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return fail(SUCO_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr uint64_t kMagic = 0x5375436f49647831ULL;
-
-int64_t count_A_host(double alpha, int64_t n) {
-#pragma clang fp contract(off)
-    double prod = alpha * (double)n;
-    int64_t a = (int64_t)std::ceil(prod - 1e-9);
-    return std::min<int64_t>(std::max<int64_t>(a, 1), n);
-}
-
-int64_t count_B_host(double beta, int64_t n, int k) {
-#pragma clang fp contract(off)
-    double prod = beta * (double)n;
-    int64_t b = (int64_t)std::floor(prod + 1e-9);
-    return std::min<int64_t>(std::max<int64_t>(b, k), n);
-}
-
-// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014), counter form: output m of a
-// stream with the given base.
-uint64_t splitmix64_at(uint64_t base, uint64_t m) {
-    uint64_t z = base + (m + 1) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
-struct DeviceGuard {
-    int prev = -1;
-    bool changed = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
-            changed = hipSetDevice(dev) == hipSuccess;
-        }
-    }
-    ~DeviceGuard() {
-        if (changed) (void)hipSetDevice(prev);
-    }
-};
-
-template <class T>
-int dev_alloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc((void **)p, sizeof(T) * count) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return fail(SUCO_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
-    }
-    return SUCO_OK;
-}
-
-}  // namespace
-
-struct suco_index {
-    uint64_t magic = kMagic;
-    int device = 0;
-    int64_t n = 0;
-    int d = 0, ns = 0, sk = 0, K = 0, P = 0, TILE = 0, chunk = 0;
-    std::vector<HalfDims> halves_h;
-    std::vector<float> cent_h;
-    float *X = nullptr;
-    float *cent = nullptr;
-    HalfDims *halves = nullptr;
-    uint32_t *toffs = nullptr;
-    uint16_t *ids16 = nullptr;
-    uint32_t *csize = nullptr;
-    uint8_t *assign = nullptr;
-    // query workspace (one arena, grown on demand)
-    std::mutex mu;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-    char *arena = nullptr;
-    size_t arena_bytes = 0;
-    // optional per-step timing: event pairs around every launch
-    struct EvPair { hipEvent_t a, b; int stage; };
-    bool prof_on = false;
-    std::vector<EvPair> prof_pool;
-    size_t prof_used = 0;
-
-    IndexView view() const {
-        IndexView v;
-        v.X = X; v.cent = cent; v.halves = halves; v.toffs = toffs; v.ids16 = ids16; v.csize = csize;
-        v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE;
-        return v;
-    }
-
-    void release() {
-        if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
-        for (auto &e : prof_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
-        prof_pool.clear();
-        prof_used = 0;
-        for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
-                        (void *)assign, (void *)arena})
-            if (p) (void)hipFree(p);
-        X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
-        assign = nullptr; arena = nullptr; arena_bytes = 0;
-        magic = 0;
-    }
-};
-
-namespace {
-
-bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
-
-enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kStages };
-
-// Launch through `fn`, bracketed by a pair of timing events when profiling is on.
-template <class F>
-hipError_t timed(suco_index *ix, int stage, hipStream_t st, F &&fn) {
-    if (!ix->prof_on) return fn();
-    if (ix->prof_used == ix->prof_pool.size()) {
-        suco_index::EvPair e{};
-        if (hipEventCreate(&e.a) != hipSuccess) return hipErrorOutOfMemory;
-        if (hipEventCreate(&e.b) != hipSuccess) { (void)hipEventDestroy(e.a); return hipErrorOutOfMemory; }
-        ix->prof_pool.push_back(e);
-    }
-    auto &ev = ix->prof_pool[ix->prof_used++];
-    ev.stage = stage;
-    hipError_t e = hipEventRecord(ev.a, st);
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    return hipEventRecord(ev.b, st);
-}
 
 int check_shape(int64_t n, int32_t d, int32_t ns, int32_t sk) {
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(SUCO_E_INVAL, "n must be in [1, 2^31)");
@@ -363,28 +215,6 @@ int ensure_arena(suco_index *ix, size_t bytes) {
     int rc = dev_alloc(&ix->arena, bytes);
     if (rc) return rc;
     ix->arena_bytes = bytes;
-    return SUCO_OK;
-}
-
-// the collision kernel (512 threads) takes this many runs of every subspace per batch
-int runs_per_sub(int ns) {
-    int r = 1;
-    while (r * 2 * ns <= 512 && r < 64) r *= 2;
-    return r;
-}
-
-struct RerankCfg { int G, U, parts; int64_t rpp; };
-
-int rerank_cfg(int d, int64_t B, RerankCfg *c) {
-    if (d % 4) return fail(SUCO_E_UNSUPPORTED, "the re-rank needs d to be a multiple of 4");
-    const int d4 = d / 4;
-    int G = 1;
-    while (G * 2 <= std::max(1, d4 / 2) && G < kWave) G *= 2;
-    const int U = (d4 + G - 1) / G;
-    if (U > kMaxU) return fail(SUCO_E_UNSUPPORTED, "the re-rank supports d <= 2048");
-    c->G = G; c->U = U;
-    c->rpp = 512;
-    c->parts = (int)((B + c->rpp - 1) / c->rpp);
     return SUCO_OK;
 }
 

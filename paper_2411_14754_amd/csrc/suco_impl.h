@@ -35,10 +35,13 @@ struct QueryPass {
     const float *Q;           // [nq][d]
     int nq;
     const float *alpha_q;     // [nq] or null
-    double alpha;             // used when alpha_q is null
+    const double *alpha_qd;   // [nq] or null (takes precedence over alpha_q)
+    double alpha;             // used when both are null
     int64_t B;
     int k;
     int runs_per_sub;         // collision step: runs of each subspace per batch (power of two)
+    const int *nq_dev;        // if set: the batch size is read here and this pass takes
+    int q_base;               //   queries [q_base, q_base + nq) of it (nq is the capacity)
     // workspace
     uint16_t *cells;          // [nq][ns][K]
     int32_t *ncells;          // [nq][ns]
@@ -58,6 +61,8 @@ struct RerankPass {
     int64_t n;                // points in X
     int d, k, nq;
     int parts;                // work-groups per query
+    const int *nq_dev;        // as in QueryPass
+    int q_base;
     int64_t rows_per_part;
     int G;                    // lanes per row (power of two)
     int U;                    // float4 slices per lane
@@ -68,6 +73,19 @@ struct RerankPass {
 
 // Launchers (query_kernels.hip)
 int collide_static_lds();   // bytes of LDS the collision kernel declares statically
+
+// A kernel with its launch shape: the same plan serves a direct launch and a graph node.
+struct Launch {
+    const void *func = nullptr;
+    dim3 grid, block;
+    size_t lds = 0;
+};
+Launch plan_activate(const QueryPass &p, int cap);
+Launch plan_collide(const QueryPass &p, int cap);
+Launch plan_select(const QueryPass &p, int cap);
+Launch plan_rerank(const RerankPass &r, int cap);
+Launch plan_merge(const RerankPass &r, int cap);
+hipError_t launch(const Launch &L, void *arg, hipStream_t s);
 hipError_t launch_activate(const QueryPass &p, hipStream_t s);
 hipError_t launch_collide(const QueryPass &p, hipStream_t s);
 hipError_t launch_select(const QueryPass &p, hipStream_t s);
