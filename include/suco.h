@@ -204,6 +204,57 @@ SUCO_API int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, con
 SUCO_API int suco_batcher_tuning(const suco_batcher *b, int32_t bucket, int32_t *params, double *ms);
 SUCO_API int suco_batcher_free(suco_batcher *b);
 
+/* ---------------------------------------------------- learned budget --
+ * The paper fixes one collision ratio alpha for all queries (Alg. 4) and names
+ * combining the method with learned models as future work (Sec. 6).  A small
+ * network predicts a per-query alpha instead:
+ *   features f (2*n_s + 1 per query): for each subspace half, the Euclidean
+ *     distance from the query half to its nearest centre, then the query norm;
+ *   x = (f - mu) / sigma; h1 = GELU(W1 x + b1); h2 = GELU(W2 h1 + b2);
+ *   y = W3 h2 + b3 (y predicts log alpha); GELU(x) = x * Phi(x);
+ *   alpha = clamp(scale * exp(y), alpha_min, alpha_max).
+ * Parameters are one FP32 array in the order W1 [H][n_in], b1 [H], W2 [H][H],
+ * b2 [H], W3 [H], b3 [1]; H = 128.  Training runs in FP32 on the GPU (mean
+ * squared error, Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
+ * correction); inference rounds weights and layer inputs to BF16 and
+ * accumulates in FP32.  All device arrays below are row-major FP32. */
+typedef struct suco_mlp suco_mlp;
+/* Parameter count, or -1 if (n_in, hidden) is not supported. */
+SUCO_API int64_t suco_mlp_num_params(int32_t n_in, int32_t hidden);
+/* params: host array (NULL: uniform +-sqrt(3/fan_in) from SplitMix64 draws of
+ * `seed`, biases 0).  mu = 0 and sigma = 1 until suco_mlp_set_norm. */
+SUCO_API int suco_mlp_create(int32_t n_in, int32_t hidden, const float *params, uint64_t seed, suco_mlp **out);
+SUCO_API int suco_mlp_set_norm(suco_mlp *m, const float *mu, const float *sigma);         /* host [n_in] */
+SUCO_API int suco_mlp_get_params(const suco_mlp *m, float *params);                       /* host, synchronises */
+SUCO_API int suco_mlp_set_params(suco_mlp *m, const float *params);                       /* host */
+/* Loss and its gradient for rows F [m][n_in], targets t [m] (device); grads
+ * device [num_params], loss device [1] or NULL.  Asynchronous on `stream`. */
+SUCO_API int suco_mlp_forward_backward(suco_mlp *m, const float *F, const float *t, int64_t rows, float *loss,
+                                       float *grads, void *stream);
+/* One epoch of mini-batch Adam over F [m][n_in], t [m] (device): batches of
+ * `batch` consecutive positions of `order` (device int32 [m], a permutation of
+ * the rows; NULL = row order).  mean_loss (host, may be NULL) receives the
+ * mean batch loss, which synchronises the stream after every batch. */
+SUCO_API int suco_mlp_train_epoch(suco_mlp *m, const float *F, const float *t, int64_t rows, int32_t batch,
+                                  float lr, const int32_t *order, float *mean_loss, void *stream);
+/* BF16 inference: y [m] (log alpha) and alpha [m], device, either may be NULL. */
+SUCO_API int suco_mlp_predict(suco_mlp *m, const float *F, int64_t rows, float scale, float alpha_min,
+                              float alpha_max, float *y, float *alpha, void *stream);
+SUCO_API int suco_mlp_free(suco_mlp *m);
+/* Query features F device [nq][2*n_s + 1]. */
+SUCO_API int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float *F, void *stream);
+/* k-ANN query with the network's per-query alpha: features, BF16 inference,
+ * then exactly suco_query_alpha with those alphas; alpha_used (device [nq],
+ * may be NULL) receives them. */
+SUCO_API int suco_query_learned(const suco_index *ix, suco_mlp *m, const float *Q, int64_t nq, int32_t k,
+                                double beta, float scale, float alpha_min, float alpha_max, int32_t *ids,
+                                float *dists, float *alpha_used, void *stream);
+/* Attach a model to a batcher (NULL detaches): its graphs then compute the
+ * features and the alphas on the device before the query path, and each
+ * batch's results equal suco_query_learned's.  The model must outlive the
+ * batcher or be detached first. */
+SUCO_API int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, float alpha_min, float alpha_max);
+
 /* ----------------------------------------------------------- timing --
  * Per-step timing for measurement: while enabled, every launch of a query
  * call is bracketed by a pair of HIP events on the query stream (a few

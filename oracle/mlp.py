@@ -59,6 +59,17 @@ class MLP64:
             return y, (x, z1, h1, z2, h2)
         return y
 
+    def forward_bf16(self, F):
+        """BF16 inference model: parameters and each layer's input rounded to
+        BF16 (the standardised features in FP32 first), products and sums in
+        FP64, GELU in FP64 and its output rounded to BF16 through FP32."""
+        p = {k: bf16_round(np.asarray(v, np.float32)).astype(np.float64) for k, v in self.p.items()}
+        x32 = (np.asarray(F, np.float32) - self.mu.astype(np.float32)) / self.sigma.astype(np.float32)
+        x = bf16_round(x32).astype(np.float64)
+        h1 = bf16_round(gelu(x @ p["W1"].T + p["b1"]).astype(np.float32)).astype(np.float64)
+        h2 = bf16_round(gelu(h1 @ p["W2"].T + p["b2"]).astype(np.float32)).astype(np.float64)
+        return (h2 @ p["W3"].T + p["b3"])[:, 0]
+
     def loss_and_grad(self, F, t):
         """MSE loss and its analytic gradient with respect to every parameter."""
         p = self.p

@@ -23,7 +23,9 @@ EXPORTED = (
     "suco_build_from_index", "suco_index_export", "suco_index_info", "suco_index_free", "suco_query",
     "suco_query_alpha", "suco_query_debug", "suco_collide_select", "suco_rerank", "suco_profile",
     "suco_profile_read", "suco_batcher_create", "suco_batcher_query", "suco_batcher_tuning",
-    "suco_batcher_free",
+    "suco_batcher_free", "suco_mlp_num_params", "suco_mlp_create", "suco_mlp_set_norm", "suco_mlp_get_params",
+    "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
+    "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge")
@@ -75,6 +77,19 @@ def lib():
         L.suco_batcher_query.argtypes = [P, P, i64, P, dbl, P, P, P]
         L.suco_batcher_tuning.argtypes = [P, i32, P, P]
         L.suco_batcher_free.argtypes = [P]
+        L.suco_mlp_num_params.restype = i64
+        L.suco_mlp_num_params.argtypes = [i32, i32]
+        L.suco_mlp_create.argtypes = [i32, i32, P, C.c_uint64, C.POINTER(P)]
+        L.suco_mlp_set_norm.argtypes = [P, P, P]
+        L.suco_mlp_get_params.argtypes = [P, P]
+        L.suco_mlp_set_params.argtypes = [P, P]
+        L.suco_mlp_forward_backward.argtypes = [P, P, P, i64, P, P, P]
+        L.suco_mlp_train_epoch.argtypes = [P, P, P, i64, i32, C.c_float, P, P, P]
+        L.suco_mlp_predict.argtypes = [P, P, i64, C.c_float, C.c_float, C.c_float, P, P, P]
+        L.suco_mlp_free.argtypes = [P]
+        L.suco_query_features.argtypes = [P, P, i64, P, P]
+        L.suco_query_learned.argtypes = [P, P, P, i64, i32, dbl, C.c_float, C.c_float, C.c_float, P, P, P, P]
+        L.suco_batcher_set_model.argtypes = [P, P, C.c_float, C.c_float, C.c_float]
         _lib = L
     return _lib
 
@@ -280,6 +295,12 @@ class Batcher:
                                         _dev(dists, torch.float32), _stream(stream)))
         return ids, dists
 
+    def set_model(self, mlp, scale: float = 1.0, alpha_min: float = 1e-4, alpha_max: float = 1.0):
+        """Compute each batch's alphas with `mlp` inside the graph (None detaches)."""
+        self._model = mlp
+        _check(lib().suco_batcher_set_model(self._h, mlp._h if mlp is not None else None, float(scale),
+                                            float(alpha_min), float(alpha_max)))
+
     def tuning(self, bucket: int):
         prm = np.zeros(3, np.int32)
         ms = C.c_double()
@@ -298,3 +319,104 @@ class Batcher:
                 _lib.suco_batcher_free(self._h)
         except Exception:
             pass
+
+
+class MLP:
+    """The learned activation-budget network (see suco_mlp_create)."""
+
+    HIDDEN = 128
+
+    def __init__(self, n_in: int, params: np.ndarray | None = None, seed: int = 1):
+        self.n_in = n_in
+        self.num_params = int(lib().suco_mlp_num_params(n_in, self.HIDDEN))
+        if self.num_params < 0:
+            raise ValueError("unsupported network shape")
+        h = C.c_void_p()
+        pp = None
+        if params is not None:
+            params = np.ascontiguousarray(params, np.float32).reshape(-1)
+            if params.size != self.num_params:
+                raise ValueError(f"expected {self.num_params} parameters")
+            pp = params.ctypes.data_as(P)
+        _check(lib().suco_mlp_create(n_in, self.HIDDEN, pp, C.c_uint64(seed), C.byref(h)))
+        self._h = h
+
+    def set_norm(self, mu, sigma):
+        mu = np.ascontiguousarray(mu, np.float32)
+        sigma = np.ascontiguousarray(sigma, np.float32)
+        _check(lib().suco_mlp_set_norm(self._h, mu.ctypes.data_as(P), sigma.ctypes.data_as(P)))
+        self.mu, self.sigma = mu, sigma
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, np.float32)
+        _check(lib().suco_mlp_get_params(self._h, out.ctypes.data_as(P)))
+        return out
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, np.float32).reshape(-1)
+        _check(lib().suco_mlp_set_params(self._h, params.ctypes.data_as(P)))
+
+    def forward_backward(self, F, t, stream=None):
+        """(loss, gradient) on the GPU in FP32 for rows F [m, n_in] and targets t [m]."""
+        torch = _torch()
+        m = F.shape[0]
+        g = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().suco_mlp_forward_backward(self._h, _dev(F, torch.float32, (m, self.n_in), "F"),
+                                               _dev(t, torch.float32, (m,), "t"), m, _opt(loss), _opt(g),
+                                               _stream(stream)))
+        return loss, g
+
+    def train_epoch(self, F, t, batch: int, lr: float, order=None, want_loss=True, stream=None) -> float:
+        torch = _torch()
+        m = F.shape[0]
+        po = _dev(order, torch.int32, (m,), "order") if order is not None else None
+        ml = C.c_float(0.0)
+        _check(lib().suco_mlp_train_epoch(self._h, _dev(F, torch.float32, (m, self.n_in), "F"),
+                                          _dev(t, torch.float32, (m,), "t"), m, int(batch), float(lr), po,
+                                          C.byref(ml) if want_loss else None, _stream(stream)))
+        return float(ml.value)
+
+    def predict(self, F, scale: float = 1.0, alpha_min: float = 1e-4, alpha_max: float = 1.0, stream=None):
+        """BF16 inference: (y = predicted log alpha, alpha)."""
+        torch = _torch()
+        m = F.shape[0]
+        y = torch.empty(m, dtype=torch.float32, device="cuda")
+        a = torch.empty(m, dtype=torch.float32, device="cuda")
+        _check(lib().suco_mlp_predict(self._h, _dev(F, torch.float32, (m, self.n_in), "F"), m, float(scale),
+                                      float(alpha_min), float(alpha_max), _opt(y), _opt(a), _stream(stream)))
+        return y, a
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().suco_mlp_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if _lib is not None and getattr(self, "_h", None) is not None and self._h.value:
+                _lib.suco_mlp_free(self._h)
+        except Exception:
+            pass
+
+
+def query_features(index: Index, Q, stream=None):
+    torch = _torch()
+    nq = Q.shape[0]
+    F = torch.empty((nq, 2 * index.ns + 1), dtype=torch.float32, device="cuda")
+    _check(lib().suco_query_features(index._h, _dev(Q, torch.float32, (nq, index.d), "Q"), nq, _opt(F),
+                                     _stream(stream)))
+    return F
+
+
+def query_learned(index: Index, mlp: MLP, Q, k: int, beta: float, scale: float, alpha_min: float = 1e-4,
+                  alpha_max: float = 1.0, out=None, stream=None):
+    """k-ANN query with per-query alphas from `mlp`: returns (ids, dists, alpha_used)."""
+    torch = _torch()
+    nq = Q.shape[0]
+    ids, dists = out if out is not None else index._out(nq, k)
+    au = torch.empty(nq, dtype=torch.float32, device="cuda")
+    _check(lib().suco_query_learned(index._h, mlp._h, _dev(Q, torch.float32, (nq, index.d), "Q"), nq, k,
+                                    float(beta), float(scale), float(alpha_min), float(alpha_max),
+                                    _dev(ids, torch.int32), _dev(dists, torch.float32), _opt(au), _stream(stream)))
+    return ids, dists, au

@@ -76,6 +76,8 @@ struct Bucket {
     hipGraphExec_t exec = nullptr;
     std::vector<QueryPass> qps;
     std::vector<RerankPass> rps;
+    FeatPass fp{};
+    InferPass ip{};
     void destroy() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -108,6 +110,10 @@ struct suco_batcher {
     uint32_t *hist = nullptr, *cand = nullptr;
     uint64_t *part_keys = nullptr;
     std::map<int, Bucket> buckets;
+    // attached model: features and alphas computed inside the graph
+    suco_mlp *model = nullptr;
+    float scale = 1.f, amin = 0.f, amax = 1.f;
+    float *Fs = nullptr;
     std::string tune_path;
     std::map<std::string, Tuned> tune_cache;
     std::mutex mu;
@@ -118,6 +124,8 @@ struct suco_batcher {
         if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
         for (auto &kv : buckets) kv.second.destroy();
         buckets.clear();
+        if (Fs) (void)hipFree(Fs);
+        Fs = nullptr;
         for (void *p : {(void *)Qs, (void *)alphas, (void *)ids_s, (void *)dists_s, (void *)mail, (void *)nq_dev,
                         (void *)cells, (void *)lvl, (void *)ncells, (void *)aprime, (void *)hist, (void *)cand,
                         (void *)part_keys})
@@ -137,7 +145,8 @@ std::string tune_key(const suco_batcher *b, int bucket) {
     const suco_index *ix = b->ix;
     std::ostringstream os;
     os << "gfx950 n=" << ix->n << " d=" << ix->d << " ns=" << ix->ns << " sk=" << ix->sk << " P=" << ix->P
-       << " TILE=" << ix->TILE << " B=" << b->B << " k=" << b->k << " C=" << b->C << " bucket=" << bucket;
+       << " TILE=" << ix->TILE << " B=" << b->B << " k=" << b->k << " C=" << b->C << " bucket=" << bucket
+       << (b->model ? " learned" : "");
     return os.str();
 }
 
@@ -188,6 +197,28 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         void *args[] = {&b->mail, &b->Qs, &b->alphas, &b->nq_dev, &b->d4};
         e = add_node(bk->graph, &prev, reinterpret_cast<const void *>(&k_stage_in), dim3(256), dim3(256), 0, args);
         if (e != hipSuccess) return e;
+    }
+    if (b->model) {
+        bk->fp = FeatPass{};
+        bk->fp.ix = ix->view();
+        bk->fp.Q = b->Qs;
+        bk->fp.nq = bk->size;
+        bk->fp.nq_dev = b->nq_dev;
+        bk->fp.F = b->Fs;
+        bk->ip = InferPass{};
+        bk->ip.w = mlp_infer_view(b->model);
+        bk->ip.F = b->Fs;
+        bk->ip.m = bk->size;
+        bk->ip.m_dev = b->nq_dev;
+        bk->ip.scale = b->scale;
+        bk->ip.amin = b->amin;
+        bk->ip.amax = b->amax;
+        bk->ip.alpha64 = b->alphas;
+        const Launch Lf = plan_features(bk->size), Li = plan_mlp_infer(bk->size);
+        void *af[] = {&bk->fp};
+        void *ai[] = {&bk->ip};
+        if ((e = add_node(bk->graph, &prev, Lf.func, Lf.grid, Lf.block, Lf.lds, af)) != hipSuccess) return e;
+        if ((e = add_node(bk->graph, &prev, Li.func, Li.grid, Li.block, Li.lds, ai)) != hipSuccess) return e;
     }
     const int passes = (bk->size + b->C - 1) / b->C;
     const int C = std::min(b->C, bk->size);
@@ -319,12 +350,19 @@ int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float 
     if (!batcher_ok(b)) return fail(SUCO_E_STATE, "invalid or freed batcher handle");
     if (!index_ok(b->ix)) return fail(SUCO_E_STATE, "the batcher's index was freed");
     if (nq < 0 || nq > b->maxb) return fail(SUCO_E_INVAL, "nq must be in [0, max_batch]");
-    if (!alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (!b->model && !alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (b->model && alpha_q) return fail(SUCO_E_INVAL, "a batcher with a model takes no alpha_q");
+    if (b->model && !mlp_valid(b->model)) return fail(SUCO_E_STATE, "the batcher's model was freed");
     if (nq > 0 && (!Q || !ids || !dists)) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
     if (nq == 0) return SUCO_OK;
     hipStream_t st = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(b->mu);
     DeviceGuard dg(b->device);
+    if (b->model) {
+        const int rc = mlp_prepare(b->model, st);
+        if (rc) return rc;
+        alpha = 1.0;
+    }
     if (b->pending) HIPCHECK(hipStreamWaitEvent(st, b->done, 0));
     Mail m{};
     m.nq = (int)nq;
@@ -352,6 +390,29 @@ int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float 
     HIPCHECK(hipGraphLaunch(bk.exec, st));
     HIPCHECK(hipEventRecord(b->done, st));
     b->pending = true;
+    return SUCO_OK;
+}
+
+int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, float alpha_min, float alpha_max) {
+    if (!batcher_ok(b)) return fail(SUCO_E_STATE, "invalid or freed batcher handle");
+    if (m && !mlp_valid(m)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (m && mlp_n_in(m) != 2 * b->ix->ns + 1) return fail(SUCO_E_INVAL, "the model's n_in must be 2*n_s + 1");
+    if (m && !(scale > 0.f)) return fail(SUCO_E_INVAL, "scale must be positive");
+    if (m && !(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))
+        return fail(SUCO_E_INVAL, "need 0 < alpha_min <= alpha_max <= 1");
+    std::lock_guard<std::mutex> lock(b->mu);
+    DeviceGuard dg(b->device);
+    if (b->pending) HIPCHECK(hipEventSynchronize(b->done));
+    if (m && !b->Fs) {
+        const int rc = dev_alloc(&b->Fs, (size_t)b->maxb * (2 * b->ix->ns + 1));
+        if (rc) return rc;
+    }
+    b->model = m;
+    b->scale = scale;
+    b->amin = alpha_min;
+    b->amax = alpha_max;
+    // graphs are rebuilt on next use (tuned shapes are kept)
+    for (auto &kv : b->buckets) kv.second.destroy();
     return SUCO_OK;
 }
 

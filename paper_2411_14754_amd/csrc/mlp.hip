@@ -1,0 +1,589 @@
+// Learned activation budget: a small MLP that predicts a per-query collision
+// ratio alpha from cheap query features.
+//
+// Features (2*ns + 1 per query): for every subspace half, the Euclidean
+// distance from the query half to its nearest centre (the square root of the
+// smallest step-1 distance, computed with the activation step's arithmetic),
+// and the query norm.
+//
+// Network: x = (f - mu) / sigma; h1 = GELU(W1 x + b1); h2 = GELU(W2 h1 + b2);
+// y = W3 h2 + b3, y predicting log alpha; GELU(x) = x * Phi(x) (Hendrycks and
+// Gimpel 2016), Phi from erff.  Parameters in one flat FP32 array in the order
+// W1 [H][n_in], b1 [H], W2 [H][H], b2 [H], W3 [H], b3 [1].
+//
+// Training (FP32): per row, a block computes the forward pass and the row's
+// back-propagated pre-activation gradients; a second kernel forms the
+// parameter gradients as sums over the rows in row order (deterministic); a
+// third applies Adam (Kingma and Ba 2015, with bias correction).  Loss is the
+// mean squared error over the batch.
+//
+// Inference (BF16): weights and layer inputs are rounded to BF16 (nearest,
+// ties to even) and products are accumulated in FP32 in index order; the
+// collision ratio is alpha = clamp(scale * exp(y), alpha_min, alpha_max).
+#include "runtime_impl.h"
+
+namespace suco {
+
+constexpr int kH = 128;        // hidden width supported by the kernels
+constexpr int kMaxIn = 255;    // 2*ns + 1 for ns <= 127
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// Round to the nearest BF16 value (ties to even), returned as FP32.
+__device__ __forceinline__ float bf16r(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;   // inf / nan unchanged
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// ------------------------------------------------------------- features --
+__global__ __launch_bounds__(128) void k_features(FeatPass fp) {
+    __shared__ float mins[2 * kMaxNs];
+    const IndexView ix = fp.ix;
+    const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
+    const int sk = ix.sk, nh = 2 * ix.ns;
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const float *qv = fp.Q + (int64_t)q * ix.d;
+        for (int g = threadIdx.x; g < nh; g += blockDim.x) {
+            const HalfDims hd = ix.halves[g];
+            const float *qp = qv + hd.dim0;
+            float best = 0.f;
+            for (int c = 0; c < sk; ++c) {
+                const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
+                float s = 0.f;
+                for (int j = 0; j < hd.w; ++j) {
+                    const float t2 = qp[j] - cp[j];
+                    s = fmaf(t2, t2, s);
+                }
+                best = (c == 0 || s < best) ? s : best;
+            }
+            mins[g] = __fsqrt_rn(best);
+        }
+        __syncthreads();
+        float *out = fp.F + (int64_t)q * (nh + 1);
+        for (int g = threadIdx.x; g < nh; g += blockDim.x) out[g] = mins[g];
+        if (threadIdx.x == 0) {
+            float s = 0.f;
+            for (int j = 0; j < ix.d; ++j) s = fmaf(qv[j], qv[j], s);
+            out[nh] = __fsqrt_rn(s);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------- inference --
+// Block of H threads per row; weights are pre-rounded BF16 values in FP32.
+__global__ __launch_bounds__(kH) void k_mlp_infer(InferPass ip) {
+    __shared__ float x[kMaxIn + 1];
+    __shared__ float h[kH];
+    __shared__ float red[kH / kWave];
+    const MlpView w = ip.w;
+    const int j = threadIdx.x;
+    const int m = ip.m_dev ? *ip.m_dev : ip.m;
+    for (int r = blockIdx.x; r < m; r += gridDim.x) {
+        for (int i = j; i < w.n_in; i += kH) x[i] = bf16r((ip.F[(int64_t)r * w.n_in + i] - w.mu[i]) / w.sigma[i]);
+        __syncthreads();
+        float z = w.b1[j];
+        for (int i = 0; i < w.n_in; ++i) z = fmaf(w.W1[j * w.n_in + i], x[i], z);
+        h[j] = bf16r(gelu_f(z));
+        __syncthreads();
+        float z2 = w.b2[j];
+        for (int i = 0; i < kH; ++i) z2 = fmaf(w.W2[j * kH + i], h[i], z2);
+        const float h2 = bf16r(gelu_f(z2));
+        float part = w.W3[j] * h2;
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+        if ((j & (kWave - 1)) == 0) red[j / kWave] = part;
+        __syncthreads();
+        if (j == 0) {
+            const float yv = w.b3[0] + red[0] + red[1];
+            if (ip.y) ip.y[r] = yv;
+            float a = ip.scale * expf(yv);
+            a = a < ip.amin ? ip.amin : (a > ip.amax ? ip.amax : a);
+            if (ip.alpha) ip.alpha[r] = a;
+            if (ip.alpha64) ip.alpha64[r] = (double)a;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ training --
+struct TrainRows {
+    MlpView w;
+    const float *F, *t;
+    const int32_t *order;   // row permutation or null
+    int m;                  // rows in this batch
+    int64_t row0;           // first position in `order` (or in F) of this batch
+    float *xs, *z1, *h1, *z2, *h2, *dz1, *dz2, *dy, *sq;   // per-row workspaces
+};
+
+// One block of H threads per row: forward pass, squared error, and the row's
+// gradients with respect to the pre-activations of both hidden layers.
+__global__ __launch_bounds__(kH) void k_mlp_rows(TrainRows a) {
+    __shared__ float x[kMaxIn + 1];
+    __shared__ float h[kH];
+    __shared__ float d2[kH];
+    __shared__ float red[kH / kWave];
+    const int j = threadIdx.x, r = blockIdx.x, n_in = a.w.n_in;
+    const int64_t pos = a.row0 + r;
+    const int64_t src = a.order ? a.order[pos] : pos;
+    for (int i = j; i < n_in; i += kH) {
+        const float v = (a.F[src * n_in + i] - a.w.mu[i]) / a.w.sigma[i];
+        x[i] = v;
+        a.xs[(int64_t)r * n_in + i] = v;
+    }
+    __syncthreads();
+    float z = a.w.b1[j];
+    for (int i = 0; i < n_in; ++i) z = fmaf(a.w.W1[j * n_in + i], x[i], z);
+    const float g1 = gelu_f(z);
+    a.z1[(int64_t)r * kH + j] = z;
+    a.h1[(int64_t)r * kH + j] = g1;
+    h[j] = g1;
+    __syncthreads();
+    float z2 = a.w.b2[j];
+    for (int i = 0; i < kH; ++i) z2 = fmaf(a.w.W2[j * kH + i], h[i], z2);
+    const float g2 = gelu_f(z2);
+    a.z2[(int64_t)r * kH + j] = z2;
+    a.h2[(int64_t)r * kH + j] = g2;
+    float part = a.w.W3[j] * g2;
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    if ((j & (kWave - 1)) == 0) red[j / kWave] = part;
+    __syncthreads();
+    const float y = a.w.b3[0] + red[0] + red[1];
+    const float e = y - a.t[src];
+    const float dy = 2.0f * e / (float)a.m;
+    if (j == 0) {
+        a.dy[r] = dy;
+        a.sq[r] = e * e;
+    }
+    const float dz2 = dy * a.w.W3[j] * gelu_grad_f(z2);
+    a.dz2[(int64_t)r * kH + j] = dz2;
+    d2[j] = dz2;
+    __syncthreads();
+    float dh1 = 0.f;
+    for (int o = 0; o < kH; ++o) dh1 = fmaf(a.w.W2[o * kH + j], d2[o], dh1);
+    a.dz1[(int64_t)r * kH + j] = dh1 * gelu_grad_f(z);
+}
+
+// Parameter gradients: one thread per parameter, summing over the rows in order.
+__global__ __launch_bounds__(256) void k_mlp_grads(TrainRows a, float *g, float *loss) {
+    const int n_in = a.w.n_in;
+    const int64_t nW1 = (int64_t)kH * n_in, nW2 = (int64_t)kH * kH;
+    const int64_t total = nW1 + kH + nW2 + kH + kH + 1;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == total && loss) {
+        float s = 0.f;
+        for (int r = 0; r < a.m; ++r) s += a.sq[r];
+        *loss = s / (float)a.m;
+    }
+    if (p >= total) return;
+    float s = 0.f;
+    if (p < nW1) {                                   // dW1[j][i] = sum_r dz1[r][j] x[r][i]
+        const int jj = (int)(p / n_in), i = (int)(p % n_in);
+        for (int r = 0; r < a.m; ++r) s = fmaf(a.dz1[(int64_t)r * kH + jj], a.xs[(int64_t)r * n_in + i], s);
+    } else if (p < nW1 + kH) {                       // db1
+        const int jj = (int)(p - nW1);
+        for (int r = 0; r < a.m; ++r) s += a.dz1[(int64_t)r * kH + jj];
+    } else if (p < nW1 + kH + nW2) {                 // dW2[j][i] = sum_r dz2[r][j] h1[r][i]
+        const int64_t q = p - nW1 - kH;
+        const int jj = (int)(q / kH), i = (int)(q % kH);
+        for (int r = 0; r < a.m; ++r) s = fmaf(a.dz2[(int64_t)r * kH + jj], a.h1[(int64_t)r * kH + i], s);
+    } else if (p < nW1 + kH + nW2 + kH) {            // db2
+        const int jj = (int)(p - nW1 - kH - nW2);
+        for (int r = 0; r < a.m; ++r) s += a.dz2[(int64_t)r * kH + jj];
+    } else if (p < total - 1) {                      // dW3[j] = sum_r dy[r] h2[r][j]
+        const int jj = (int)(p - nW1 - kH - nW2 - kH);
+        for (int r = 0; r < a.m; ++r) s = fmaf(a.dy[r], a.h2[(int64_t)r * kH + jj], s);
+    } else {                                         // db3
+        for (int r = 0; r < a.m; ++r) s += a.dy[r];
+    }
+    g[p] = s;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *w, const float *g, float *m1, float *m2, int64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float gp = g[p];
+    const float a = b1 * m1[p] + (1.0f - b1) * gp;
+    const float v = b2 * m2[p] + (1.0f - b2) * gp * gp;
+    m1[p] = a;
+    m2[p] = v;
+    w[p] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+__global__ void k_round_bf16(const float *src, float *dst, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) dst[p] = bf16r(src[p]);
+}
+
+}  // namespace suco
+
+using namespace suco;
+
+struct suco_mlp {
+    uint64_t magic = 0x5375436f4d4c5031ULL;
+    int device = 0, n_in = 0, H = kH;
+    int64_t np = 0;
+    float *w = nullptr, *wb = nullptr;       // FP32 parameters, BF16-rounded copy for inference
+    float *m1 = nullptr, *m2 = nullptr, *g = nullptr;
+    float *mu = nullptr, *sigma = nullptr;
+    float *loss = nullptr;
+    int64_t steps = 0;
+    bool wb_valid = false;
+    // training workspace (rows)
+    int rows_cap = 0;
+    float *ws = nullptr;
+    std::mutex mu_lock;
+
+    MlpView view(const float *params) const {
+        MlpView v;
+        v.n_in = n_in; v.H = H;
+        v.W1 = params;
+        v.b1 = v.W1 + (int64_t)H * n_in;
+        v.W2 = v.b1 + H;
+        v.b2 = v.W2 + (int64_t)H * H;
+        v.W3 = v.b2 + H;
+        v.b3 = v.W3 + H;
+        v.mu = mu; v.sigma = sigma;
+        return v;
+    }
+    void release() {
+        for (void *p : {(void *)w, (void *)wb, (void *)m1, (void *)m2, (void *)g, (void *)mu, (void *)sigma,
+                        (void *)loss, (void *)ws})
+            if (p) (void)hipFree(p);
+        w = wb = m1 = m2 = g = mu = sigma = loss = ws = nullptr;
+        magic = 0;
+    }
+};
+
+namespace {
+
+bool mlp_ok(const suco_mlp *p) { return p != nullptr && p->magic == 0x5375436f4d4c5031ULL; }
+
+int64_t nparams(int n_in, int H) { return (int64_t)H * n_in + H + (int64_t)H * H + H + H + 1; }
+
+int ensure_rows(suco_mlp *p, int rows) {
+    if (rows <= p->rows_cap) return SUCO_OK;
+    if (p->ws) (void)hipFree(p->ws);
+    p->ws = nullptr;
+    p->rows_cap = 0;
+    const size_t per = (size_t)p->n_in + 6 * kH + 2;
+    int rc = dev_alloc(&p->ws, per * rows);
+    if (rc) return rc;
+    p->rows_cap = rows;
+    return SUCO_OK;
+}
+
+TrainRows rows_args(suco_mlp *p, const float *F, const float *t, const int32_t *order, int m, int64_t row0) {
+    TrainRows a{};
+    a.w = p->view(p->w);
+    a.F = F; a.t = t; a.order = order; a.m = m; a.row0 = row0;
+    float *q = p->ws;
+    const int cap = p->rows_cap;
+    a.xs = q; q += (size_t)cap * p->n_in;
+    a.z1 = q; q += (size_t)cap * kH;
+    a.h1 = q; q += (size_t)cap * kH;
+    a.z2 = q; q += (size_t)cap * kH;
+    a.h2 = q; q += (size_t)cap * kH;
+    a.dz1 = q; q += (size_t)cap * kH;
+    a.dz2 = q; q += (size_t)cap * kH;
+    a.dy = q; q += cap;
+    a.sq = q;
+    return a;
+}
+
+hipError_t grads_pass(suco_mlp *p, const TrainRows &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_rows, dim3((unsigned)a.m), dim3(kH), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t tot = p->np + 1;
+    hipLaunchKernelGGL(k_mlp_grads, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, p->g, p->loss);
+    return hipGetLastError();
+}
+
+int refresh_bf16(suco_mlp *p, hipStream_t st) {
+    if (p->wb_valid) return SUCO_OK;
+    hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, st, p->w, p->wb, p->np);
+    HIPCHECK(hipGetLastError());
+    p->wb_valid = true;
+    return SUCO_OK;
+}
+
+}  // namespace
+
+namespace suco {
+Launch plan_features(int nq_cap) {
+    Launch L;
+    L.func = reinterpret_cast<const void *>(&k_features);
+    L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 65536)));
+    L.block = dim3(128);
+    return L;
+}
+
+Launch plan_mlp_infer(int m_cap) {
+    Launch L;
+    L.func = reinterpret_cast<const void *>(&k_mlp_infer);
+    L.grid = dim3((unsigned)std::max(1, std::min(m_cap, 65536)));
+    L.block = dim3(kH);
+    return L;
+}
+
+MlpView mlp_infer_view(suco_mlp *p) { return p->view(p->wb); }
+int mlp_n_in(const suco_mlp *p) { return p->n_in; }
+int mlp_prepare(suco_mlp *p, hipStream_t st) { return refresh_bf16(p, st); }
+bool mlp_valid(const suco_mlp *p) { return mlp_ok(p); }
+}  // namespace suco
+
+extern "C" {
+
+int64_t suco_mlp_num_params(int32_t n_in, int32_t hidden) {
+    return (n_in < 1 || hidden != kH) ? -1 : nparams(n_in, hidden);
+}
+
+int suco_mlp_create(int32_t n_in, int32_t hidden, const float *params, uint64_t seed, suco_mlp **out) {
+    if (!out) return fail(SUCO_E_INVAL, "out must not be NULL");
+    if (n_in < 1 || n_in > kMaxIn) return fail(SUCO_E_INVAL, "n_in must be in [1, 255]");
+    if (hidden != kH) return fail(SUCO_E_UNSUPPORTED, "the kernels support hidden = 128");
+    suco_mlp *p = new (std::nothrow) suco_mlp();
+    if (!p) return fail(SUCO_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(SUCO_E_HIP, "no device"); }
+    p->n_in = n_in;
+    p->np = nparams(n_in, kH);
+    int rc;
+    if ((rc = dev_alloc(&p->w, p->np)) || (rc = dev_alloc(&p->wb, p->np)) || (rc = dev_alloc(&p->m1, p->np)) ||
+        (rc = dev_alloc(&p->m2, p->np)) || (rc = dev_alloc(&p->g, p->np)) || (rc = dev_alloc(&p->mu, n_in)) ||
+        (rc = dev_alloc(&p->sigma, n_in)) || (rc = dev_alloc(&p->loss, 1))) {
+        p->release();
+        delete p;
+        return rc;
+    }
+    std::vector<float> h((size_t)p->np, 0.f);
+    if (params) {
+        std::memcpy(h.data(), params, sizeof(float) * p->np);
+    } else {
+        // uniform in +-sqrt(3 / fan_in) from SplitMix64 draws; biases zero
+        const int64_t segs[3][2] = {{0, (int64_t)kH * n_in}, {(int64_t)kH * n_in + kH, (int64_t)kH * kH},
+                                    {(int64_t)kH * n_in + kH + (int64_t)kH * kH + kH, kH}};
+        const int fan[3] = {n_in, kH, kH};
+        uint64_t m = 0;
+        for (int s = 0; s < 3; ++s) {
+            const double bound = std::sqrt(3.0 / fan[s]);
+            for (int64_t t = 0; t < segs[s][1]; ++t) {
+                const double u = (double)(splitmix64_at(seed, m++) >> 11) * (1.0 / 9007199254740992.0);
+                h[segs[s][0] + t] = (float)((2.0 * u - 1.0) * bound);
+            }
+        }
+    }
+    std::vector<float> zeros((size_t)p->np, 0.f), ones((size_t)n_in, 1.f), zin((size_t)n_in, 0.f);
+    hipError_t e = hipMemcpy(p->w, h.data(), sizeof(float) * p->np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->m1, zeros.data(), sizeof(float) * p->np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->m2, zeros.data(), sizeof(float) * p->np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->mu, zin.data(), sizeof(float) * n_in, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->sigma, ones.data(), sizeof(float) * n_in, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        p->release();
+        delete p;
+        return fail(SUCO_E_HIP, std::string("mlp upload: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return SUCO_OK;
+}
+
+int suco_mlp_set_norm(suco_mlp *p, const float *mu, const float *sigma) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (!mu || !sigma) return fail(SUCO_E_INVAL, "mu and sigma must not be NULL");
+    for (int i = 0; i < p->n_in; ++i)
+        if (!(sigma[i] > 0.f)) return fail(SUCO_E_INVAL, "sigma must be positive");
+    std::lock_guard<std::mutex> lock(p->mu_lock);
+    DeviceGuard dg(p->device);
+    HIPCHECK(hipMemcpy(p->mu, mu, sizeof(float) * p->n_in, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(p->sigma, sigma, sizeof(float) * p->n_in, hipMemcpyHostToDevice));
+    return SUCO_OK;
+}
+
+int suco_mlp_get_params(const suco_mlp *p, float *params) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (!params) return fail(SUCO_E_INVAL, "params must not be NULL");
+    DeviceGuard dg(p->device);
+    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipMemcpy(params, p->w, sizeof(float) * p->np, hipMemcpyDeviceToHost));
+    return SUCO_OK;
+}
+
+int suco_mlp_set_params(suco_mlp *p, const float *params) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (!params) return fail(SUCO_E_INVAL, "params must not be NULL");
+    std::lock_guard<std::mutex> lock(p->mu_lock);
+    DeviceGuard dg(p->device);
+    HIPCHECK(hipMemcpy(p->w, params, sizeof(float) * p->np, hipMemcpyHostToDevice));
+    p->wb_valid = false;
+    return SUCO_OK;
+}
+
+int suco_mlp_forward_backward(suco_mlp *p, const float *F, const float *t, int64_t m, float *loss, float *grads,
+                              void *stream) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (m < 1 || m > (1 << 20)) return fail(SUCO_E_INVAL, "m must be in [1, 2^20]");
+    if (!F || !t || !grads) return fail(SUCO_E_INVAL, "F, t and grads must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(p->mu_lock);
+    DeviceGuard dg(p->device);
+    int rc = ensure_rows(p, (int)m);
+    if (rc) return rc;
+    const TrainRows a = rows_args(p, F, t, nullptr, (int)m, 0);
+    HIPCHECK(grads_pass(p, a, st));
+    HIPCHECK(hipMemcpyAsync(grads, p->g, sizeof(float) * p->np, hipMemcpyDeviceToDevice, st));
+    if (loss) HIPCHECK(hipMemcpyAsync(loss, p->loss, sizeof(float), hipMemcpyDeviceToDevice, st));
+    return SUCO_OK;
+}
+
+int suco_mlp_train_epoch(suco_mlp *p, const float *F, const float *t, int64_t m, int32_t batch, float lr,
+                         const int32_t *order, float *mean_loss, void *stream) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (m < 1 || batch < 1 || batch > 65536) return fail(SUCO_E_INVAL, "m >= 1 and batch in [1, 65536]");
+    if (!(lr > 0.f)) return fail(SUCO_E_INVAL, "lr must be positive");
+    if (!F || !t) return fail(SUCO_E_INVAL, "F and t must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(p->mu_lock);
+    DeviceGuard dg(p->device);
+    int rc = ensure_rows(p, batch);
+    if (rc) return rc;
+    double lsum = 0.0;
+    int64_t nb = 0;
+    for (int64_t r0 = 0; r0 < m; r0 += batch) {
+        const int mb = (int)std::min<int64_t>(batch, m - r0);
+        const TrainRows a = rows_args(p, F, t, order, mb, r0);
+        HIPCHECK(grads_pass(p, a, st));
+        ++p->steps;
+        const float c1 = 1.0f - std::pow(0.9f, (float)p->steps), c2 = 1.0f - std::pow(0.999f, (float)p->steps);
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, st, p->w, p->g, p->m1,
+                           p->m2, p->np, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+        HIPCHECK(hipGetLastError());
+        if (mean_loss) {
+            float l = 0.f;
+            HIPCHECK(hipMemcpyAsync(&l, p->loss, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            lsum += (double)l * mb;
+        }
+        ++nb;
+    }
+    p->wb_valid = false;
+    if (mean_loss) *mean_loss = (float)(lsum / (double)m);
+    return SUCO_OK;
+}
+
+int suco_mlp_predict(suco_mlp *p, const float *F, int64_t m, float scale, float alpha_min, float alpha_max,
+                     float *y, float *alpha, void *stream) {
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (m < 0 || (m > 0 && !F)) return fail(SUCO_E_INVAL, "F must not be NULL");
+    if (!(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))
+        return fail(SUCO_E_INVAL, "need 0 < alpha_min <= alpha_max <= 1");
+    if (m == 0) return SUCO_OK;
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(p->mu_lock);
+    DeviceGuard dg(p->device);
+    int rc = refresh_bf16(p, st);
+    if (rc) return rc;
+    InferPass ip{};
+    ip.w = p->view(p->wb);
+    ip.F = F; ip.m = (int)m; ip.scale = scale; ip.amin = alpha_min; ip.amax = alpha_max; ip.y = y; ip.alpha = alpha;
+    HIPCHECK(launch(plan_mlp_infer((int)m), &ip, st));
+    return SUCO_OK;
+}
+
+int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float *F, void *stream) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (nq < 0 || (nq > 0 && (!Q || !F))) return fail(SUCO_E_INVAL, "Q and F must not be NULL");
+    if (nq == 0) return SUCO_OK;
+    DeviceGuard dg(ix->device);
+    for (int64_t q0 = 0; q0 < nq; q0 += 65536) {
+        const int cn = (int)std::min<int64_t>(65536, nq - q0);
+        FeatPass fp{};
+        fp.ix = ix->view(); fp.Q = Q + q0 * ix->d; fp.nq = cn; fp.F = F + q0 * (2 * ix->ns + 1);
+        HIPCHECK(launch(plan_features(cn), &fp, (hipStream_t)stream));
+    }
+    return SUCO_OK;
+}
+
+int suco_mlp_free(suco_mlp *p) {
+    if (!p) return SUCO_OK;
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    {
+        DeviceGuard dg(p->device);
+        (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lock(p->mu_lock);
+        p->release();
+    }
+    delete p;
+    return SUCO_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ learned query --
+namespace {
+struct LearnedBufs {
+    float *F = nullptr, *alpha = nullptr;
+    int64_t cap = 0;
+};
+}  // namespace
+
+struct suco_learned_state {
+    std::mutex mu;
+    LearnedBufs b;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+namespace {
+suco_learned_state g_learned_states[1];   // one shared staging area, serialised by its mutex
+}
+
+extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float *Q, int64_t nq, int32_t k,
+                                  double beta, float scale, float alpha_min, float alpha_max, int32_t *ids,
+                                  float *dists, float *alpha_used, void *stream) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (p->n_in != 2 * ix->ns + 1) return fail(SUCO_E_INVAL, "the model's n_in must be 2*n_s + 1");
+    if (!(scale > 0.f)) return fail(SUCO_E_INVAL, "scale must be positive");
+    if (!(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))
+        return fail(SUCO_E_INVAL, "need 0 < alpha_min <= alpha_max <= 1");
+    if (nq < 0 || (nq > 0 && (!Q || !ids || !dists))) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
+    if (k < 1 || k > kMaxK || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, min(64, n)]");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
+    if (nq == 0) return SUCO_OK;
+    hipStream_t st = (hipStream_t)stream;
+    suco_learned_state &S = g_learned_states[0];
+    std::lock_guard<std::mutex> lock(S.mu);
+    DeviceGuard dg(ix->device);
+    if (!S.done) HIPCHECK(hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
+    if (nq * p->n_in > S.b.cap) {
+        if (S.pending) HIPCHECK(hipEventSynchronize(S.done));
+        if (S.b.F) (void)hipFree(S.b.F);
+        if (S.b.alpha) (void)hipFree(S.b.alpha);
+        S.b = LearnedBufs{};
+        int rc;
+        if ((rc = dev_alloc(&S.b.F, (size_t)nq * p->n_in)) || (rc = dev_alloc(&S.b.alpha, (size_t)nq))) {
+            if (S.b.F) (void)hipFree(S.b.F);
+            S.b = LearnedBufs{};
+            return rc;
+        }
+        S.b.cap = nq * p->n_in;
+    }
+    if (S.pending) HIPCHECK(hipStreamWaitEvent(st, S.done, 0));
+    int rc = suco_query_features(ix, Q, nq, S.b.F, stream);
+    if (rc) return rc;
+    rc = suco_mlp_predict(p, S.b.F, nq, scale, alpha_min, alpha_max, nullptr, S.b.alpha, stream);
+    if (rc) return rc;
+    rc = suco_query_alpha(ix, Q, nq, k, S.b.alpha, beta, ids, dists, stream);
+    if (rc) return rc;
+    if (alpha_used) HIPCHECK(hipMemcpyAsync(alpha_used, S.b.alpha, sizeof(float) * nq, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipEventRecord(S.done, st));
+    S.pending = true;
+    return SUCO_OK;
+}

@@ -183,3 +183,13 @@ inline int rerank_cfg(int d, int64_t B, RerankCfg *c) {
 
 
 }  // namespace suco
+
+namespace suco {
+// The learned-budget network, for the batcher's graph (mlp.hip).
+MlpView mlp_infer_view(suco_mlp *p);
+int mlp_n_in(const suco_mlp *p);
+int mlp_prepare(suco_mlp *p, hipStream_t st);
+bool mlp_valid(const suco_mlp *p);
+Launch plan_features(int nq_cap);
+Launch plan_mlp_infer(int m_cap);
+}  // namespace suco

@@ -92,6 +92,32 @@ hipError_t launch_select(const QueryPass &p, hipStream_t s);
 hipError_t launch_rerank(const RerankPass &r, hipStream_t s);
 hipError_t launch_merge(const RerankPass &r, hipStream_t s);
 
+// The learned-budget network (mlp.hip): parameter views and per-pass arguments.
+struct MlpView {
+    int n_in, H;
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    const float *mu, *sigma;
+};
+struct FeatPass {
+    IndexView ix;
+    const float *Q;
+    int nq;
+    const int *nq_dev;        // if set, the number of queries is read here
+    float *F;                 // [nq][2ns+1]
+};
+struct InferPass {
+    MlpView w;                // BF16-rounded weights
+    const float *F;
+    int m;
+    const int *m_dev;         // if set, the number of rows is read here
+    float scale, amin, amax;
+    float *y;                 // [m] log-alpha predictions or null
+    float *alpha;             // [m] or null
+    double *alpha64;          // [m] or null
+};
+Launch plan_features(int nq_cap);
+Launch plan_mlp_infer(int m_cap);
+
 // Launchers (build_kernels.hip)
 struct KmeansPass {
     const float *X;
