@@ -111,6 +111,11 @@ def main():
     ap.add_argument("--tile-max", type=int, default=0, help="largest collision tile (0: library default)")
     ap.add_argument("--query-chunk", type=int, default=0, help="queries per pass (0: library default)")
     ap.add_argument("--alpha", type=float, default=None, help="time this alpha and skip the sweep")
+    ap.add_argument("--plain-only", action="store_true", help="report plain SuCo only (no learned+batched)")
+    ap.add_argument("--train-queries", type=int, default=20_000)
+    ap.add_argument("--val-queries", type=int, default=10_000)
+    ap.add_argument("--epochs", type=int, default=25)
+    ap.add_argument("--target-recall", type=float, default=0.951)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "
                          "scale HBM byte counters) and exit")
@@ -201,20 +206,22 @@ def main():
         "rerank": 4.0 * B * d + 4.0 * B,             # candidate rows + candidate ids
     }
 
-    for _ in range(args.warmup):
-        run(alpha)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        run(alpha)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
-    value = nq * args.steps / (ms / 1e3)
-    rec = recall_at(ids, gt)
-    log(f"timed: {args.steps} steps, {ms_step:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}")
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    ms_plain = timed(lambda: run(alpha), args.steps, args.warmup)
+    plain_value = nq * args.steps / (ms_plain / 1e3)
+    plain_rec = recall_at(ids, gt)
+    log(f"plain timed: {ms_plain / args.steps:.3f} ms/step, {plain_value:.0f} QPS, recall@10={plain_rec:.4f}")
 
     # same steps again with every launch bracketed by HIP events on the query stream
     ix.profile(True)
@@ -223,13 +230,13 @@ def main():
         run(alpha)
     stage = ix.profile_read()
     ix.profile(False)
-    chunk = None
     launches = stage["collide"][1] // args.steps
     chunk = math.ceil(nq / max(1, launches))
     per_kernel = {}
     for s, (tms, cnt) in stage.items():
         avg_ms = tms / max(1, cnt)
-        ent = {"avg_ms": round(avg_ms, 5), "launches": cnt, "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
+        ent = {"avg_ms": round(avg_ms, 5), "launches": cnt,
+               "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
         if s in step_bytes:
             # launches cover `chunk` queries except a ragged last one: use the per-step total
             bytes_launch = step_bytes[s] * nq / max(1, cnt // args.steps)
@@ -241,6 +248,57 @@ def main():
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name)}
+
+    # learned + batched: labels from plain sweeps on training queries, FP32
+    # training, scale calibrated on held-out queries, then the evaluation queries
+    # as a stream of uneven batches through a batcher with the model attached
+    learned_info = None
+    value, ms, rec, form = plain_value, ms_plain, plain_rec, "plain"
+    if not args.plain_only:
+        from paper_2411_14754_amd import learned
+        t0 = time.time()
+        Qt = torch.from_numpy(W.train_queries(args.train_queries + args.val_queries)).cuda()
+        gt_t = exact_topk(Xd, Qt, k)
+        m_tr = args.train_queries
+        grid = learned.alpha_grid(0.0005, 0.05)
+        net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
+        amin, amax = grid[0], grid[-1]
+        scale = learned.calibrate_scale(ix, net, Qt[m_tr:], gt_t[m_tr:], k, beta, args.target_recall, amin, amax)
+        train_s = time.time() - t0
+        log(f"learned budget: trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, "
+            f"scale {scale:.3f}")
+        b = suco.Batcher(ix, 4096, k, beta)
+        b.set_model(net, scale, amin, amax)
+        sizes = W.batch_sizes(nq)
+
+        def stream_pass():
+            s0 = 0
+            for sz in sizes:
+                b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+                s0 += sz
+
+        ms_l = timed(stream_pass, args.steps, max(1, args.warmup))
+        value = nq * args.steps / (ms_l / 1e3)
+        rec = recall_at(ids, gt)
+        _, _, au = suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax)
+        mean_alpha = float(au.double().mean())
+        # plain SuCo at the same recall, interpolated on the sweep
+        plain_eq = None
+        for lo, hi in zip(sweep, sweep[1:]):
+            if lo["recall"] < rec <= hi["recall"]:
+                f = (rec - lo["recall"]) / (hi["recall"] - lo["recall"])
+                plain_eq = math.exp(math.log(lo["qps"]) + f * (math.log(hi["qps"]) - math.log(lo["qps"])))
+        ms, form = ms_l, "learned+batched"
+        log(f"learned+batched: {ms_l / args.steps:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}, "
+            f"mean alpha {mean_alpha:.5f}; plain at that recall {plain_eq}")
+        learned_info = {"train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
+                        "scale": round(scale, 5), "mean_alpha": round(mean_alpha, 6), "train_s": round(train_s, 2),
+                        "batch_sizes": sizes, "plain_qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1),
+                        "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)]}
+        b.free()
+        net.free()
+    ms_step = ms / args.steps
+    log(f"reported: {form}, {value:.0f} QPS, recall@10={rec:.4f}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -261,9 +319,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"sift_like n={n} d={d} int 0..255, N_s={ns}, sqrtK={sk}, nq={nq}, k={k}, "
-                               f"beta={beta}; plain SuCo (learned and batched forms not in this line)",
-                   "form": "plain", "alpha": alpha, "recall_at_10": round(rec, 5),
-                   "qps_at_recall_0.95_interp": None if qps_interp is None else round(qps_interp, 1),
+                               f"beta={beta}",
+                   "form": form, "recall_at_10": round(rec, 5),
+                   "plain": {"alpha": alpha, "qps": round(plain_value, 1), "recall_at_10": round(plain_rec, 5),
+                             "qps_at_recall_0.95_interp": None if qps_interp is None else round(qps_interp, 1)},
+                   "learned": learned_info,
                    "queries_per_pass": chunk, "index_build_s": round(build_s, 3), "sweep": sweep},
         "kernels": per_kernel,
         "roofline": roofline,
