@@ -268,8 +268,17 @@ def main():
         log(f"learned budget: trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, "
             f"scale {scale:.3f}")
         b = suco.Batcher(ix, 4096, k, beta)
-        b.set_model(net, scale, amin, amax)
         sizes = W.batch_sizes(nq)
+
+        def plain_stream():
+            s0 = 0
+            for sz in sizes:
+                b.query(Qd[s0:s0 + sz], alpha=alpha, out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+                s0 += sz
+
+        ms_pb = timed(plain_stream, args.steps, max(1, args.warmup))
+        log(f"plain batched stream: {ms_pb / args.steps:.3f} ms/step, {nq * args.steps / (ms_pb / 1e3):.0f} QPS")
+        b.set_model(net, scale, amin, amax)
 
         def stream_pass():
             s0 = 0
@@ -291,7 +300,8 @@ def main():
         ms, form = ms_l, "learned+batched"
         log(f"learned+batched: {ms_l / args.steps:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}, "
             f"mean alpha {mean_alpha:.5f}; plain at that recall {plain_eq}")
-        learned_info = {"train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
+        learned_info = {"plain_batched_stream_qps": round(nq * args.steps / (ms_pb / 1e3), 1),
+                        "train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
                         "scale": round(scale, 5), "mean_alpha": round(mean_alpha, 6), "train_s": round(train_s, 2),
                         "batch_sizes": sizes, "plain_qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1),
                         "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)]}

@@ -59,7 +59,13 @@ typedef struct suco_build_params {
                            [256, 65536]; 0 means 65536.  Each query's SC-scores are
                            counted tile by tile in on-chip memory.                    */
     int32_t query_chunk;/* queries processed per internal pass; 0 means automatic    */
+    int32_t flags;      /* SUCO_BUILD_* bits                                          */
 } suco_build_params;
+
+/* When every coordinate of D is an integer in 0..255 the index also keeps a
+ * byte copy of D, from which the re-rank reads its rows (they convert to FP32
+ * exactly, so results are unchanged).  This flag keeps FP32 rows only. */
+#define SUCO_BUILD_NO_BYTE_ROWS 1
 
 SUCO_API int suco_version(void);
 SUCO_API const char *suco_last_error(void);

@@ -39,7 +39,10 @@ class SucoError(RuntimeError):
 
 class BuildParams(C.Structure):
     _fields_ = [("iters", C.c_int32), ("seed", C.c_uint64), ("tile_max", C.c_int32),
-                ("query_chunk", C.c_int32)]
+                ("query_chunk", C.c_int32), ("flags", C.c_int32)]
+
+
+BUILD_NO_BYTE_ROWS = 1
 
 
 _lib = None
@@ -144,23 +147,23 @@ class Index:
         self.K = sqrt_k * sqrt_k
 
     @staticmethod
-    def _params(iters, seed, tile_max, query_chunk):
-        return BuildParams(iters, seed, tile_max, query_chunk)
+    def _params(iters, seed, tile_max, query_chunk, flags=0):
+        return BuildParams(iters, seed, tile_max, query_chunk, flags)
 
     @classmethod
     def build(cls, X, n_s: int, sqrt_k: int, iters: int = 25, seed: int = 1, tile_max: int = 0,
-              query_chunk: int = 0, stream=None) -> "Index":
+              query_chunk: int = 0, flags: int = 0, stream=None) -> "Index":
         torch = _torch()
         n, d = X.shape
         px = _dev(X, torch.float32, name="X")
-        prm = cls._params(iters, seed, tile_max, query_chunk)
+        prm = cls._params(iters, seed, tile_max, query_chunk, flags)
         h = C.c_void_p()
         _check(lib().suco_build(px, n, d, n_s, sqrt_k, C.byref(prm), _stream(stream), C.byref(h)))
         return cls(h.value, n, d, n_s, sqrt_k)
 
     @classmethod
     def from_index(cls, X, n_s: int, sqrt_k: int, centroids: np.ndarray, assign: np.ndarray,
-                   tile_max: int = 0, query_chunk: int = 0, stream=None) -> "Index":
+                   tile_max: int = 0, query_chunk: int = 0, flags: int = 0, stream=None) -> "Index":
         torch = _torch()
         n, d = X.shape
         px = _dev(X, torch.float32, name="X")
@@ -168,7 +171,7 @@ class Index:
         asg = np.ascontiguousarray(assign, np.int32).reshape(-1)
         if cent.size != sqrt_k * d or asg.size != 2 * n_s * n:
             raise ValueError("centroids must hold sqrt_k*d values and assign 2*n_s*n values")
-        prm = cls._params(0, 0, tile_max, query_chunk)
+        prm = cls._params(0, 0, tile_max, query_chunk, flags)
         h = C.c_void_p()
         _check(lib().suco_build_from_index(px, n, d, n_s, sqrt_k, cent.ctypes.data_as(P),
                                            asg.ctypes.data_as(P), C.byref(prm), _stream(stream), C.byref(h)))

@@ -239,7 +239,7 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         qp.cells = b->cells; qp.ncells = b->ncells; qp.aprime = b->aprime; qp.hist = b->hist; qp.lvl = b->lvl;
         qp.cand = b->cand;
         RerankPass &rp = bk->rps[c];
-        rp.X = ix->X; rp.Q = qp.Q; rp.cand = b->cand; rp.B = b->B; rp.n = ix->n; rp.d = ix->d; rp.k = b->k;
+        rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = b->cand; rp.B = b->B; rp.n = ix->n; rp.d = ix->d; rp.k = b->k;
         rp.nq = C; rp.parts = parts; rp.nq_dev = b->nq_dev; rp.q_base = c * b->C; rp.rows_per_part = t.rpp;
         rp.G = b->rcfg.G; rp.U = b->rcfg.U; rp.part_keys = b->part_keys;
         rp.ids = b->ids_s + (int64_t)c * b->C * b->k;

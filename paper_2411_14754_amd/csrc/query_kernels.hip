@@ -540,7 +540,11 @@ __device__ __forceinline__ void topk_insert(uint64_t &best, uint64_t kk, int k, 
     }
 }
 
-template <int NT>
+// ROWS8: the rows are read from the index's byte copy of X (kept when every
+// coordinate is an integer in 0..255); each byte converts to FP32 exactly, so
+// the arithmetic, its order and the result are those of the FP32 rows, with a
+// quarter of the bytes moved.
+template <int NT, bool ROWS8>
 __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item) {
     __shared__ uint64_t wl[NT / kWave][kMaxK];
     const int ql = item / r.parts, part = item - ql * r.parts;
@@ -564,12 +568,20 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
         const bool valid = rw < re && id < r.n;   // ids outside [0, n) are ignored
         id = valid ? id : 0u;
         const float4 *xr = reinterpret_cast<const float4 *>(r.X + (int64_t)id * r.d);
+        const uint32_t *xr8 = reinterpret_cast<const uint32_t *>(r.X8 + (int64_t)id * r.d);
         float acc = 0.f;
 #pragma unroll
         for (int u = 0; u < kMaxU; ++u) {
             const int j = li + G * u;
             if (u < r.U && j < d4) {
-                const float4 x = xr[j];
+                float4 x;
+                if constexpr (ROWS8) {
+                    const uint32_t b = xr8[j];
+                    x = make_float4((float)(b & 0xffu), (float)((b >> 8) & 0xffu), (float)((b >> 16) & 0xffu),
+                                    (float)(b >> 24));
+                } else {
+                    x = xr[j];
+                }
                 float t;
                 t = x.x - qr[u].x; acc = fmaf(t, t, acc);
                 t = x.y - qr[u].y; acc = fmaf(t, t, acc);
@@ -595,11 +607,11 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     }
 }
 
-template <int NT>
+template <int NT, bool ROWS8>
 __global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
     const int items = pass_nq(r.nq_dev, r.q_base, r.nq) * r.parts;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        rerank_item<NT>(r, item);
+        rerank_item<NT, ROWS8>(r, item);
         __syncthreads();
     }
 }
@@ -627,6 +639,37 @@ __device__ __forceinline__ void merge_item(const RerankPass &r, const int ql) {
 __global__ __launch_bounds__(kWave) void k_merge(RerankPass r) {
     const int items = pass_nq(r.nq_dev, r.q_base, r.nq);
     for (int item = blockIdx.x; item < items; item += gridDim.x) merge_item(r, item);
+}
+
+// ======================================================== byte rows ==
+// Flags (as 1) any coordinate that is not an integer in 0..255.
+__global__ __launch_bounds__(256) void k_check_bytes(const float *X, int64_t m, int *bad) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const float x = X[t];
+        mine |= !(x >= 0.f && x <= 255.f && x == rintf(x));
+    }
+    if (mine) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && any) atomicOr(bad, 1);
+}
+
+__global__ __launch_bounds__(256) void k_to_bytes(const float *X, int64_t m, uint8_t *X8) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+        X8[t] = (uint8_t)X[t];
+}
+
+hipError_t launch_check_bytes(const float *X, int64_t m, int *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_bytes, dim3(2048), dim3(256), 0, s, X, m, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bytes(const float *X, int64_t m, uint8_t *X8, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bytes, dim3(2048), dim3(256), 0, s, X, m, X8);
+    return hipGetLastError();
 }
 
 // ============================================================= launchers ==
@@ -675,7 +718,8 @@ Launch plan_rerank(const RerankPass &r, int cap) {
     L.lds = 0;
     L.grid = dim3(grid_for((int64_t)r.nq * r.parts, cap));
     L.block = dim3(256);
-    L.func = reinterpret_cast<const void *>(&k_rerank<256>);
+    L.func = r.X8 ? reinterpret_cast<const void *>(&k_rerank<256, true>)
+                  : reinterpret_cast<const void *>(&k_rerank<256, false>);
     return L;
 }
 

@@ -51,6 +51,7 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     if (!ix) return fail(SUCO_E_NOMEM, "host allocation failed");
     ix->device = dev;
     ix->n = n; ix->d = d; ix->ns = ns; ix->sk = sk; ix->K = sk * sk;
+    ix->no_byte_rows = p && (p->flags & SUCO_BUILD_NO_BYTE_ROWS);
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
     const int64_t per = (n + P0 - 1) / P0;
     ix->TILE = (int)((per + 255) / 256 * 256);
@@ -85,9 +86,29 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     return SUCO_OK;
 }
 
+// IMI, then a byte copy of X for the re-rank when every coordinate is an
+// integer in 0..255 (such rows convert back to FP32 exactly).
 int finish_index(suco_index *ix, hipStream_t st) {
     HIPCHECK(launch_imi_build(ix->assign, ix->n, ix->ns, ix->sk, ix->P, ix->TILE, ix->toffs, ix->ids16,
                               ix->csize, st));
+    int *bad = nullptr;
+    int rc = dev_alloc(&bad, 1);
+    if (rc) return rc;
+    int hb = 1;
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), st);
+    const int64_t m = ix->n * ix->d;
+    if (e == hipSuccess) e = launch_check_bytes(ix->X, m, bad, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(SUCO_E_HIP, std::string("byte check: ") + hipGetErrorString(e));
+    if (hb == 0 && ix->d % 4 == 0 && !ix->no_byte_rows) {
+        if (dev_alloc(&ix->X8, (size_t)m) == SUCO_OK) {
+            HIPCHECK(launch_to_bytes(ix->X, m, ix->X8, st));
+        } else {
+            (void)hipGetLastError();   // keep the FP32 rows only
+        }
+    }
     HIPCHECK(hipStreamSynchronize(st));
     return SUCO_OK;
 }
@@ -271,7 +292,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
         RerankPass rp{};
-        rp.X = ix->X; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
+        rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
         rp.parts = rc_cfg.parts; rp.rows_per_part = rc_cfg.rpp; rp.G = rc_cfg.G; rp.U = rc_cfg.U;
         rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
         HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));
@@ -480,7 +501,7 @@ int suco_rerank(const suco_index *cix, const float *Q, int64_t nq, const int32_t
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
         RerankPass rp{};
-        rp.X = ix->X; rp.Q = Q + c0 * ix->d; rp.cand = reinterpret_cast<const uint32_t *>(cand) + c0 * B;
+        rp.X = ix->X; rp.X8 = ix->X8; rp.Q = Q + c0 * ix->d; rp.cand = reinterpret_cast<const uint32_t *>(cand) + c0 * B;
         rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn; rp.parts = c.parts; rp.rows_per_part = c.rpp;
         rp.G = c.G; rp.U = c.U; rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
         HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));

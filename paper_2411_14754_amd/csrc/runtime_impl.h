@@ -99,6 +99,8 @@ struct suco_index {
     uint16_t *ids16 = nullptr;
     uint32_t *csize = nullptr;
     uint8_t *assign = nullptr;
+    uint8_t *X8 = nullptr;          // byte copy of X when every coordinate is an integer in 0..255
+    bool no_byte_rows = false;
     // query workspace (one arena, grown on demand)
     std::mutex mu;
     hipEvent_t done = nullptr;
@@ -124,10 +126,10 @@ struct suco_index {
         prof_pool.clear();
         prof_used = 0;
         for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
-                        (void *)assign, (void *)arena})
+                        (void *)assign, (void *)arena, (void *)X8})
             if (p) (void)hipFree(p);
         X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
-        assign = nullptr; arena = nullptr; arena_bytes = 0;
+        assign = nullptr; arena = nullptr; arena_bytes = 0; X8 = nullptr;
         magic = 0;
     }
 };

@@ -55,6 +55,7 @@ struct QueryPass {
 
 struct RerankPass {
     const float *X;
+    const uint8_t *X8;        // byte copy of X, or null
     const float *Q;
     const uint32_t *cand;     // [nq][B]
     int64_t B;
@@ -91,6 +92,8 @@ hipError_t launch_collide(const QueryPass &p, hipStream_t s);
 hipError_t launch_select(const QueryPass &p, hipStream_t s);
 hipError_t launch_rerank(const RerankPass &r, hipStream_t s);
 hipError_t launch_merge(const RerankPass &r, hipStream_t s);
+hipError_t launch_check_bytes(const float *X, int64_t m, int *bad, hipStream_t s);
+hipError_t launch_to_bytes(const float *X, int64_t m, uint8_t *X8, hipStream_t s);
 
 // The learned-budget network (mlp.hip): parameter views and per-pass arguments.
 struct MlpView {

@@ -29,19 +29,28 @@ def per_query_recall(ids, gt):
 
 
 def label_alphas(index: Index, Q, gt, k: int, beta: float, grid: list[float], chunk: int = 16384):
-    """Smallest grid alpha with per-query recall@k = 1 (else the largest)."""
+    """Per query, the smallest grid alpha whose recall@k equals the recall at
+    the grid's largest alpha: where the query's recall stops improving.  (A
+    query that the candidate budget beta*n never lets reach recall 1 is not
+    pushed to the largest alpha.)"""
     import torch
     nq = Q.shape[0]
+    grid = sorted(grid)
+    best = torch.empty(nq, dtype=torch.float32, device="cuda")
+    for s in range(0, nq, chunk):
+        e = min(nq, s + chunk)
+        ids, _ = index.query(Q[s:e], k, grid[-1], beta)
+        best[s:e] = per_query_recall(ids, gt[s:e])
     label = torch.full((nq,), float(grid[-1]), dtype=torch.float32, device="cuda")
     done = torch.zeros(nq, dtype=torch.bool, device="cuda")
-    for a in sorted(grid):
+    for a in grid:
         for s in range(0, nq, chunk):
             e = min(nq, s + chunk)
             todo = ~done[s:e]
             if not bool(todo.any()):
                 continue
             ids, _ = index.query(Q[s:e], k, a, beta)
-            hit = (per_query_recall(ids, gt[s:e]) >= 1.0) & todo
+            hit = (per_query_recall(ids, gt[s:e]) >= best[s:e]) & todo
             label[s:e][hit] = a
             done[s:e] |= hit
     return label

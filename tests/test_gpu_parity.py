@@ -260,3 +260,24 @@ def test_sift_like_full_size_sampled(suco):
     assert (np.diff(full["cand"], axis=1) > 0).all() and full["cand"].shape[1] == B
     assert ((full["cand"] >= 0) & (full["cand"] < X.shape[0])).all()
     gix.free()
+
+
+def test_byte_rows_equal_fp32_rows(suco):
+    """Integer data in 0..255: the re-rank from the index's byte copy of X gives
+    bitwise the results of the FP32 rows (and the oracle's top-k exactly)."""
+    W = synth.Workload(2)
+    X, Q = W.data(50_000), W.queries(200)
+    _, c32, asg, _ = oracle.build_index(X, 8, 20, iters=4)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    a = suco.Index.from_index(Xd, 8, 20, c32, asg)
+    b = suco.Index.from_index(Xd, 8, 20, c32, asg, flags=suco.BUILD_NO_BYTE_ROWS)
+    ra = a.query(Qd, 10, 0.02, 0.01)
+    rb = b.query(Qd, 10, 0.02, 0.01)
+    torch.cuda.synchronize()
+    assert np.array_equal(ra[0].cpu().numpy(), rb[0].cpu().numpy())
+    assert np.array_equal(ra[1].cpu().numpy(), rb[1].cpu().numpy())
+    oix = oracle.Index(X, 8, 20, c32, asg)
+    ref = oix.query(Q, 10, 0.02, 0.01)
+    assert np.array_equal(ra[0].cpu().numpy(), ref["ids"])
+    a.free()
+    b.free()
