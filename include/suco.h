@@ -66,6 +66,10 @@ typedef struct suco_build_params {
  * byte copy of D, from which the re-rank reads its rows (they convert to FP32
  * exactly, so results are unchanged).  This flag keeps FP32 rows only. */
 #define SUCO_BUILD_NO_BYTE_ROWS 1
+/* Also keep what suco_query_bf16 reads: a BF16 copy of D (2*n*d bytes), a
+ * per-row bound of its rounding error (4*n bytes) and BF16 centres.  Needs d
+ * to be a multiple of 8. */
+#define SUCO_BUILD_BF16 2
 
 SUCO_API int suco_version(void);
 SUCO_API const char *suco_last_error(void);
@@ -159,6 +163,44 @@ SUCO_API int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, 
                      const float *alpha_q, double alpha, double beta, int32_t *ids, float *dists,
                      uint8_t *scores, int32_t *cand, int32_t *ncells, int32_t *aprime,
                      uint16_t *cells, float *feat, void *stream);
+
+/* ------------------------------------------------- BF16 split precision --
+ * The query of suco_query with BF16 arithmetic where it cannot change the
+ * answer, on an index built with SUCO_BUILD_BF16.
+ *  - flags & SUCO_BF16_S1: step 1 runs on the matrix cores, the centre
+ *    distances being |q^|^2 + |c^|^2 - 2 q^.c^ from BF16-rounded query halves
+ *    q^ and centres c^ with FP32 accumulation.  The keys of step 2 then carry
+ *    the BF16 rounding, so cells whose keys nearly tie may be activated
+ *    differently from suco_query.  Without the flag step 1 is that of
+ *    suco_query (FP32) and the activated cells are identical.
+ *  - Step 5 in two passes: a first pass over all B candidates reads the BF16
+ *    copy of D (half the bytes) and brackets each candidate's FP32 squared
+ *    distance between certified lower and upper bounds (from a per-row bound
+ *    of the BF16 rounding error and the FP32 rounding of both sums); the
+ *    survivors are the candidates whose lower bound does not exceed the k-th
+ *    smallest upper bound, a set that provably contains the FP32 top-k.  The
+ *    survivors are re-ranked exactly as suco_query re-ranks, so for the same
+ *    candidates ids and dists are bitwise those of suco_query.
+ *
+ *  Q, ids, dists, k, alpha, beta   as in suco_query.
+ *  nsurv   device int32 [nq] survivor count per query, or NULL.
+ *  relerr  device double [nq][k] |dists - t| / t per result, t the FP64
+ *          Euclidean distance of the returned point, or NULL.
+ *  cdist   device float32 [nq][2*n_s][sqrt_k] the BF16 centre distances
+ *          (only with SUCO_BF16_S1), or NULL.
+ *  errors  SUCO_E_STATE if the index was built without SUCO_BUILD_BF16.
+ */
+#define SUCO_BF16_S1 1
+SUCO_API int suco_query_bf16(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
+                             double beta, int32_t flags, int32_t *ids, float *dists, int32_t *nsurv,
+                             double *relerr, float *cdist, void *stream);
+/* As suco_query_bf16, also exporting the intermediate results of steps 2-4
+ * (scores, cand, ncells, aprime, cells: layouts and meaning as in
+ * suco_query_debug; each may be NULL). */
+SUCO_API int suco_query_bf16_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
+                                   double beta, int32_t flags, int32_t *ids, float *dists, int32_t *nsurv,
+                                   double *relerr, float *cdist, uint8_t *scores, int32_t *cand,
+                                   int32_t *ncells, int32_t *aprime, uint16_t *cells, void *stream);
 
 /* ------------------------------------------------------- single steps --
  * The steps of the query path on their own, fed by the caller; they let each
@@ -268,9 +310,10 @@ SUCO_API int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, f
  * and returns, per step, the summed milliseconds and launch counts since the
  * last read, then resets.  Steps, in order: 0 activate (centre distances and
  * Dynamic Activation), 1 collide (SC-score counting), 2 select (top-B by
- * score), 3 rerank (candidate distances, partial top-k), 4 merge (final top-k).
- *  ms        host double [5]
- *  launches  host int64 [5] */
+ * score), 3 rerank (candidate distances, partial top-k), 4 merge (final top-k),
+ * 5 BF16 centre distances, 6 BF16 first re-rank pass, 7 survivors.
+ *  ms        host double [8]
+ *  launches  host int64 [8] */
 SUCO_API int suco_profile(suco_index *ix, int enable);
 SUCO_API int suco_profile_read(suco_index *ix, double *ms, int64_t *launches);
 

@@ -71,6 +71,10 @@ def lib():
         L.so_query_cells.argtypes = [P, P, i32, C.c_double, i32, P, P, P, P, P, P]
         L.so_sclinear.argtypes = [P, i64, i32, i32, P, i64, i32, C.c_double, C.c_double, P, P, P, i32]
         L.so_bruteforce.argtypes = [P, i64, i32, P, i64, i32, P, P, i32]
+        L.so_bf16.restype = C.c_double
+        L.so_bf16.argtypes = [C.c_float]
+        L.so_bf16_round.argtypes = [P, i64, P]
+        L.so_index_set_s1_bf16.argtypes = [P, i32]
         _lib = L
     return _lib
 
@@ -151,6 +155,10 @@ class Index:
         if getattr(self, "h", None) and _lib is not None:
             _lib.so_index_free(self.h)
             self.h = None
+
+    def set_s1_bf16(self, on: bool = True):
+        """Centre distances from BF16-rounded query halves and centres (the split-precision model)."""
+        lib().so_index_set_s1_bf16(self.h, 1 if on else 0)
 
     def offs(self) -> np.ndarray:
         p = lib().so_index_offs(self.h)
@@ -258,6 +266,15 @@ def bruteforce(X, Q, k, nthreads=None):
     lib().so_bruteforce(_p(X), X.shape[0], X.shape[1], _p(Q), Q.shape[0], k, _p(ids), _p(dist),
                         nthreads or default_threads())
     return ids, dist
+
+
+def bf16_round_arith(x) -> np.ndarray:
+    """Round FP32 values to BF16 (nearest, ties to even), returned as FP32: the C
+    oracle's arithmetic form (scale, nearbyint, scale back), used by its step-1 model."""
+    x = np.ascontiguousarray(x, np.float32)
+    out = np.empty_like(x)
+    lib().so_bf16_round(_p(x), x.size, _p(out))
+    return out
 
 
 def recall(ids: np.ndarray, gt: np.ndarray) -> float:

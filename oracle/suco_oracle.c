@@ -198,6 +198,30 @@ EXPORT int so_build(const float *X, int64_t n, int d, int ns, int sk, int iters,
 /* and one IMI per subspace (Alg. 2, the loop appending j to                */
 /* IMI_i[a1(j), a2(j)]): cell = a1*sqrtK + a2, member ids in ascending order.*/
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* BF16 model (not in the paper; the split-precision form).  BF16 keeps 8    */
+/* significant bits (1 implicit + 7 stored) and the FP32 exponent range.     */
+/* Rounding to nearest, ties to even, done arithmetically: scale the value   */
+/* so that its 8 significant bits form the integer part, round that with     */
+/* nearbyint (ties to even in the default rounding mode), scale back.  Below */
+/* 2^-126 the grid is that of BF16 subnormals, spacing 2^-133.  Results past */
+/* the largest BF16 value round to infinity; inf and nan pass through.       */
+/* ------------------------------------------------------------------------ */
+EXPORT double so_bf16(float x) {
+    double v = (double)x;
+    if (isnan(v) || isinf(v) || v == 0.0) return v;
+    int e;
+    (void)frexp(v, &e);                 /* v = m * 2^e, 0.5 <= |m| < 1 */
+    if (e - 1 < -126) e = -125;         /* subnormal grid: spacing 2^-133 */
+    double step = ldexp(1.0, e - 8);    /* 8 significant bits above it */
+    double r = nearbyint(v / step) * step;
+    return (double)(float)r;            /* exact, or +-inf past the BF16 range */
+}
+
+EXPORT void so_bf16_round(const float *x, int64_t m, float *out) {
+    for (int64_t t = 0; t < m; ++t) out[t] = (float)so_bf16(x[t]);
+}
+
 typedef struct {
     const float *X;
     int64_t n;
@@ -206,6 +230,7 @@ typedef struct {
     float *cent;       /* [sk*d] packed per half */
     int64_t *offs;     /* [ns][K+1] */
     int32_t *ids;      /* [ns][n]   */
+    int s1_bf16;       /* centre distances from BF16-rounded values (model) */
 } so_index;
 
 EXPORT so_index *so_index_create(const float *X, int64_t n, int d, int ns, int sk,
@@ -255,12 +280,18 @@ EXPORT void so_centroid_dists(const so_index *ix, const float *q, int g, double 
     for (int c = 0; c < ix->sk; ++c) {
         double s = 0.0;
         for (int j = 0; j < w; ++j) {
-            double t = (double)q[d0 + j] - (double)cg[(int64_t)c * w + j];
+            double a = (double)q[d0 + j], b = (double)cg[(int64_t)c * w + j];
+            if (ix->s1_bf16) { a = so_bf16(q[d0 + j]); b = so_bf16(cg[(int64_t)c * w + j]); }
+            double t = a - b;
             s += t * t;
         }
         dist[c] = s;
     }
 }
+
+/* Model of the split-precision step 1 (not in the paper): the same squared
+ * distances, from the query half and centres first rounded to BF16. */
+EXPORT void so_index_set_s1_bf16(so_index *ix, int on) { ix->s1_bf16 = on != 0; }
 
 /* Alg. 4, "obtain the indices of sorted dists in ascending order".
  * READING: ties by centre id. */

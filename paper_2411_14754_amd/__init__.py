@@ -26,9 +26,10 @@ EXPORTED = (
     "suco_batcher_free", "suco_mlp_num_params", "suco_mlp_create", "suco_mlp_set_norm", "suco_mlp_get_params",
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
+    "suco_query_bf16", "suco_query_bf16_debug",
 )
 
-STAGES = ("activate", "collide", "select", "rerank", "merge")
+STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors")
 
 
 class SucoError(RuntimeError):
@@ -43,6 +44,8 @@ class BuildParams(C.Structure):
 
 
 BUILD_NO_BYTE_ROWS = 1
+BUILD_BF16 = 2
+BF16_S1 = 1
 
 
 _lib = None
@@ -93,6 +96,8 @@ def lib():
         L.suco_query_features.argtypes = [P, P, i64, P, P]
         L.suco_query_learned.argtypes = [P, P, P, i64, i32, dbl, C.c_float, C.c_float, C.c_float, P, P, P, P]
         L.suco_batcher_set_model.argtypes = [P, P, C.c_float, C.c_float, C.c_float]
+        L.suco_query_bf16.argtypes = [P, P, i64, i32, dbl, dbl, i32, P, P, P, P, P, P]
+        L.suco_query_bf16_debug.argtypes = [P, P, i64, i32, dbl, dbl, i32, P, P, P, P, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -251,6 +256,37 @@ class Index:
                                       float(alpha), float(beta), _opt(ids), _opt(dists), _opt(o["scores"]),
                                       _opt(o["cand"]), _opt(o["ncells"]), _opt(o["aprime"]), _opt(o["cells"]),
                                       _opt(o["feat"]), _stream(stream)))
+        return o
+
+    def query_bf16(self, Q, k: int, alpha: float, beta: float, s1_bf16: bool = False, nsurv=True,
+                   relerr=True, cdist=False, debug=False, out=None, stream=None):
+        """BF16 split-precision query (see suco_query_bf16): returns a dict with ids, dists and
+        the requested extras (nsurv int32 [nq], relerr float64 [nq,k], cdist float32
+        [nq,2ns,sqrt_k]); debug=True adds scores, cand, ncells, aprime and cells as in query_debug."""
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        ids, dists = out if out is not None else self._out(nq, k)
+        dev = "cuda"
+        o = dict(ids=ids, dists=dists)
+        o["nsurv"] = torch.empty((nq,), dtype=torch.int32, device=dev) if nsurv else None
+        o["relerr"] = torch.empty((nq, k), dtype=torch.float64, device=dev) if relerr else None
+        o["cdist"] = (torch.empty((nq, 2 * self.ns, self.sqrt_k), dtype=torch.float32, device=dev)
+                      if cdist else None)
+        flags = BF16_S1 if s1_bf16 else 0
+        head = (self._h, pq, nq, k, float(alpha), float(beta), flags, _dev(ids, torch.int32),
+                _dev(dists, torch.float32), _opt(o["nsurv"]), _opt(o["relerr"]), _opt(o["cdist"]))
+        if not debug:
+            _check(lib().suco_query_bf16(*head, _stream(stream)))
+            return o
+        B = count_B(beta, self.n, k)
+        o["scores"] = torch.empty((nq, self.n), dtype=torch.uint8, device=dev)
+        o["cand"] = torch.empty((nq, B), dtype=torch.int32, device=dev)
+        o["ncells"] = torch.empty((nq, self.ns), dtype=torch.int32, device=dev)
+        o["aprime"] = torch.empty((nq, self.ns), dtype=torch.int32, device=dev)
+        o["cells"] = torch.empty((nq, self.ns, self.K), dtype=torch.uint16, device=dev)
+        _check(lib().suco_query_bf16_debug(*head, _opt(o["scores"]), _opt(o["cand"]), _opt(o["ncells"]),
+                                           _opt(o["aprime"]), _opt(o["cells"]), _stream(stream)))
         return o
 
     def collide_select(self, cells, ncells, k: int, beta: float, want_scores=True, stream=None):

@@ -17,27 +17,9 @@
 #include <algorithm>
 
 #include "suco_impl.h"
+#include "wave.h"
 
 namespace suco {
-
-// ------------------------------------------------------------ wave helpers
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
-    uint32_t lo = __shfl((uint32_t)v, src, kWave);
-    uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
-    uint32_t lo = __shfl_up((uint32_t)v, d, kWave);
-    uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, kWave);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // Sum over the block; every thread gets the total.
 template <int NT>
@@ -119,9 +101,14 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
     const int tid = threadIdx.x;
     const float *q = a.Q + (int64_t)ql * a.ix.d;
 
-    // centre distances of both halves (squared L2, FP32, dimension order)
+    // centre distances of both halves (squared L2, FP32, dimension order), or
+    // the ones given by an earlier kernel
     for (int t = tid; t < 2 * sk; t += NT) {
         const int h = t >= sk, c = t - h * sk;
+        if (a.Dext) {
+            Dr[h][c] = a.Dext[((int64_t)ql * 2 * ns + 2 * i + h) * sk + c];
+            continue;
+        }
         const HalfDims hd = a.ix.halves[2 * i + h];
         const float *cp = a.ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
         const float *qp = q + hd.dim0;
@@ -520,6 +507,7 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
     }
 }
 
+
 // ================================================================ rerank ==
 // Block of NT threads per (query, part of the candidate list).  G lanes share
 // a row: lane li of the group reads float4 slices li, li+G, ... of the row,
@@ -528,18 +516,6 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
 // keeps its k best (squared distance bits << 32 | id) sorted across lanes
 // 0..k-1; the waves' lists are merged at the end.  Keys order exactly by
 // (distance, id) because the distances are non-negative.
-__device__ __forceinline__ void topk_insert(uint64_t &best, uint64_t kk, int k, int lane) {
-    const uint64_t kth = shfl64(best, k - 1);
-    if (kk < kth) {
-        const int pos = __popcll(__ballot(lane < k && best < kk));
-        const uint64_t up = shfl_up64(best, 1);
-        if (lane < k) {
-            if (lane == pos) best = kk;
-            else if (lane > pos) best = up;
-        }
-    }
-}
-
 // ROWS8: the rows are read from the index's byte copy of X (kept when every
 // coordinate is an integer in 0..255); each byte converts to FP32 exactly, so
 // the arithmetic, its order and the result are those of the FP32 rows, with a
@@ -560,7 +536,8 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     }
     uint64_t best = ~0ull;
     const int64_t rb = (int64_t)part * r.rows_per_part;
-    const int64_t re = rb + r.rows_per_part < r.B ? rb + r.rows_per_part : r.B;
+    const int64_t rows = r.rows_dev ? (r.rows_dev[ql] < r.B ? (int64_t)r.rows_dev[ql] : r.B) : r.B;
+    const int64_t re = rb + r.rows_per_part < rows ? rb + r.rows_per_part : rows;
     const uint32_t *cq = r.cand + (int64_t)ql * r.B;
     for (int64_t base = rb + (int64_t)wv * R; base < re; base += (int64_t)(NT / kWave) * R) {
         const int64_t rw = base + slot;

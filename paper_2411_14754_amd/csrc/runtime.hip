@@ -47,11 +47,14 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     tile_max = std::min(tile_max, (max_lds - static_lds) / 256 * 256);
     if (tile_max < 256 || (int64_t)sk * sk * 4 > max_lds || (int64_t)sk * (sk + 1) * 4 + 4096 > max_lds)
         return fail(SUCO_E_UNSUPPORTED, "the device has too little LDS per work-group for this shape");
+    if (p && (p->flags & SUCO_BUILD_BF16) && d % 8)
+        return fail(SUCO_E_UNSUPPORTED, "SUCO_BUILD_BF16 needs d to be a multiple of 8");
     suco_index *ix = new (std::nothrow) suco_index();
     if (!ix) return fail(SUCO_E_NOMEM, "host allocation failed");
     ix->device = dev;
     ix->n = n; ix->d = d; ix->ns = ns; ix->sk = sk; ix->K = sk * sk;
     ix->no_byte_rows = p && (p->flags & SUCO_BUILD_NO_BYTE_ROWS);
+    ix->want_bf16 = p && (p->flags & SUCO_BUILD_BF16);
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
     const int64_t per = (n + P0 - 1) / P0;
     ix->TILE = (int)((per + 255) / 256 * 256);
@@ -108,6 +111,15 @@ int finish_index(suco_index *ix, hipStream_t st) {
         } else {
             (void)hipGetLastError();   // keep the FP32 rows only
         }
+    }
+    if (ix->want_bf16) {
+        int rc2;
+        if ((rc2 = dev_alloc(&ix->Xb, (size_t)m)) || (rc2 = dev_alloc(&ix->xerr, (size_t)ix->n)) ||
+            (rc2 = dev_alloc(&ix->centb, (size_t)ix->sk * ix->d)) ||
+            (rc2 = dev_alloc(&ix->cnorm2, (size_t)2 * ix->ns * ix->sk)))
+            return rc2;
+        HIPCHECK(launch_bf16_rows(ix->X, ix->n, ix->d, ix->Xb, ix->xerr, st));
+        HIPCHECK(launch_bf16_centres(ix->cent, ix->halves, 2 * ix->ns, ix->sk, ix->d, ix->centb, ix->cnorm2, st));
     }
     HIPCHECK(hipStreamSynchronize(st));
     return SUCO_OK;
@@ -254,25 +266,56 @@ int check_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, dou
     return SUCO_OK;
 }
 
+// BF16 split precision (suco_query_bf16): optional MFMA centre distances, and
+// the re-rank as BF16 first pass, certified survivors, FP32 re-rank of those.
+struct Bf16Opts {
+    int flags = 0;
+    int32_t *nsurv = nullptr;
+    double *relerr = nullptr;
+    float *cdist = nullptr;
+};
+
 int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, const float *alpha_q, double alpha,
-              double beta, int32_t *ids, float *dists, const DebugOut *dbg, hipStream_t st) {
+              double beta, int32_t *ids, float *dists, const DebugOut *dbg, const Bf16Opts *bo, hipStream_t st) {
     int rc = check_query(cix, Q, nq, k, beta, ids, dists);
     if (rc) return rc;
     if (!alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (bo) {
+        if (bo->flags & ~SUCO_BF16_S1) return fail(SUCO_E_INVAL, "unknown flags");
+        if (!cix->Xb) return fail(SUCO_E_STATE, "the index was built without SUCO_BUILD_BF16");
+    }
     if (nq == 0) return SUCO_OK;
     suco_index *ix = const_cast<suco_index *>(cix);
     const int64_t B = count_B_host(beta, ix->n, k);
-    RerankCfg rc_cfg;
-    if ((rc = rerank_cfg(ix->d, B, &rc_cfg))) return rc;
+    RerankCfg c32, c16{};
+    if ((rc = rerank_cfg(ix->d, B, &c32))) return rc;
+    if (bo && (rc = rerank_bf16_cfg(ix->d, B, &c16))) return rc;
+    const int parts = std::max(c32.parts, c16.parts);
     std::lock_guard<std::mutex> lock(ix->mu);
     DeviceGuard dg(ix->device);
     const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
-    size_t bytes = 0;
+    const int nh = 2 * ix->ns;
     const bool dense = dbg && dbg->scores;
-    carve(ix, nullptr, C, B, k, rc_cfg.parts, dense, &bytes);
+    // BF16 buffers follow the common workspace
+    float *D = nullptr, *lo = nullptr;
+    uint32_t *surv = nullptr;
+    int32_t *nsv = nullptr;
+    auto extra = [&](char *base, size_t off) {
+        Carve cv{base, off};
+        D = cv.take<float>(C * nh * ix->sk);
+        lo = cv.take<float>(C * (size_t)B);
+        surv = cv.take<uint32_t>(C * (size_t)B);
+        nsv = cv.take<int32_t>(C);
+        return cv.off;
+    };
+    size_t bytes = 0;
+    carve(ix, nullptr, C, B, k, parts, dense, &bytes);
+    if (bo) bytes = extra(nullptr, bytes);
     if ((rc = ensure_arena(ix, bytes))) return rc;
     if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
-    Work w = carve(ix, ix->arena, C, B, k, rc_cfg.parts, dense, nullptr);
+    size_t wbytes = 0;
+    Work w = carve(ix, ix->arena, C, B, k, parts, dense, &wbytes);
+    if (bo) extra(ix->arena, wbytes);
     const IndexView v = ix->view();
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
@@ -288,15 +331,43 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         qp.cells = w.cells; qp.ncells = w.ncells; qp.aprime = w.aprime;
         qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
         qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores; qp.cand = w.cand;
+        if (bo && (bo->flags & SUCO_BF16_S1)) {
+            CentreBf16Pass cp{};
+            cp.Q = qp.Q; cp.nq = cn; cp.d = ix->d; cp.sk = ix->sk; cp.nh = nh; cp.halves = ix->halves;
+            cp.centb = ix->centb; cp.cnorm2 = ix->cnorm2; cp.D = D;
+            HIPCHECK(timed(ix, kCentresBf16, st, [&] { return launch(plan_centre_dists_bf16(cp), &cp, st); }));
+            qp.Dext = D;
+            if (bo->cdist)
+                HIPCHECK(hipMemcpyAsync(bo->cdist + c0 * nh * ix->sk, D, sizeof(float) * cn * nh * ix->sk,
+                                        hipMemcpyDeviceToDevice, st));
+        }
         HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
         RerankPass rp{};
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
-        rp.parts = rc_cfg.parts; rp.rows_per_part = rc_cfg.rpp; rp.G = rc_cfg.G; rp.U = rc_cfg.U;
+        rp.parts = c32.parts; rp.rows_per_part = c32.rpp; rp.G = c32.G; rp.U = c32.U;
         rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
+        if (bo) {
+            Bf16RerankPass bp{};
+            bp.Xb = ix->Xb; bp.xerr = ix->xerr; bp.Q = qp.Q; bp.cand = w.cand; bp.B = B; bp.n = ix->n;
+            bp.d = ix->d; bp.k = k; bp.nq = cn; bp.parts = c16.parts; bp.rows_per_part = c16.rpp; bp.G = c16.G;
+            bp.U = c16.U; bp.part_keys = w.part_keys; bp.lo = lo; bp.surv = surv; bp.nsurv = nsv;
+            HIPCHECK(timed(ix, kRerankBf16, st, [&] { return launch(plan_rerank_bf16(bp, 0), &bp, st); }));
+            HIPCHECK(timed(ix, kSurvivors, st, [&] { return launch(plan_survivors(bp), &bp, st); }));
+            // the FP32 re-rank of the survivors: one part per query
+            rp.cand = surv; rp.rows_dev = nsv; rp.parts = 1; rp.rows_per_part = B;
+        }
         HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));
         HIPCHECK(timed(ix, kMerge, st, [&] { return launch_merge(rp, st); }));
+        if (bo && bo->nsurv)
+            HIPCHECK(hipMemcpyAsync(bo->nsurv + c0, nsv, sizeof(int32_t) * cn, hipMemcpyDeviceToDevice, st));
+        if (bo && bo->relerr) {
+            RelErrPass ep{};
+            ep.X = ix->X; ep.n = ix->n; ep.Q = qp.Q; ep.ids = rp.ids; ep.dists = rp.dists; ep.nq = cn; ep.d = ix->d; ep.k = k;
+            ep.relerr = bo->relerr + c0 * k;
+            HIPCHECK(launch(plan_relerr(ep), &ep, st));
+        }
         if (dbg) {
             const int ns = ix->ns;
             if (dbg->ncells)
@@ -418,13 +489,13 @@ int suco_index_free(suco_index *ix) {
 
 int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
                int32_t *ids, float *dists, void *stream) {
-    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, (hipStream_t)stream);
+    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, int32_t k, const float *alpha_q,
                      double beta, int32_t *ids, float *dists, void *stream) {
     if (nq > 0 && !alpha_q) return fail(SUCO_E_INVAL, "alpha_q must not be NULL");
-    return run_query(ix, Q, nq, k, alpha_q, 0.0, beta, ids, dists, nullptr, (hipStream_t)stream);
+    return run_query(ix, Q, nq, k, alpha_q, 0.0, beta, ids, dists, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k, const float *alpha_q,
@@ -433,7 +504,26 @@ int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k
     DebugOut dbg;
     dbg.scores = scores; dbg.cand = cand; dbg.ncells = ncells; dbg.aprime = aprime; dbg.cells = cells;
     dbg.feat = feat;
-    return run_query(ix, Q, nq, k, alpha_q, alpha, beta, ids, dists, &dbg, (hipStream_t)stream);
+    return run_query(ix, Q, nq, k, alpha_q, alpha, beta, ids, dists, &dbg, nullptr, (hipStream_t)stream);
+}
+
+int suco_query_bf16(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+                    int32_t flags, int32_t *ids, float *dists, int32_t *nsurv, double *relerr, float *cdist,
+                    void *stream) {
+    Bf16Opts bo;
+    bo.flags = flags; bo.nsurv = nsurv; bo.relerr = relerr; bo.cdist = cdist;
+    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, &bo, (hipStream_t)stream);
+}
+
+int suco_query_bf16_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+                          int32_t flags, int32_t *ids, float *dists, int32_t *nsurv, double *relerr, float *cdist,
+                          uint8_t *scores, int32_t *cand, int32_t *ncells, int32_t *aprime, uint16_t *cells,
+                          void *stream) {
+    Bf16Opts bo;
+    bo.flags = flags; bo.nsurv = nsurv; bo.relerr = relerr; bo.cdist = cdist;
+    DebugOut dbg;
+    dbg.scores = scores; dbg.cand = cand; dbg.ncells = ncells; dbg.aprime = aprime; dbg.cells = cells;
+    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, &dbg, &bo, (hipStream_t)stream);
 }
 
 int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells, const int32_t *ncells,

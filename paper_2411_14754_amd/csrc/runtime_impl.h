@@ -101,6 +101,12 @@ struct suco_index {
     uint8_t *assign = nullptr;
     uint8_t *X8 = nullptr;          // byte copy of X when every coordinate is an integer in 0..255
     bool no_byte_rows = false;
+    bool want_bf16 = false;
+    // BF16 split precision (built on request)
+    uint16_t *Xb = nullptr;         // [n][d] BF16 copy of X
+    float *xerr = nullptr;          // [n] upper bound of |bf16(x) - x|
+    uint16_t *centb = nullptr;      // BF16 centres, layout of cent
+    float *cnorm2 = nullptr;        // [2ns][sqrt_k] squared norms of the BF16 centres
     // query workspace (one arena, grown on demand)
     std::mutex mu;
     hipEvent_t done = nullptr;
@@ -126,10 +132,12 @@ struct suco_index {
         prof_pool.clear();
         prof_used = 0;
         for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
-                        (void *)assign, (void *)arena, (void *)X8})
+                        (void *)assign, (void *)arena, (void *)X8, (void *)Xb, (void *)xerr, (void *)centb,
+                        (void *)cnorm2})
             if (p) (void)hipFree(p);
         X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
         assign = nullptr; arena = nullptr; arena_bytes = 0; X8 = nullptr;
+        Xb = nullptr; xerr = nullptr; centb = nullptr; cnorm2 = nullptr;
         magic = 0;
     }
 };
@@ -139,7 +147,7 @@ namespace suco {
 
 inline bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
 
-enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kStages };
+enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kStages };
 
 // Launch through `fn`, bracketed by a pair of timing events when profiling is on.
 template <class F>
@@ -169,6 +177,20 @@ inline int runs_per_sub(int ns) {
 }
 
 struct RerankCfg { int G, U, parts; int64_t rpp; };
+
+// BF16 first pass: G lanes per row, U slices of 8 values per lane.
+inline int rerank_bf16_cfg(int d, int64_t B, RerankCfg *c) {
+    if (d % 8) return fail(SUCO_E_UNSUPPORTED, "the BF16 re-rank needs d to be a multiple of 8");
+    const int d8 = d / 8;
+    int G = 1;
+    while (G * 2 <= std::max(1, d8 / 2) && G < kWave) G *= 2;
+    const int U = (d8 + G - 1) / G;
+    if (U > kMaxU16) return fail(SUCO_E_UNSUPPORTED, "the BF16 re-rank supports d <= 2048");
+    c->G = G; c->U = U;
+    c->rpp = 512;
+    c->parts = (int)((B + c->rpp - 1) / c->rpp);
+    return SUCO_OK;
+}
 
 inline int rerank_cfg(int d, int64_t B, RerankCfg *c) {
     if (d % 4) return fail(SUCO_E_UNSUPPORTED, "the re-rank needs d to be a multiple of 4");

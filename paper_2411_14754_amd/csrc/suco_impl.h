@@ -51,6 +51,7 @@ struct QueryPass {
     uint16_t *lvl;            // [nq][P][TILE] non-zero-score tile-local ids by level
     uint8_t *scores;          // [nq][P*TILE] dense scores, or null
     uint32_t *cand;           // [nq][B]
+    const float *Dext;        // [nq][2ns][sqrt_k] centre distances computed elsewhere, or null
 };
 
 struct RerankPass {
@@ -65,6 +66,7 @@ struct RerankPass {
     const int *nq_dev;        // as in QueryPass
     int q_base;
     int64_t rows_per_part;
+    const int32_t *rows_dev;  // [nq] candidates per query (<= B), or null for B
     int G;                    // lanes per row (power of two)
     int U;                    // float4 slices per lane
     uint64_t *part_keys;      // [nq][parts][k] (squared distance bits << 32 | id)
@@ -120,6 +122,46 @@ struct InferPass {
 };
 Launch plan_features(int nq_cap);
 Launch plan_mlp_infer(int m_cap);
+
+// BF16 split precision (bf16.hip).
+struct CentreBf16Pass {
+    const float *Q;           // [nq][d]
+    int nq, d, sk, nh;        // nh = 2 n_s halves
+    const HalfDims *halves;   // [nh]
+    const uint16_t *centb;    // BF16 centres, layout of IndexView::cent
+    const float *cnorm2;      // [nh][sk] squared norms of the BF16 centres
+    float *D;                 // [nq][nh][sk]
+};
+struct Bf16RerankPass {
+    const uint16_t *Xb;       // [n][d] BF16 copy of X
+    const float *xerr;        // [n] upper bound of |bf16(x) - x| per row
+    const float *Q;
+    const uint32_t *cand;     // [nq][B]
+    int64_t B, n;
+    int d, k, nq, parts;
+    int64_t rows_per_part;
+    int G, U;                 // lanes per row, 16-byte slices (8 values) per lane
+    uint64_t *part_keys;      // [nq][parts][k] upper-bound keys
+    float *lo;                // [nq][B] lower bounds
+    uint32_t *surv;           // [nq][B] survivors, first nsurv[q] valid
+    int32_t *nsurv;           // [nq]
+};
+struct RelErrPass {
+    const float *X, *Q;
+    const int32_t *ids;
+    const float *dists;
+    int64_t n;
+    int nq, d, k;
+    double *relerr;           // [nq][k]
+};
+constexpr int kMaxU16 = 4;    // BF16 slices of 8 values per lane in the first pass
+Launch plan_centre_dists_bf16(const CentreBf16Pass &p);
+Launch plan_rerank_bf16(const Bf16RerankPass &r, int cap);
+Launch plan_survivors(const Bf16RerankPass &r);
+Launch plan_relerr(const RelErrPass &r);
+hipError_t launch_bf16_rows(const float *X, int64_t n, int d, uint16_t *Xb, float *xerr, hipStream_t s);
+hipError_t launch_bf16_centres(const float *cent, const HalfDims *halves, int nh, int sk, int d, uint16_t *centb,
+                               float *cnorm2, hipStream_t s);
 
 // Launchers (build_kernels.hip)
 struct KmeansPass {

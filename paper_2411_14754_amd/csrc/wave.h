@@ -1,0 +1,43 @@
+// Wave-level helpers shared by the gfx950 kernels (64-lane wavefronts).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "suco_impl.h"
+
+namespace suco {
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    uint32_t lo = __shfl((uint32_t)v, src, kWave);
+    uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+    uint32_t lo = __shfl_up((uint32_t)v, d, kWave);
+    uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A wave keeps its k best keys sorted ascending in lanes 0..k-1 (lanes >= k
+// hold ~0); insert one key, given to every lane, keeping the k smallest.
+__device__ __forceinline__ void topk_insert(uint64_t &best, uint64_t kk, int k, int lane) {
+    const uint64_t kth = shfl64(best, k - 1);
+    if (kk < kth) {
+        const int pos = __popcll(__ballot(lane < k && best < kk));
+        const uint64_t up = shfl_up64(best, 1);
+        if (lane < k) {
+            if (lane == pos) best = kk;
+            else if (lane > pos) best = up;
+        }
+    }
+}
+
+}  // namespace suco

@@ -424,3 +424,59 @@ def test_bf16_round_to_nearest_even():
     x = np.random.default_rng(0).normal(size=10000).astype(np.float32) * 100
     assert np.array_equal(oracle.bf16_round(x),
                           torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy())
+
+
+def test_bf16_arith_form_matches_bit_form_and_torch():
+    # the C oracle rounds arithmetically, oracle.mlp by bit arithmetic, torch by its own conversion
+    import torch
+    rng = np.random.default_rng(7)
+    x = (rng.standard_normal(200000) * 10.0 ** rng.integers(-44, 38, 200000)).astype(np.float32)
+    ties = (np.float32(1.0) + np.arange(1, 512, 2, dtype=np.float32) * np.float32(2 ** -8)).astype(np.float32)
+    sub = (np.arange(-300, 300, dtype=np.float32) * np.float32(2 ** -140)).astype(np.float32)
+    big = np.array([3.3895314e38, 3.3961775e38, 3.40282e38, -3.40282e38, np.inf, -np.inf, 0.0, -0.0], np.float32)
+    allv = np.concatenate([x, ties, sub, big]).astype(np.float32)
+    a = oracle.bf16_round_arith(allv)
+    b = oracle.bf16_round(allv)
+    t = torch.from_numpy(allv).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(a.view(np.uint32), t.view(np.uint32))
+    assert np.array_equal(b.view(np.uint32), t.view(np.uint32))
+    # relative rounding error at most 2^-8 for normal values
+    nz = (np.abs(allv) > 2.0 ** -126) & np.isfinite(allv) & np.isfinite(a)
+    assert (np.abs(a[nz].astype(np.float64) - allv[nz]) <= 2.0 ** -8 * np.abs(allv[nz].astype(np.float64))).all()
+
+
+def test_s1_bf16_model_equals_fp32_on_bf16_exact_values():
+    # values with at most 8 significant bits are unchanged by BF16 rounding, so the
+    # split-precision step-1 model must reproduce the plain step-1 distances exactly
+    X = (np.random.default_rng(3).integers(0, 64, size=(400, 16)) / 4.0).astype(np.float32)
+    c64, c32, asg, _ = oracle.build_index(X, 4, 4, iters=5, seed=2)
+    c32 = oracle.bf16_round(c32)            # make the centres BF16-exact too
+    ix = oracle.Index(X, 4, 4, c32, asg)
+    q = X[17] + np.float32(0.25)
+    plain = [ix.centroid_dists(q, g) for g in range(8)]
+    ix.set_s1_bf16(True)
+    model = [ix.centroid_dists(q, g) for g in range(8)]
+    for a, b in zip(plain, model):
+        assert np.array_equal(a, b)
+
+
+def test_s1_bf16_model_is_distance_of_rounded_values():
+    import torch
+    X, ix, (c64, c32, asg, _) = small_index(n=500, d=24, ns=3, sk=5, seed=11, kind="gauss")
+    q = (X[3] * np.float32(1.37) + np.float32(0.011)).astype(np.float32)
+    ix.set_s1_bf16(True)
+    lay = oracle.layout(24, 3)
+    for g in range(6):
+        d0, w = int(lay[0][g]), int(lay[1][g])
+        cen = c32.reshape(-1)[5 * d0:5 * d0 + 5 * w].reshape(5, w)
+        qb = torch.from_numpy(q[d0:d0 + w].copy()).to(torch.bfloat16).double().numpy()
+        cb = torch.from_numpy(cen.copy()).to(torch.bfloat16).double().numpy()
+        ref = ((cb - qb[None, :]) ** 2).sum(axis=1)
+        assert np.allclose(ix.centroid_dists(q, g), ref, rtol=1e-15, atol=0)
+        # and differs from the FP32 distances by at most the rounding's effect
+        ix.set_s1_bf16(False)
+        plain = ix.centroid_dists(q, g)
+        ix.set_s1_bf16(True)
+        bound = 2 * np.sqrt(plain) * (2.0 ** -8) * (np.linalg.norm(q[d0:d0 + w]) + np.linalg.norm(cen, axis=1)) \
+            + ((2.0 ** -8) * (np.linalg.norm(q[d0:d0 + w]) + np.linalg.norm(cen, axis=1))) ** 2
+        assert (np.abs(ix.centroid_dists(q, g) - plain) <= bound * (1 + 1e-9)).all()
