@@ -57,6 +57,28 @@ def exact_topk(Xd, Qd, k, chunk=256):
     return torch.cat(out).to(torch.int32)
 
 
+def exact_topk_float(Xd, Qd, k, extra=64, chunk=128):
+    """Exact k-NN ids by (squared distance, id) for real-valued data: the FP32
+    product-form distances shortlist k + extra points per query, whose
+    distances are then recomputed in FP64 from the rows and sorted by
+    (distance, id).  The shortlist is exact unless the FP32 form misorders a
+    true neighbour past `extra` others, far beyond its rounding error here."""
+    import torch
+    xn = (Xd * Xd).sum(dim=1)
+    out = []
+    for s in range(0, Qd.shape[0], chunk):
+        q = Qd[s:s + chunk]
+        d2 = xn[None, :] + (q * q).sum(dim=1)[:, None] - 2.0 * (q @ Xd.T)
+        short = torch.topk(d2, k + extra, dim=1, largest=False).indices
+        rows = Xd[short].double()
+        e = ((rows - q.double()[:, None, :]) ** 2).sum(dim=2)
+        order = torch.argsort(short, dim=1)                    # ties by id: sort ids first, stably by distance
+        short, e = torch.gather(short, 1, order), torch.gather(e, 1, order)
+        o2 = torch.sort(e, dim=1, stable=True).indices[:, :k]
+        out.append(torch.gather(short, 1, o2))
+    return torch.cat(out).to(torch.int32)
+
+
 def recall_at(ids, gt):
     k = gt.shape[1]
     hit = (ids[:, :, None] == gt[:, None, :]).any(dim=2).sum(dim=1)
@@ -100,9 +122,167 @@ def cpu_baseline(X, Q, alpha, beta, k, sample, log):
                       f"FP64 C oracle, OpenMP over queries; {dt:.1f}s"}
 
 
+def bench_bf16(args, log):
+    """GIST-like n=1,000,000 d=960 in (0,1), N_s=20, sqrtK=50, 1,000 queries,
+    k=10, beta=0.005: BF16 split precision (MFMA centre distances, BF16 re-rank
+    first pass, certified survivors, FP32 re-rank of the survivors) against the
+    plain FP32 path on the same index, at the smallest grid alpha reaching
+    recall@10 = 0.95."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+
+    W = synth.Workload(3)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    log("generating data")
+    X, Q = W.data(), W.queries()
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1, flags=suco.BUILD_BF16, tile_max=args.tile_max,
+                          query_chunk=args.query_chunk)
+    build_s = time.time() - t0
+    log(f"index built in {build_s:.2f}s")
+    gt = exact_topk_float(Xd, Qd, k)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    nsurv = torch.empty((nq,), dtype=torch.int32, device="cuda")
+    relerr = torch.empty((nq, k), dtype=torch.float64, device="cuda")
+
+    def run_bf16(alpha):
+        suco._check(suco.lib().suco_query_bf16(ix._h, suco._dev(Qd, torch.float32), nq, k, alpha, beta,
+                                               suco.BF16_S1, suco._dev(ids, torch.int32),
+                                               suco._dev(dists, torch.float32), suco._dev(nsurv, torch.int32),
+                                               None, None, suco._stream(None)))
+
+    def run_plain(alpha):
+        ix.query(Qd, k, alpha, beta, out=(ids, dists))
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    sweep = []
+    for a in ((0.0005, 0.00075, 0.001, 0.0015, 0.002, 0.003, 0.005, 0.01, 0.02, 0.05) if args.alpha is None
+              else (args.alpha,)):
+        ms_b = timed(lambda: run_bf16(a), 1, 1)
+        rb = recall_at(ids, gt)
+        ms_p = timed(lambda: run_plain(a), 1, 1)
+        rp = recall_at(ids, gt)
+        sweep.append({"alpha": a, "recall_bf16": round(rb, 5), "qps_bf16": round(nq / (ms_b / 1e3), 1),
+                      "recall_plain": round(rp, 5), "qps_plain": round(nq / (ms_p / 1e3), 1)})
+        log(f"alpha={a}: bf16 recall={rb:.4f} qps={nq / (ms_b / 1e3):.0f} | plain recall={rp:.4f} "
+            f"qps={nq / (ms_p / 1e3):.0f}")
+    ok = [e for e in sweep if e["recall_bf16"] >= TARGET_RECALL]
+    alpha = ok[0]["alpha"] if ok else sweep[-1]["alpha"]
+
+    ms_plain = timed(lambda: run_plain(alpha), args.steps, args.warmup)
+    plain_rec = recall_at(ids, gt)
+    plain_ids, plain_d = ids.clone(), dists.clone()
+    # with FP32 centre distances the BF16 re-rank must return the plain answer bit for bit
+    o = ix.query_bf16(Qd, k, alpha, beta, s1_bf16=False, nsurv=False, relerr=False)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(o["ids"], plain_ids) and torch.equal(o["dists"], plain_d))
+    del o
+    ms = timed(lambda: run_bf16(alpha), args.steps, args.warmup)
+    value = nq * args.steps / (ms / 1e3)
+    rec = recall_at(ids, gt)
+    agree = recall_at(ids, plain_ids)
+    surv = nsurv.double()
+    log(f"bf16 timed: {ms / args.steps:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}; plain "
+        f"{nq * args.steps / (ms_plain / 1e3):.0f} QPS recall@10={plain_rec:.4f}; FP32-S1 BF16 re-rank equals "
+        f"plain: {same}; top-k overlap with plain {agree:.4f}; "
+        f"survivors mean {float(surv.mean()):.1f} max {int(nsurv.max())}")
+    o = ix.query_bf16(Qd, k, alpha, beta, s1_bf16=True, nsurv=False, relerr=True)
+    torch.cuda.synchronize()
+    rel = o["relerr"]
+    aprime = None
+    o = ix.query_bf16(Qd[:64], k, alpha, beta, s1_bf16=True, nsurv=False, relerr=False, debug=True)
+    torch.cuda.synchronize()
+    aprime = float(o["aprime"].double().sum(dim=1).mean())
+    U = float((o["scores"] > 0).sum(dim=1).double().mean())
+    del o
+    B = suco.count_B(beta, n, k)
+    R = float(surv.mean())
+    step_bytes = {
+        "collide": 2.0 * aprime + 2.0 * U,
+        "rerank_bf16": 2.0 * B * d + 4.0 * B + 4.0 * B + 4.0 * B,   # BF16 rows, ids, error bounds, lower bounds
+        "survivors": 4.0 * B + 4.0 * B + 4.0 * R,                   # ids and lower bounds read, survivors written
+        "rerank": 4.0 * R * d + 4.0 * R,                            # FP32 rows of the survivors
+    }
+    ix.profile(True)
+    ix.profile_read()
+    for _ in range(args.steps):
+        run_bf16(alpha)
+    stage = ix.profile_read()
+    ix.profile(False)
+    per_kernel = {}
+    for st_name, (tms, cnt) in stage.items():
+        if cnt == 0:
+            continue
+        avg_ms = tms / cnt
+        ent = {"avg_ms": round(avg_ms, 5), "launches": cnt,
+               "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
+        if st_name in step_bytes:
+            bytes_launch = step_bytes[st_name] * nq / max(1, cnt // args.steps)
+            ent["alg_bytes_per_launch"] = bytes_launch
+            ent["gbs"] = round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1)
+        per_kernel[st_name] = ent
+    dom = max(step_bytes, key=lambda t: stage[t][0])
+    kern_name = {"collide": "k_collide", "rerank_bf16": "k_rerank_bf16", "survivors": "k_survivors",
+                 "rerank": "k_rerank"}[dom]
+    achieved = per_kernel[dom]["gbs"]
+    roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        log("timing the CPU oracle")
+        _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=2, seed=1, nthreads=threads)
+        oix = oracle.Index(X, ns, sk, c32, asg)
+        sample = min(args.cpu_sample, 64)
+        t0 = time.time()
+        oix.query(Q[:sample], k, alpha, beta, nthreads=threads)
+        dt = time.time() - t0
+        cpu = {"value": round(sample / dt, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {sample} of the 1,000 queries at alpha={alpha}, beta={beta}, k={k}; FP64 C "
+                         f"oracle on its own 2-iteration index, OpenMP over queries; {dt:.1f}s"}
+    line = {
+        "metric": "QPS at recall@10=0.95, GIST-like n=1M d=960: BF16 split-precision SuCo on 1 GPU",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": f"gist_like n={n} d={d} in (0,1), N_s={ns}, sqrtK={sk}, nq={nq}, k={k}, beta={beta}",
+                   "form": "bf16 split precision", "alpha": alpha, "recall_at_10": round(rec, 5),
+                   "fp32_s1_equals_plain_bitwise": same, "topk_overlap_with_plain": round(agree, 5),
+                   "plain": {"qps": round(nq * args.steps / (ms_plain / 1e3), 1), "recall_at_10": round(plain_rec, 5)},
+                   "survivors": {"mean": round(R, 2), "max": int(nsurv.max())},
+                   "relerr_vs_fp64": {"max": float(rel.max()), "mean": float(rel.mean())},
+                   "index_build_s": round(build_s, 3), "sweep": sweep},
+        "kernels": per_kernel, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ix.free()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("sift_like", "gist_like"), default="sift_like",
+                    help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split precision")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=512)
@@ -137,6 +317,10 @@ def main():
     def log(msg):
         if not args.quiet:
             print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload == "gist_like":
+        bench_bf16(args, log)
+        return
 
     import torch
     import paper_2411_14754_amd as suco
