@@ -195,7 +195,14 @@ __global__ __launch_bounds__(256) void k_rerank_bf16(Bf16RerankPass r) {
             const float e = e0 + gam * (acc + e0) + 1e-30f;
             if (valid && li == 0) r.lo[(int64_t)ql * r.B + rw] = acc - e;
             const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc + e) << 32) | id) : ~0ull;
-            for (int s2 = 0; s2 < R; ++s2) topk_insert(best, shfl64(key, s2 * G), k, lane);
+            // only keys below the current k-th can enter the list
+            const uint64_t kth = shfl64(best, k - 1);   // every lane takes part in the shuffle
+            uint64_t m = __ballot(li == 0 && key < kth);
+            while (m != 0ull) {
+                const int src = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                topk_insert(best, shfl64(key, src), k, lane);
+            }
         }
         if (lane < k) wl[wv][lane] = best;
         __syncthreads();

@@ -520,17 +520,25 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
 // coordinate is an integer in 0..255); each byte converts to FP32 exactly, so
 // the arithmetic, its order and the result are those of the FP32 rows, with a
 // quarter of the bytes moved.
-template <int NT, bool ROWS8>
+// UM: most slices per lane (U <= UM); NRG = kMaxU / UM row groups are taken
+// per wave iteration, and the loads of all of them are issued before any
+// arithmetic so that more bytes are in flight per wave.
+// Insertion: a key can enter the wave's list only if it is below the current
+// k-th key, so one ballot per iteration finds the few rows that need the
+// (cross-lane) insertion; the others cost nothing more.  The list is the set
+// of the k smallest keys seen, whatever the insertion order (keys are unique).
+template <int NT, bool ROWS8, int UM>
 __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item) {
+    constexpr int NRG = kMaxU / UM;
     __shared__ uint64_t wl[NT / kWave][kMaxK];
     const int ql = item / r.parts, part = item - ql * r.parts;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int G = r.G, R = kWave / G, li = lane & (G - 1), slot = lane / G;
     const int d4 = r.d >> 2, k = r.k;
-    float4 qr[kMaxU];
+    float4 qr[UM];
     const float4 *q4 = reinterpret_cast<const float4 *>(r.Q + (int64_t)ql * r.d);
 #pragma unroll
-    for (int u = 0; u < kMaxU; ++u) {
+    for (int u = 0; u < UM; ++u) {
         const int j = li + G * u;
         qr[u] = (u < r.U && j < d4) ? q4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -539,36 +547,68 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     const int64_t rows = r.rows_dev ? (r.rows_dev[ql] < r.B ? (int64_t)r.rows_dev[ql] : r.B) : r.B;
     const int64_t re = rb + r.rows_per_part < rows ? rb + r.rows_per_part : rows;
     const uint32_t *cq = r.cand + (int64_t)ql * r.B;
-    for (int64_t base = rb + (int64_t)wv * R; base < re; base += (int64_t)(NT / kWave) * R) {
-        const int64_t rw = base + slot;
-        uint32_t id = rw < re ? cq[rw] : 0u;
-        const bool valid = rw < re && id < r.n;   // ids outside [0, n) are ignored
-        id = valid ? id : 0u;
-        const float4 *xr = reinterpret_cast<const float4 *>(r.X + (int64_t)id * r.d);
-        const uint32_t *xr8 = reinterpret_cast<const uint32_t *>(r.X8 + (int64_t)id * r.d);
-        float acc = 0.f;
+    for (int64_t base = rb + (int64_t)wv * R * NRG; base < re; base += (int64_t)(NT / kWave) * R * NRG) {
+        uint32_t id[NRG];
+        bool valid[NRG];
+        float4 x[NRG][UM];
+        uint32_t x8[NRG][UM];
 #pragma unroll
-        for (int u = 0; u < kMaxU; ++u) {
-            const int j = li + G * u;
-            if (u < r.U && j < d4) {
-                float4 x;
+        for (int g = 0; g < NRG; ++g) {
+            const int64_t rw = base + (int64_t)g * R + slot;
+            id[g] = rw < re ? cq[rw] : 0u;
+            valid[g] = rw < re && id[g] < r.n;   // ids outside [0, n) are ignored
+            id[g] = valid[g] ? id[g] : 0u;
+        }
+#pragma unroll
+        for (int g = 0; g < NRG; ++g) {
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+                const int j = li + G * u;
+                const bool in = u < r.U && j < d4;
                 if constexpr (ROWS8) {
-                    const uint32_t b = xr8[j];
-                    x = make_float4((float)(b & 0xffu), (float)((b >> 8) & 0xffu), (float)((b >> 16) & 0xffu),
-                                    (float)(b >> 24));
+                    x8[g][u] = in ? reinterpret_cast<const uint32_t *>(r.X8 + (int64_t)id[g] * r.d)[j] : 0u;
                 } else {
-                    x = xr[j];
+                    x[g][u] = in ? reinterpret_cast<const float4 *>(r.X + (int64_t)id[g] * r.d)[j]
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                float t;
-                t = x.x - qr[u].x; acc = fmaf(t, t, acc);
-                t = x.y - qr[u].y; acc = fmaf(t, t, acc);
-                t = x.z - qr[u].z; acc = fmaf(t, t, acc);
-                t = x.w - qr[u].w; acc = fmaf(t, t, acc);
             }
         }
-        for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        const uint64_t key = valid ? (((uint64_t)__float_as_uint(acc) << 32) | id) : ~0ull;
-        for (int s = 0; s < R; ++s) topk_insert(best, shfl64(key, s * G), k, lane);
+        uint64_t key[NRG];
+#pragma unroll
+        for (int g = 0; g < NRG; ++g) {
+            float acc = 0.f;
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+                const int j = li + G * u;
+                if (u < r.U && j < d4) {
+                    float4 xv;
+                    if constexpr (ROWS8) {
+                        const uint32_t b = x8[g][u];
+                        xv = make_float4((float)(b & 0xffu), (float)((b >> 8) & 0xffu), (float)((b >> 16) & 0xffu),
+                                         (float)(b >> 24));
+                    } else {
+                        xv = x[g][u];
+                    }
+                    float t;
+                    t = xv.x - qr[u].x; acc = fmaf(t, t, acc);
+                    t = xv.y - qr[u].y; acc = fmaf(t, t, acc);
+                    t = xv.z - qr[u].z; acc = fmaf(t, t, acc);
+                    t = xv.w - qr[u].w; acc = fmaf(t, t, acc);
+                }
+            }
+            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+            key[g] = valid[g] ? (((uint64_t)__float_as_uint(acc) << 32) | id[g]) : ~0ull;
+        }
+#pragma unroll
+        for (int g = 0; g < NRG; ++g) {
+            const uint64_t kth = shfl64(best, k - 1);   // every lane takes part in the shuffle
+            uint64_t m = __ballot(li == 0 && key[g] < kth);
+            while (m != 0ull) {
+                const int src = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                topk_insert(best, shfl64(key[g], src), k, lane);
+            }
+        }
     }
     if (lane < k) wl[wv][lane] = best;
     __syncthreads();
@@ -584,11 +624,11 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     }
 }
 
-template <int NT, bool ROWS8>
+template <int NT, bool ROWS8, int UM>
 __global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
     const int items = pass_nq(r.nq_dev, r.q_base, r.nq) * r.parts;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        rerank_item<NT, ROWS8>(r, item);
+        rerank_item<NT, ROWS8, UM>(r, item);
         __syncthreads();
     }
 }
@@ -695,8 +735,14 @@ Launch plan_rerank(const RerankPass &r, int cap) {
     L.lds = 0;
     L.grid = dim3(grid_for((int64_t)r.nq * r.parts, cap));
     L.block = dim3(256);
-    L.func = r.X8 ? reinterpret_cast<const void *>(&k_rerank<256, true>)
-                  : reinterpret_cast<const void *>(&k_rerank<256, false>);
+    // the smallest slice bound that holds U (U <= kMaxU = 8)
+    const int um = r.U <= 2 ? 2 : (r.U <= 4 ? 4 : 8);
+    if (r.X8) L.func = um == 2 ? reinterpret_cast<const void *>(&k_rerank<256, true, 2>)
+                     : um == 4 ? reinterpret_cast<const void *>(&k_rerank<256, true, 4>)
+                               : reinterpret_cast<const void *>(&k_rerank<256, true, 8>);
+    else L.func = um == 2 ? reinterpret_cast<const void *>(&k_rerank<256, false, 2>)
+                : um == 4 ? reinterpret_cast<const void *>(&k_rerank<256, false, 4>)
+                          : reinterpret_cast<const void *>(&k_rerank<256, false, 8>);
     return L;
 }
 
