@@ -234,6 +234,7 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         qp.B = b->B;
         qp.k = b->k;
         qp.runs_per_sub = runs_per_sub(ix->ns);
+        qp.tgroups = tile_groups(qp.nq, ix->P);
         qp.nq_dev = b->nq_dev;
         qp.q_base = c * b->C;
         qp.cells = b->cells; qp.ncells = b->ncells; qp.aprime = b->aprime; qp.hist = b->hist; qp.lvl = b->lvl;

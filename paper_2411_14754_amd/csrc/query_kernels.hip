@@ -236,110 +236,124 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
 }
 
 // =============================================================== collide ==
-// Block per (query, tile).  The tile's TILE scores live in LDS as bytes packed
-// in 32-bit words; each point id occurs once per subspace, so a 32-bit LDS
-// atomic add of 1 << 8*(id & 3) increments exactly one byte without carry
-// (scores never exceed ns <= 127).  The activated cells of all subspaces are
-// runs of contiguous ids inside the tile (ids are stored tile-major).  The
-// block loads up to NT run descriptors at once into LDS (one thread per run),
-// scans their lengths, and then the threads take the flattened ids of all
-// those runs, kCollideUnroll at a time with their loads issued together, each
-// finding its run by a binary search over the run prefix.
+// Block per (query, group of tiles): the block takes the tiles p = g, g + S,
+// g + 2S, ... of its query (S = tile groups per query) one after another.  A
+// tile's TILE scores live in LDS as bytes packed in 32-bit words; each point
+// id occurs once per subspace, so a 32-bit LDS atomic add of 1 << 8*(id & 3)
+// increments exactly one byte without carry (scores never exceed ns <= 127).
+// The LDS scores are zeroed once per block and cleared after every tile (only
+// the touched words when they were listed), so later tiles start from zero.
+// The activated cells of all subspaces are runs of contiguous ids inside the
+// tile (ids are stored tile-major).  The block loads up to NT run descriptors
+// at once into LDS (one thread per run), scans their lengths, and then the
+// threads take the flattened ids of all those runs, kCollideUnroll at a time
+// with their loads issued together, each finding its run by a binary search
+// over the run prefix.  A query's first batch of cells is read once and kept
+// in registers for all its tiles.
 // The block then counts G[t] = #{score >= t} with 7-bit SWAR compares and
 // lists every point of non-zero score, as its tile-local id, grouped by score
 // level in descending order: level s occupies [G[s+1], G[s]) of the tile's
 // list.  Points of score 0 are not written; the dense scores are written only
 // when asked for.
 // Words of the tile touched by the counting are listed as they are first
-// incremented (a wave appends its first touches with one atomic), so the two
-// passes after the counting visit only those words; when more than
-// kTouchCap words are touched the passes scan the whole tile instead.
+// incremented (a wave appends its first touches with one atomic), so the
+// passes after the counting visit only those words; when more than kTouchCap
+// words are touched the passes scan the whole tile instead.
 constexpr int kCollideUnroll = 4;
 constexpr int kTouchCap = 4096;
 
 template <int NT>
-__device__ __forceinline__ void collide_item(const QueryPass &a, const int item) {
-    extern __shared__ uint32_t sc[];   // TILE/4 words
-    __shared__ uint32_t G[kMaxNs + 2];
-    __shared__ uint32_t cur[kMaxNs + 2];
-    __shared__ int64_t rstart[NT];          // start of each run in ids16
-    __shared__ uint32_t rpre[NT];           // ids before each run in the batch
-    __shared__ uint32_t red[NT / kWave + 1];
-    __shared__ uint16_t touched[kTouchCap];
-    __shared__ uint32_t n_touched;
-    const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
-    const int p = item % P, ql = item / P;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    const uint64_t lanes_below = (1ull << lane) - 1ull;
-    const int words = TILE >> 2;
-    for (int w = tid; w < words; w += NT) sc[w] = 0u;
-    for (int t = tid; t < ns + 2; t += NT) G[t] = 0u;
-    if (tid == 0) n_touched = 0u;
-    // thread -> (subspace i, run slot jj): a batch takes runs jb..jb+RJ-1 of every subspace
-    const int RJ = a.runs_per_sub;
-    const int i = tid / RJ, jj = tid - i * RJ;
-    const bool has_i = i < ns;
-    const int my_nc = has_i ? a.ncells[ql * ns + i] : 0;
-    const uint16_t *my_cells = a.cells + ((int64_t)ql * ns + (has_i ? i : 0)) * K;
-    const uint32_t *to = a.ix.toffs + ((int64_t)(has_i ? i : 0) * P + p) * (K + 1);
-    for (int jb = 0; __syncthreads_or(jb < my_nc); jb += RJ) {
-        const int j = jb + jj;
-        uint32_t len = 0;
-        int64_t st = 0;
-        if (has_i && j < my_nc) {
-            const int c = my_cells[j];
-            const uint32_t s = to[c];
-            len = to[c + 1] - s;
-            st = (int64_t)i * P * TILE + s;
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<NT>(len, red, &tot);
-        rstart[tid] = st;
-        rpre[tid] = ex;
-        __syncthreads();
-        for (uint32_t e0 = 0; e0 < tot; e0 += NT * kCollideUnroll) {
-            uint32_t lid[kCollideUnroll];
+struct CollideLds {
+    uint32_t G[kMaxNs + 2];
+    uint32_t cur[kMaxNs + 2];
+    int64_t rstart[NT];          // start of each run in ids16
+    uint32_t rpre[NT];           // ids before each run in the batch
+    uint32_t red[NT / kWave + 1];
+    uint16_t touched[kTouchCap];
+    uint32_t n_touched;
+};
+
+// Scan one run per thread (length len at ids16 offset st) into the block's run
+// table; returns the batch's id count.  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ uint32_t collide_runs(CollideLds<NT> &L, uint32_t len, int64_t st) {
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<NT>(len, L.red, &tot);
+    L.rstart[threadIdx.x] = st;
+    L.rpre[threadIdx.x] = ex;
+    __syncthreads();
+    return tot;
+}
+
+// Issue the loads of ids e0 + u*NT + tid (u < kCollideUnroll) of the run table;
+// bit u of the result says whether slot u holds an id.  Each id finds its run
+// by binary search.  The loads are unconditional (an empty slot reads entry 0)
+// so that no later instruction has to wait for them before they are used.
+template <int NT>
+__device__ __forceinline__ uint32_t collide_fetch(const QueryPass &a, const CollideLds<NT> &L, uint32_t e0,
+                                                  uint32_t tot, uint32_t (&lid)[kCollideUnroll]) {
+    uint32_t vm = 0u;
 #pragma unroll
-            for (int u = 0; u < kCollideUnroll; ++u) {
-                const uint32_t e = e0 + (uint32_t)(u * NT + tid);
-                lid[u] = 0xffffffffu;
-                if (e < tot) {
-                    int lo = 0, hi = NT - 1;           // run: largest j with rpre[j] <= e
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (rpre[mid] <= e) lo = mid; else hi = mid - 1;
-                    }
-                    lid[u] = a.ix.ids16[rstart[lo] + (e - rpre[lo])];
-                }
+    for (int u = 0; u < kCollideUnroll; ++u) {
+        const uint32_t e = e0 + (uint32_t)(u * NT + threadIdx.x);
+        int64_t at = 0;
+        if (e < tot) {
+            int lo = 0, hi = NT - 1;           // run: largest j with rpre[j] <= e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.rpre[mid] <= e) lo = mid; else hi = mid - 1;
             }
-#pragma unroll
-            for (int u = 0; u < kCollideUnroll; ++u) {
-                const bool v = lid[u] != 0xffffffffu;
-                uint32_t old = 1u;
-                if (v) old = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
-                const bool first = v && old == 0u;
-                const uint64_t m = __ballot(first);
-                if (m != 0ull) {
-                    const int leader = __ffsll((unsigned long long)m) - 1;
-                    uint32_t base = 0u;
-                    if (lane == leader) base = atomicAdd(&n_touched, (uint32_t)__popcll(m));
-                    base = __shfl(base, leader, kWave);
-                    if (first) {
-                        const uint32_t pos = base + (uint32_t)__popcll(m & lanes_below);
-                        if (pos < (uint32_t)kTouchCap) touched[pos] = (uint16_t)(lid[u] >> 2);
-                    }
-                }
-            }
+            at = L.rstart[lo] + (e - L.rpre[lo]);
+            vm |= 1u << u;
         }
-        __syncthreads();
+        lid[u] = a.ix.ids16[at];
     }
-    const uint32_t nt = n_touched;
+    return vm;
+}
+
+// +1 on the scores of the fetched ids; words touched for the first time are listed.
+template <int NT>
+__device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, const uint32_t (&lid)[kCollideUnroll],
+                                              const uint32_t vm) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int u = 0; u < kCollideUnroll; ++u) {
+        const bool v = (vm >> u) & 1u;
+        uint32_t old = 1u;
+        if (v) old = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
+        const bool first = v && old == 0u;
+        const uint64_t m = __ballot(first);
+        if (m != 0ull) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t base = 0u;
+            if (lane == leader) base = atomicAdd(&L.n_touched, (uint32_t)__popcll(m));
+            base = __shfl(base, leader, kWave);
+            if (first) {
+                const uint32_t pos = base + (uint32_t)__popcll(m & lanes_below);
+                if (pos < (uint32_t)kTouchCap) L.touched[pos] = (uint16_t)(lid[u] >> 2);
+            }
+        }
+    }
+}
+
+// After the counting of tile p: tile histogram, level lists, optional dense
+// scores; then the scores, G and the touched list are reset for the next tile.
+// Starts and ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
+                                               const int p) {
+    const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int words = TILE >> 2;
+    __syncthreads();
+    const uint32_t nt = L.n_touched;
     const bool sparse = nt <= (uint32_t)kTouchCap;
     const int nw = sparse ? (int)nt : words;
     for (int t0 = 1; t0 <= ns; t0 += 8) {
         uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int j = tid; j < nw; j += NT) {
-            const int w = sparse ? (int)touched[j] : j;
+            const int w = sparse ? (int)L.touched[j] : j;
             const uint32_t x = sc[w];
             if (x == 0u) continue;
 #pragma unroll
@@ -350,22 +364,22 @@ __device__ __forceinline__ void collide_item(const QueryPass &a, const int item)
         for (int u = 0; u < 8; ++u) {
             if (t0 + u <= ns) {
                 const uint32_t s = wave_sum(c[u]);
-                if (lane == 0) atomicAdd(&G[t0 + u], s);
+                if (lane == 0) atomicAdd(&L.G[t0 + u], s);
             }
         }
     }
     __syncthreads();
-    for (int t = tid; t <= ns; t += NT) cur[t] = G[t + 1];
+    for (int t = tid; t <= ns; t += NT) L.cur[t] = L.G[t + 1];
     __syncthreads();
     uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
     for (int j = tid; j < nw; j += NT) {
-        const int w = sparse ? (int)touched[j] : j;
+        const int w = sparse ? (int)L.touched[j] : j;
         const uint32_t x = sc[w];
         if (x == 0u) continue;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t s = (x >> (8 * u)) & 0xffu;
-            if (s != 0u) seg[atomicAdd(&cur[s], 1u)] = (uint16_t)(4 * w + u);
+            if (s != 0u) seg[atomicAdd(&L.cur[s], 1u)] = (uint16_t)(4 * w + u);
         }
     }
     if (a.scores != nullptr) {
@@ -376,17 +390,122 @@ __device__ __forceinline__ void collide_item(const QueryPass &a, const int item)
     const int64_t t0 = (int64_t)p * TILE;
     const int64_t valid = a.ix.n - t0 < TILE ? a.ix.n - t0 : TILE;
     uint32_t *h = a.hist + ((int64_t)ql * P + p) * (ns + 2);
-    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : G[t];
+    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : L.G[t];
+    __syncthreads();
+    if (sparse) {
+        for (int j = tid; j < (int)nt; j += NT) sc[L.touched[j]] = 0u;
+    } else {
+        uint4 *z = reinterpret_cast<uint4 *>(sc);
+        for (int w = tid; w < (words >> 2); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    for (int t = tid; t < ns + 2; t += NT) L.G[t] = 0u;
+    if (tid == 0) L.n_touched = 0u;
+    __syncthreads();
 }
 
-// Items are (query, tile) with the tile fastest; a grid that is a multiple of
-// P keeps every tile on the same XCD (blocks are dealt to XCDs round-robin).
+// One tile with any number of run batches (a subspace with more activated
+// cells than one batch holds): runs are reloaded batch by batch.
+template <int NT>
+__device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
+                                             const int p, const int my_nc, const int c_first) {
+    const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
+    const int RJ = a.runs_per_sub;
+    const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
+    const bool has_i = i < ns;
+    const uint16_t *my_cells = a.cells + ((int64_t)ql * ns + (has_i ? i : 0)) * K;
+    const uint32_t *to = a.ix.toffs + ((int64_t)(has_i ? i : 0) * P + p) * (K + 1);
+    for (int jb = 0; __syncthreads_or(jb < my_nc); jb += RJ) {
+        const int j = jb + jj;
+        uint32_t len = 0;
+        int64_t st = 0;
+        if (has_i && j < my_nc) {
+            const int c = jb == 0 ? c_first : (int)my_cells[j];
+            const uint32_t s = to[c];
+            len = to[c + 1] - s;
+            st = (int64_t)i * P * TILE + s;
+        }
+        const uint32_t tot = collide_runs<NT>(L, len, st);
+        for (uint32_t e0 = 0; e0 < tot; e0 += NT * kCollideUnroll) {
+            uint32_t lid[kCollideUnroll];
+            const uint32_t vm = collide_fetch<NT>(a, L, e0, tot, lid);
+            collide_count<NT>(L, sc, lid, vm);
+        }
+        __syncthreads();
+    }
+    collide_finish<NT>(a, L, sc, ql, p);
+}
+
+// The tiles of one (query, tile group) when every subspace's activated cells
+// fit one batch, as a two-stage pipeline: while tile p's histogram and level
+// lists are built, the ids of the group's next tile and the run offsets of the
+// one after it are already being loaded.  Those loads are unconditional (from
+// a valid tile when there is no next one) so the compiler has no reason to wait
+// for them before they are needed.
+template <int NT>
+__device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc,
+                                                        const int ql, const int g, const int my_nc, const int c_first) {
+    const int P = a.ix.P, K = a.ix.K, TILE = a.ix.TILE, S = a.tgroups;
+    const int RJ = a.runs_per_sub, ns = a.ix.ns;
+    const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
+    const bool has_run = i < ns && jj < my_nc;
+    const int ic = i < ns ? i : 0;
+    // run offsets of cell c_first (cell 0 of subspace 0 for threads without a run) in tile p
+    const uint32_t *tob = a.ix.toffs + (int64_t)ic * P * (K + 1) + c_first;
+    const int64_t rbase = (int64_t)ic * P * TILE;
+    uint32_t rs = tob[(int64_t)g * (K + 1)], re = tob[(int64_t)g * (K + 1) + 1];
+    uint32_t lid[kCollideUnroll];
+    uint32_t tot = collide_runs<NT>(L, has_run ? re - rs : 0u, rbase + rs);
+    uint32_t vm = collide_fetch<NT>(a, L, 0, tot, lid);
+    {
+        const int pn = g + S < P ? g + S : g;
+        rs = tob[(int64_t)pn * (K + 1)];
+        re = tob[(int64_t)pn * (K + 1) + 1];
+    }
+    for (int p = g; p < P; p += S) {
+        collide_count<NT>(L, sc, lid, vm);
+        for (uint32_t e0 = NT * kCollideUnroll; e0 < tot; e0 += NT * kCollideUnroll) {
+            vm = collide_fetch<NT>(a, L, e0, tot, lid);
+            collide_count<NT>(L, sc, lid, vm);
+        }
+        __syncthreads();
+        if (p + S < P) {
+            tot = collide_runs<NT>(L, has_run ? re - rs : 0u, rbase + rs);
+            vm = collide_fetch<NT>(a, L, 0, tot, lid);
+            const int pn = p + 2 * S < P ? p + 2 * S : p;
+            rs = tob[(int64_t)pn * (K + 1)];
+            re = tob[(int64_t)pn * (K + 1) + 1];
+        }
+        collide_finish<NT>(a, L, sc, ql, p);
+    }
+}
+
+// Items are (query, tile group); a grid smaller than the items strides over
+// them.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
-    const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * a.ix.P;
+    extern __shared__ uint32_t sc[];   // TILE/4 words
+    __shared__ CollideLds<NT> L;
+    const int S = a.tgroups;
+    const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * S;
+    if ((int)blockIdx.x >= items) return;
+    {
+        uint4 *z = reinterpret_cast<uint4 *>(sc);
+        for (int w = threadIdx.x; w < (a.ix.TILE >> 4); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
+        for (int t = threadIdx.x; t < a.ix.ns + 2; t += NT) L.G[t] = 0u;
+        if (threadIdx.x == 0) L.n_touched = 0u;
+    }
+    const int RJ = a.runs_per_sub, ns = a.ix.ns;
+    const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        collide_item<NT>(a, item);
-        __syncthreads();
+        const int ql = item / S, g = item - ql * S;
+        // this thread's subspace: activated cell count and its cell of the first batch
+        const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
+        const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
+        if (__syncthreads_or(my_nc > RJ)) {
+            for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first);
+        } else {
+            collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first);
+        }
     }
 }
 
@@ -712,10 +831,8 @@ Launch plan_activate(const QueryPass &p, int cap) {
 Launch plan_collide(const QueryPass &p, int cap) {
     Launch L;
     L.lds = (size_t)p.ix.TILE;
-    const int64_t items = (int64_t)p.nq * p.ix.P;
-    unsigned g = grid_for(items, cap);
-    if ((int64_t)g < items) g = std::max<unsigned>(1u, g / p.ix.P) * p.ix.P;   // whole tile rounds
-    L.grid = dim3(g);
+    const int64_t items = (int64_t)p.nq * p.tgroups;
+    L.grid = dim3(grid_for(items, cap));
     L.block = dim3(512);
     L.func = reinterpret_cast<const void *>(&k_collide<512>);
     return L;

@@ -327,6 +327,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         qp.alpha = alpha;
         qp.B = B;
         qp.runs_per_sub = runs_per_sub(ix->ns);
+        qp.tgroups = tile_groups(qp.nq, ix->P);
         qp.k = k;
         qp.cells = w.cells; qp.ncells = w.ncells; qp.aprime = w.aprime;
         qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
@@ -553,6 +554,7 @@ int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells
         qp.nq = cn;
         qp.B = B;
         qp.runs_per_sub = runs_per_sub(ix->ns);
+        qp.tgroups = tile_groups(qp.nq, ix->P);
         qp.k = k;
         qp.cells = const_cast<uint16_t *>(cells) + c0 * ix->ns * ix->K;
         qp.ncells = const_cast<int32_t *>(ncells) + c0 * ix->ns;

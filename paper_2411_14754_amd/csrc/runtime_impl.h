@@ -176,6 +176,13 @@ inline int runs_per_sub(int ns) {
     return r;
 }
 
+// tile groups per query for the collision step: enough blocks for the pass
+// (about 2048) while each block keeps as many tiles of one query as it can
+inline int tile_groups(int64_t nq, int P) {
+    const int64_t s = (2048 + std::max<int64_t>(nq, 1) - 1) / std::max<int64_t>(nq, 1);
+    return (int)std::clamp<int64_t>(s, 1, P);
+}
+
 struct RerankCfg { int G, U, parts; int64_t rpp; };
 
 // BF16 first pass: G lanes per row, U slices of 8 values per lane.

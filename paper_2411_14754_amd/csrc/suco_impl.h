@@ -40,6 +40,7 @@ struct QueryPass {
     int64_t B;
     int k;
     int runs_per_sub;         // collision step: runs of each subspace per batch (power of two)
+    int tgroups;              // collision step: tile groups per query (1..P), one block each
     const int *nq_dev;        // if set: the batch size is read here and this pass takes
     int q_base;               //   queries [q_base, q_base + nq) of it (nq is the capacity)
     // workspace
