@@ -464,17 +464,20 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
     for (int p = g; p < P; p += S) {
         collide_count<NT>(L, sc, lid, vm);
         for (uint32_t e0 = NT * kCollideUnroll; e0 < tot; e0 += NT * kCollideUnroll) {
-            vm = collide_fetch<NT>(a, L, e0, tot, lid);
-            collide_count<NT>(L, sc, lid, vm);
+            uint32_t lid2[kCollideUnroll];
+            const uint32_t vm2 = collide_fetch<NT>(a, L, e0, tot, lid2);
+            collide_count<NT>(L, sc, lid2, vm2);
         }
         __syncthreads();
-        if (p + S < P) {
-            tot = collide_runs<NT>(L, has_run ? re - rs : 0u, rbase + rs);
-            vm = collide_fetch<NT>(a, L, 0, tot, lid);
-            const int pn = p + 2 * S < P ? p + 2 * S : p;
-            rs = tob[(int64_t)pn * (K + 1)];
-            re = tob[(int64_t)pn * (K + 1) + 1];
-        }
+        // stage the next tile of the group (an empty one after the last) and
+        // prefetch the run offsets of the one after it; every load here is
+        // unconditional, so nothing waits for them before the next iteration
+        const bool more = p + S < P;
+        tot = collide_runs<NT>(L, (has_run && more) ? re - rs : 0u, rbase + rs);
+        vm = collide_fetch<NT>(a, L, 0, tot, lid);
+        const int pn = p + 2 * S < P ? p + 2 * S : p;
+        rs = tob[(int64_t)pn * (K + 1)];
+        re = tob[(int64_t)pn * (K + 1) + 1];
         collide_finish<NT>(a, L, sc, ql, p);
     }
 }
