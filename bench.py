@@ -85,23 +85,26 @@ def recall_at(ids, gt):
     return float(hit.float().mean() / k)
 
 
+KERNEL_SOURCES = ("query_kernels.hip", "bf16.hip", "wave.h", "suco_impl.h")
+
+
 def src_hash():
     h = hashlib.sha256()
-    for f in ("query_kernels.hip", "suco_impl.h"):
+    for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2411_14754_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs on this
+    workload, if they were taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     t = json.load(open(p))
     if t.get("src_hash") != src_hash():
         return None
-    e = t.get("kernels", {}).get(kernel)
+    e = t.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
     return None if e is None else e.get("bytes_per_launch")
 
 
@@ -245,7 +248,7 @@ def bench_bf16(args, log):
                  "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "gist_like")}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -431,7 +434,7 @@ def main():
     kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "sift_like")}
 
     # learned + batched: labels from plain sweeps on training queries, FP32
     # training, scale calibrated on held-out queries, then the evaluation queries
