@@ -390,7 +390,8 @@ def main():
     step_bytes = {
         "collide": 2.0 * aprime + 2.0 * U,           # u16 ids of activated cells read, non-zero-score ids written
         "select": 2.0 * ge_T + 4.0 * B,              # ids at or above the threshold read, candidates written
-        "rerank": 4.0 * B * d + 4.0 * B,             # candidate rows + candidate ids
+        # candidate rows (bytes when the index keeps a byte copy of X) + candidate ids
+        "rerank": (1.0 if ix.flags() & suco.INDEX_BYTE_ROWS else 4.0) * B * d + 4.0 * B,
     }
 
     def timed(fn, steps, warmup):
@@ -418,10 +419,11 @@ def main():
     stage = ix.profile_read()
     ix.profile(False)
     launches = stage["collide"][1] // args.steps
-    chunk = math.ceil(nq / max(1, launches))
     per_kernel = {}
     for s, (tms, cnt) in stage.items():
-        avg_ms = tms / max(1, cnt)
+        if cnt == 0:
+            continue
+        avg_ms = tms / cnt
         ent = {"avg_ms": round(avg_ms, 5), "launches": cnt,
                "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
         if s in step_bytes:
@@ -449,7 +451,9 @@ def main():
         m_tr = args.train_queries
         grid = learned.alpha_grid(0.0005, 0.05)
         net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
-        amin, amax = grid[0], grid[-1]
+        # the predicted alpha is clamped to [0.0005, 0.01]: above 0.01 recall barely moves (sweep) while a
+        # few very large alphas make a batch's slowest blocks much slower
+        amin, amax = grid[0], 0.01
         scale = learned.calibrate_scale(ix, net, Qt[m_tr:], gt_t[m_tr:], k, beta, args.target_recall, amin, amax)
         train_s = time.time() - t0
         log(f"learned budget: trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, "
@@ -521,7 +525,7 @@ def main():
                    "plain": {"alpha": alpha, "qps": round(plain_value, 1), "recall_at_10": round(plain_rec, 5),
                              "qps_at_recall_0.95_interp": None if qps_interp is None else round(qps_interp, 1)},
                    "learned": learned_info,
-                   "queries_per_pass": chunk, "index_build_s": round(build_s, 3), "sweep": sweep},
+                   "launches_per_step": launches, "index_build_s": round(build_s, 3), "sweep": sweep},
         "kernels": per_kernel,
         "roofline": roofline,
         "cpu_baseline": cpu,

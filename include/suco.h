@@ -117,6 +117,14 @@ SUCO_API int suco_index_export(const suco_index *ix, float *centroids, int32_t *
 /* Shape of an index; any output may be NULL. */
 SUCO_API int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, int32_t *sqrt_k);
 
+/* What the index keeps besides the FP32 data: bit SUCO_INDEX_BYTE_ROWS when the
+ * re-rank reads a byte copy of D (every coordinate an integer in 0..255, the
+ * default unless SUCO_BUILD_NO_BYTE_ROWS), bit SUCO_INDEX_BF16 when it was built
+ * with SUCO_BUILD_BF16.  flags: host int32. */
+#define SUCO_INDEX_BYTE_ROWS 1
+#define SUCO_INDEX_BF16 2
+SUCO_API int suco_index_flags(const suco_index *ix, int32_t *flags);
+
 /* Release an index (NULL is accepted).  Waits for its pending queries. */
 SUCO_API int suco_index_free(suco_index *ix);
 

@@ -26,7 +26,7 @@ EXPORTED = (
     "suco_batcher_free", "suco_mlp_num_params", "suco_mlp_create", "suco_mlp_set_norm", "suco_mlp_get_params",
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
-    "suco_query_bf16", "suco_query_bf16_debug",
+    "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors")
@@ -46,6 +46,7 @@ class BuildParams(C.Structure):
 BUILD_NO_BYTE_ROWS = 1
 BUILD_BF16 = 2
 BF16_S1 = 1
+INDEX_BYTE_ROWS, INDEX_BF16 = 1, 2
 
 
 _lib = None
@@ -72,6 +73,7 @@ def lib():
         L.suco_index_export.argtypes = [P, P, P]
         L.suco_index_info.argtypes = [P, P, P, P, P]
         L.suco_index_free.argtypes = [P]
+        L.suco_index_flags.argtypes = [P, P]
         L.suco_query.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
         L.suco_query_alpha.argtypes = [P, P, i64, i32, P, dbl, P, P, P]
         L.suco_query_debug.argtypes = [P, P, i64, i32, P, dbl, dbl, P, P, P, P, P, P, P, P, P]
@@ -204,6 +206,12 @@ class Index:
         cnt = np.zeros(len(STAGES), np.int64)
         _check(lib().suco_profile_read(self._h, ms.ctypes.data_as(P), cnt.ctypes.data_as(P)))
         return {s: (float(ms[j]), int(cnt[j])) for j, s in enumerate(STAGES)}
+
+    def flags(self) -> int:
+        """INDEX_BYTE_ROWS | INDEX_BF16 bits (see suco_index_flags)."""
+        f = C.c_int32(0)
+        _check(lib().suco_index_flags(self._h, C.byref(f)))
+        return int(f.value)
 
     def export(self):
         cent = np.zeros(self.sqrt_k * self.d, np.float32)

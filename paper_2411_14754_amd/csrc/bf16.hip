@@ -143,6 +143,7 @@ __global__ __launch_bounds__(512) void k_centre_dists_bf16(CentreBf16Pass p) {
 // bounds d~ + e (bits << 32 | id), kept per wave as in the FP32 re-rank.
 __global__ __launch_bounds__(256) void k_rerank_bf16(Bf16RerankPass r) {
     __shared__ uint64_t wl[4][kMaxK];
+    __shared__ uint32_t cid[kRowChunk];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int G = r.G, R = kWave / G, li = lane & (G - 1), slot = lane / G;
     const int d8 = r.d >> 3, k = r.k;
@@ -162,10 +163,17 @@ __global__ __launch_bounds__(256) void k_rerank_bf16(Bf16RerankPass r) {
         const int64_t rb = (int64_t)part * r.rows_per_part;
         const int64_t re = rb + r.rows_per_part < r.B ? rb + r.rows_per_part : r.B;
         const uint32_t *cq = r.cand + (int64_t)ql * r.B;
-        for (int64_t base = rb + (int64_t)wv * R; base < re; base += 4 * (int64_t)R) {
-            const int64_t rw = base + slot;
-            uint32_t id = rw < re ? cq[rw] : 0u;
-            const bool valid = rw < re && id < r.n;
+        // candidate ids staged in LDS a chunk at a time (see the FP32 re-rank)
+        for (int64_t cb = rb; cb < re; cb += kRowChunk) {
+        const int cn = (int)(re - cb < kRowChunk ? re - cb : kRowChunk);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += 256) cid[t] = cq[cb + t];
+        __syncthreads();
+        for (int base = wv * R; base < cn; base += 4 * R) {
+            const int lr = base + slot;
+            const int64_t rw = cb + lr;
+            uint32_t id = lr < cn ? cid[lr] : 0u;
+            const bool valid = lr < cn && id < r.n;
             id = valid ? id : 0u;
             const uint4 *xr = reinterpret_cast<const uint4 *>(r.Xb + (int64_t)id * r.d);
             uint4 xs[kMaxU16];
@@ -203,6 +211,7 @@ __global__ __launch_bounds__(256) void k_rerank_bf16(Bf16RerankPass r) {
                 m &= m - 1ull;
                 topk_insert(best, shfl64(key, src), k, lane);
             }
+        }
         }
         if (lane < k) wl[wv][lane] = best;
         __syncthreads();

@@ -669,16 +669,24 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     const int64_t rows = r.rows_dev ? (r.rows_dev[ql] < r.B ? (int64_t)r.rows_dev[ql] : r.B) : r.B;
     const int64_t re = rb + r.rows_per_part < rows ? rb + r.rows_per_part : rows;
     const uint32_t *cq = r.cand + (int64_t)ql * r.B;
-    for (int64_t base = rb + (int64_t)wv * R * NRG; base < re; base += (int64_t)(NT / kWave) * R * NRG) {
+    // candidate ids are staged in LDS a chunk at a time (one coalesced read),
+    // so each row's load depends on an LDS read rather than a global one
+    __shared__ uint32_t cid[kRowChunk];
+    for (int64_t cb = rb; cb < re; cb += kRowChunk) {
+    const int cn = (int)(re - cb < kRowChunk ? re - cb : kRowChunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn; t += NT) cid[t] = cq[cb + t];
+    __syncthreads();
+    for (int base = wv * R * NRG; base < cn; base += (NT / kWave) * R * NRG) {
         uint32_t id[NRG];
         bool valid[NRG];
         float4 x[NRG][UM];
         uint32_t x8[NRG][UM];
 #pragma unroll
         for (int g = 0; g < NRG; ++g) {
-            const int64_t rw = base + (int64_t)g * R + slot;
-            id[g] = rw < re ? cq[rw] : 0u;
-            valid[g] = rw < re && id[g] < r.n;   // ids outside [0, n) are ignored
+            const int rw = base + g * R + slot;
+            id[g] = rw < cn ? cid[rw] : 0u;
+            valid[g] = rw < cn && id[g] < r.n;   // ids outside [0, n) are ignored
             id[g] = valid[g] ? id[g] : 0u;
         }
 #pragma unroll
@@ -731,6 +739,7 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
                 topk_insert(best, shfl64(key[g], src), k, lane);
             }
         }
+    }
     }
     if (lane < k) wl[wv][lane] = best;
     __syncthreads();

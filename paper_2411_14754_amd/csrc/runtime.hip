@@ -476,6 +476,13 @@ int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, 
     return SUCO_OK;
 }
 
+int suco_index_flags(const suco_index *ix, int32_t *flags) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (!flags) return fail(SUCO_E_INVAL, "flags must not be NULL");
+    *flags = (ix->X8 ? SUCO_INDEX_BYTE_ROWS : 0) | (ix->Xb ? SUCO_INDEX_BF16 : 0);
+    return SUCO_OK;
+}
+
 int suco_index_free(suco_index *ix) {
     if (!ix) return SUCO_OK;
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");

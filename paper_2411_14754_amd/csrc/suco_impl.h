@@ -11,6 +11,7 @@ constexpr int kMaxSqrtK = 128;   // LDS tables of the activation step are sized 
 constexpr int kMaxNs = 127;      // SC-scores are bytes counted with 7-bit SWAR compares
 constexpr int kMaxK = 64;        // one result per lane of a wave in the top-k lists
 constexpr int kMaxU = 8;         // float4 slices of a row per lane in the re-rank
+constexpr int kRowChunk = 1024;  // candidate ids staged in LDS at a time by the re-rank kernels
 
 struct HalfDims {
     int dim0;  // first dimension of the half
