@@ -57,19 +57,22 @@ def exact_topk(Xd, Qd, k, chunk=256):
     return torch.cat(out).to(torch.int32)
 
 
-def exact_topk_float(Xd, Qd, k, extra=64, chunk=128):
+def exact_topk_float(Xd, Qd, k, extra=64, chunk=None):
     """Exact k-NN ids by (squared distance, id) for real-valued data: the FP32
     product-form distances shortlist k + extra points per query, whose
     distances are then recomputed in FP64 from the rows and sorted by
     (distance, id).  The shortlist is exact unless the FP32 form misorders a
     true neighbour past `extra` others, far beyond its rounding error here."""
     import torch
+    if chunk is None:   # about 2 GiB of FP32 distances per block of queries
+        chunk = max(1, min(512, (1 << 29) // Xd.shape[0]))
     xn = (Xd * Xd).sum(dim=1)
     out = []
     for s in range(0, Qd.shape[0], chunk):
         q = Qd[s:s + chunk]
         d2 = xn[None, :] + (q * q).sum(dim=1)[:, None] - 2.0 * (q @ Xd.T)
         short = torch.topk(d2, k + extra, dim=1, largest=False).indices
+        del d2
         rows = Xd[short].double()
         e = ((rows - q.double()[:, None, :]) ** 2).sum(dim=2)
         order = torch.argsort(short, dim=1)                    # ties by id: sort ids first, stably by distance
@@ -281,11 +284,274 @@ def bench_bf16(args, log):
     ix.free()
 
 
+def timed_region(fn, steps, warmup):
+    """Milliseconds of `steps` calls of fn after `warmup` calls, HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def stage_profile(ix, fn, steps, step_bytes, nq):
+    """Per-step kernel times (suco_profile) over `steps` calls and GB/s for the steps with byte counts."""
+    ix.profile(True)
+    ix.profile_read()
+    for _ in range(steps):
+        fn()
+    stage = ix.profile_read()
+    ix.profile(False)
+    out = {}
+    tot = sum(v[0] for v in stage.values())
+    for name, (tms, cnt) in stage.items():
+        if cnt == 0:
+            continue
+        avg_ms = tms / cnt
+        ent = {"avg_ms": round(avg_ms, 5), "launches": cnt, "share": round(tms / max(1e-9, tot), 4)}
+        if name in step_bytes:
+            bytes_launch = step_bytes[name] * nq / max(1, cnt // steps)
+            ent["alg_bytes_per_launch"] = bytes_launch
+            ent["gbs"] = round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1)
+        out[name] = ent
+    return stage, out
+
+
+def oracle_baseline(X, Q, ns, sk, alpha, beta, k, sample, what):
+    """The FP64 oracle on its own 2-iteration index, timed on `sample` queries on the host."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=2, seed=1, nthreads=threads)
+    oix = oracle.Index(X, ns, sk, c32, asg)
+    t0 = time.time()
+    oix.query(Q[:sample], k, alpha, beta, nthreads=threads)
+    dt = time.time() - t0
+    return {"value": round(sample / dt, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of the {what} at alpha={alpha}, beta={beta}, k={k}; FP64 C oracle on its "
+                      f"own 2-iteration index, OpenMP over queries; {dt:.1f}s"}
+
+
+def step_bytes_for(ix, suco, Qs, k, alpha, beta, n, d):
+    """Algorithmic bytes per query of the counting, selection and re-rank steps (64-query sample)."""
+    import torch
+    o = ix.query_debug(Qs, k, alpha, beta, scores=True, cand=False, cells=False, feat=False)
+    torch.cuda.synchronize()
+    aprime = float(o["aprime"].double().sum(dim=1).mean())
+    sc = o["scores"]
+    U = float((sc > 0).sum(dim=1).double().mean())
+    B = suco.count_B(beta, n, k)
+    T = torch.sort(sc, dim=1, descending=True).values[:, B - 1:B]
+    ge_T = float((sc >= T).sum(dim=1).double().mean())
+    del o, sc
+    return {
+        "collide": 2.0 * aprime + 2.0 * U,
+        "select": 2.0 * ge_T + 4.0 * B,
+        "rerank": (1.0 if ix.flags() & suco.INDEX_BYTE_ROWS else 4.0) * B * d + 4.0 * B,
+    }
+
+
+def bench_batched_deep(args, log):
+    """Deep-like n=10,000,000 d=96 unit-norm rows, N_s=8 (12 dims), sqrtK=64, a stream of 100,000 queries
+    in uneven batches (sizes uniform in 1..4096), k=10, alpha=0.02, beta=0.002: the batched form (one HIP
+    graph per batch-size bucket, tuned launch shapes) against the plain path on the whole stream at once."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+
+    W = synth.Workload(4)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    alpha = args.alpha if args.alpha is not None else sp["alpha"]
+    log("generating data")
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1, tile_max=args.tile_max, query_chunk=args.query_chunk)
+    build_s = time.time() - t0
+    log(f"index built in {build_s:.2f}s")
+    n_gt = min(nq, 10_000)
+    gt = exact_topk_float(Xd, Qd[:n_gt], k)
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+
+    def plain():
+        ix.query(Qd, k, alpha, beta, out=(ids, dists))
+
+    ms_plain = timed_region(plain, args.steps, 1)
+    plain_ids, plain_d = ids.clone(), dists.clone()
+    rec_plain = recall_at(ids[:n_gt], gt)
+    log(f"plain: {ms_plain / args.steps:.2f} ms per 100,000 queries, recall@10={rec_plain:.4f}")
+    sizes = W.batch_sizes(nq)
+    b = suco.Batcher(ix, 4096, k, beta)
+
+    def stream():
+        s0 = 0
+        for sz in sizes:
+            b.query(Qd[s0:s0 + sz], alpha=alpha, out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+            s0 += sz
+
+    t0 = time.time()
+    stream()                                  # tunes every bucket met on first use
+    torch.cuda.synchronize()
+    tune_s = time.time() - t0
+    ms = timed_region(stream, args.steps, 1)
+    value = nq * args.steps / (ms / 1e3)
+    same = bool(torch.equal(ids, plain_ids) and torch.equal(dists, plain_d))
+    rec = recall_at(ids[:n_gt], gt)
+    log(f"batched stream of {len(sizes)} batches: {ms / args.steps:.2f} ms, {value:.0f} QPS, recall@10={rec:.4f}, "
+        f"bitwise equal to plain: {same}, tuning {tune_s:.1f}s")
+    tuned = {}
+    for j in range(13):
+        try:
+            tuned[str(1 << j)] = b.tuning(1 << j)
+        except suco.SucoError:
+            pass                               # bucket never used by this stream
+    b.free()
+    sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
+    stage, per_kernel = stage_profile(ix, plain, 1, sb, nq)
+    dom = max(sb, key=lambda t: stage[t][0])
+    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    achieved = per_kernel[dom]["gbs"]
+    roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "deep_like")}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "100,000 queries")
+    line = {
+        "metric": "QPS of a stream of uneven batches, Deep-like n=10M d=96: batched persistent SuCo on 1 GPU",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"deep_like n={n} d={d} unit-norm, N_s={ns}, sqrtK={sk}, nq={nq} in {len(sizes)} "
+                               f"batches of 1..4096, k={k}, alpha={alpha}, beta={beta}",
+                   "form": "batched", "recall_at_10_first_10000": round(rec, 5), "bitwise_equal_plain": same,
+                   "plain_one_call": {"qps": round(nq * args.steps / (ms_plain / 1e3), 1),
+                                      "recall_at_10_first_10000": round(rec_plain, 5)},
+                   "tuning_s": round(tune_s, 2), "tuned": tuned,
+                   "index_build_s": round(build_s, 3)},
+        "kernels": per_kernel, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ix.free()
+
+
+def bench_learned_lifted(args, log):
+    """Lifted n=10,000,000 d=256, N_s=16, sqrtK=64, k=10, beta=0.003: the learned budget (trained on
+    generated queries labelled by plain sweeps against exact top-10) evaluated on 10,000 held-out queries,
+    in one call and as a stream of uneven batches, against plain SuCo at equal recall."""
+    import torch
+    import paper_2411_14754_amd as suco
+    from paper_2411_14754_amd import learned
+    import synth
+
+    W = synth.Workload(5)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    log("generating data")
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1, tile_max=args.tile_max, query_chunk=args.query_chunk)
+    build_s = time.time() - t0
+    log(f"index built in {build_s:.2f}s")
+    gt = exact_topk_float(Xd, Qd, k)
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    sweep = []
+    for a in (0.0005, 0.001, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.02, 0.03):
+        ms_a = timed_region(lambda: ix.query(Qd, k, a, beta, out=(ids, dists)), 1, 1)
+        r = recall_at(ids, gt)
+        sweep.append({"alpha": a, "recall": round(r, 5), "qps": round(nq / (ms_a / 1e3), 1)})
+        log(f"plain alpha={a}: recall@10={r:.4f} qps={nq / (ms_a / 1e3):.0f}")
+    ok = [e for e in sweep if e["recall"] >= TARGET_RECALL]
+    alpha = ok[0]["alpha"] if ok else sweep[-1]["alpha"]
+    ms_plain = timed_region(lambda: ix.query(Qd, k, alpha, beta, out=(ids, dists)), args.steps, 1)
+    rec_plain = recall_at(ids, gt)
+    m_tr, m_val = args.lifted_train, 10_000
+    log(f"labelling {m_tr} training queries")
+    t0 = time.time()
+    Qt = torch.from_numpy(W.train_queries(m_tr + m_val)).cuda()
+    gt_t = exact_topk_float(Xd, Qt, k)
+    grid = learned.alpha_grid(0.0005, 0.03)
+    net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
+    amin, amax = grid[0], grid[-1]
+    scale = learned.calibrate_scale(ix, net, Qt[m_tr:], gt_t[m_tr:], k, beta, args.target_recall, amin, amax)
+    train_s = time.time() - t0
+    log(f"trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, scale {scale:.3f}")
+    ms_l1 = timed_region(lambda: suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax, out=(ids, dists)),
+                         args.steps, 1)
+    rec_l1 = recall_at(ids, gt)
+    _, _, au = suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax)
+    mean_alpha = float(au.double().mean())
+    b = suco.Batcher(ix, 4096, k, beta)
+    b.set_model(net, scale, amin, amax)
+    sizes = W.batch_sizes(nq)
+
+    def stream():
+        s0 = 0
+        for sz in sizes:
+            b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+            s0 += sz
+
+    stream()
+    ms = timed_region(stream, args.steps, 1)
+    value = nq * args.steps / (ms / 1e3)
+    rec = recall_at(ids, gt)
+    b.free()
+    plain_eq = None
+    for lo, hi in zip(sweep, sweep[1:]):
+        if lo["recall"] < rec <= hi["recall"]:
+            f = (rec - lo["recall"]) / (hi["recall"] - lo["recall"])
+            plain_eq = math.exp(math.log(lo["qps"]) + f * (math.log(hi["qps"]) - math.log(lo["qps"])))
+    log(f"learned one call {nq * args.steps / (ms_l1 / 1e3):.0f} QPS recall {rec_l1:.4f}; learned+batched "
+        f"{value:.0f} QPS recall {rec:.4f} (mean alpha {mean_alpha:.5f}); plain at that recall {plain_eq}")
+    sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
+    stage, per_kernel = stage_profile(ix, lambda: ix.query(Qd, k, alpha, beta, out=(ids, dists)), 1, sb, nq)
+    dom = max(sb, key=lambda t: stage[t][0])
+    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    achieved = per_kernel[dom]["gbs"]
+    roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "lifted256")}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "10,000 queries")
+    line = {
+        "metric": "QPS at recall@10=0.95, lifted n=10M d=256: learned+batched vs plain SuCo on 1 GPU",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"lifted256 n={n} d={d}, N_s={ns}, sqrtK={sk}, nq={nq}, k={k}, beta={beta}",
+                   "form": "learned+batched", "recall_at_10": round(rec, 5), "mean_alpha": round(mean_alpha, 6),
+                   "learned_one_call": {"qps": round(nq * args.steps / (ms_l1 / 1e3), 1), "recall_at_10": round(rec_l1, 5)},
+                   "plain": {"alpha": alpha, "qps": round(nq * args.steps / (ms_plain / 1e3), 1),
+                             "recall_at_10": round(rec_plain, 5),
+                             "qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1)},
+                   "train_queries": m_tr, "val_queries": m_val, "epochs": args.epochs, "scale": round(scale, 5),
+                   "train_s": round(train_s, 1), "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)],
+                   "index_build_s": round(build_s, 3), "sweep": sweep},
+        "kernels": per_kernel, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    net.free()
+    ix.free()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("sift_like", "gist_like"), default="sift_like",
-                    help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split precision")
+    ap.add_argument("--workload", choices=("sift_like", "gist_like", "deep_like", "lifted256"), default="sift_like",
+                    help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split "
+                         "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=512)
@@ -298,6 +564,7 @@ def main():
     ap.add_argument("--train-queries", type=int, default=20_000)
     ap.add_argument("--val-queries", type=int, default=10_000)
     ap.add_argument("--epochs", type=int, default=25)
+    ap.add_argument("--lifted-train", type=int, default=200_000, help="training queries of the lifted256 mode")
     ap.add_argument("--target-recall", type=float, default=0.951)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "
@@ -323,6 +590,12 @@ def main():
 
     if args.workload == "gist_like":
         bench_bf16(args, log)
+        return
+    if args.workload == "deep_like":
+        bench_batched_deep(args, log)
+        return
+    if args.workload == "lifted256":
+        bench_learned_lifted(args, log)
         return
 
     import torch

@@ -62,6 +62,35 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
     return base + x - v;
 }
 
+// Two exclusive prefixes at once (one pass of barriers); *ta, *tb get the sums.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint32_t *red2, uint32_t *ea,
+                                                 uint32_t *eb, uint32_t *ta, uint32_t *tb) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t xa = va, xb = vb;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t ya = __shfl_up(xa, o, kWave), yb = __shfl_up(xb, o, kWave);
+        if (lane >= o) { xa += ya; xb += yb; }
+    }
+    __syncthreads();
+    if (lane == kWave - 1) { red2[2 * w] = xa; red2[2 * w + 1] = xb; }
+    __syncthreads();
+    uint32_t ba = 0, bb = 0, sa = 0, sb = 0;
+#pragma unroll
+    for (int j = 0; j < NT / kWave; ++j) {
+        const uint32_t ra = red2[2 * j], rb = red2[2 * j + 1];
+        ba += (j < w) ? ra : 0u;
+        bb += (j < w) ? rb : 0u;
+        sa += ra;
+        sb += rb;
+    }
+    *ea = ba + xa - va;
+    *eb = bb + xb - vb;
+    *ta = sa;
+    *tb = sb;
+}
+
 // A = max(1, ceil(alpha*n - 1e-9)), capped at n, in FP64 without contraction.
 __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
 #pragma clang fp contract(off)
@@ -261,49 +290,73 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
 // words are touched the passes scan the whole tile instead.
 constexpr int kCollideUnroll = 4;
 constexpr int kTouchCap = 4096;
+constexpr int kBucketShift = 6;     // run lookup table: one entry per 64 consecutive id positions
+constexpr int kBuckets = 1024;      // positions beyond kBuckets << kBucketShift use a binary search
 
 template <int NT>
 struct CollideLds {
     uint32_t G[kMaxNs + 2];
     uint32_t cur[kMaxNs + 2];
-    int64_t rstart[NT];          // start of each run in ids16
-    uint32_t rpre[NT];           // ids before each run in the batch
-    uint32_t red[NT / kWave + 1];
+    int64_t rstart[NT];          // start in ids16 of each non-empty run of the batch (compacted)
+    uint32_t rpre[NT];           // ids before each of those runs in the batch
+    uint32_t red[2 * (NT / kWave) + 2];
+    uint16_t first[kBuckets];    // run holding position b << kBucketShift
     uint16_t touched[kTouchCap];
     uint32_t n_touched;
 };
 
+struct RunBatch {
+    uint32_t tot;                // ids in the batch
+    int nr;                      // non-empty runs
+};
+
 // Scan one run per thread (length len at ids16 offset st) into the block's run
-// table; returns the batch's id count.  Ends with a barrier.
+// table: the non-empty runs are compacted in slot order, and a table gives for
+// every 64th position the run that holds it.  Ends with a barrier.
 template <int NT>
-__device__ __forceinline__ uint32_t collide_runs(CollideLds<NT> &L, uint32_t len, int64_t st) {
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<NT>(len, L.red, &tot);
-    L.rstart[threadIdx.x] = st;
-    L.rpre[threadIdx.x] = ex;
+__device__ __forceinline__ RunBatch collide_runs(CollideLds<NT> &L, uint32_t len, int64_t st) {
+    uint32_t ex, idx, tot, nr;
+    block_excl_scan2<NT>(len, len != 0u ? 1u : 0u, L.red, &ex, &idx, &tot, &nr);
+    if (len != 0u) {
+        L.rstart[idx] = st;
+        L.rpre[idx] = ex;
+        // table entries of the positions b << kBucketShift inside this run
+        const uint32_t bfirst = (ex + (1u << kBucketShift) - 1u) >> kBucketShift;
+        const uint32_t blast = (ex + len - 1u) >> kBucketShift;
+        for (uint32_t b = bfirst; b <= blast && b < (uint32_t)kBuckets; ++b) L.first[b] = (uint16_t)idx;
+    }
     __syncthreads();
-    return tot;
+    return RunBatch{tot, (int)nr};
 }
 
 // Issue the loads of ids e0 + u*NT + tid (u < kCollideUnroll) of the run table;
-// bit u of the result says whether slot u holds an id.  Each id finds its run
-// by binary search.  The loads are unconditional (an empty slot reads entry 0)
-// so that no later instruction has to wait for them before they are used.
+// bit u of the result says whether slot u holds an id.  An id's run is the
+// table's run for its 64-position bucket or one of the next few (runs are at
+// least one id long); past the table a binary search finds it.  The loads are
+// unconditional (an empty slot reads entry 0) so that no later instruction has
+// to wait for them before they are used.
 template <int NT>
 __device__ __forceinline__ uint32_t collide_fetch(const QueryPass &a, const CollideLds<NT> &L, uint32_t e0,
-                                                  uint32_t tot, uint32_t (&lid)[kCollideUnroll]) {
+                                                  RunBatch rb, uint32_t (&lid)[kCollideUnroll]) {
     uint32_t vm = 0u;
 #pragma unroll
     for (int u = 0; u < kCollideUnroll; ++u) {
         const uint32_t e = e0 + (uint32_t)(u * NT + threadIdx.x);
         int64_t at = 0;
-        if (e < tot) {
-            int lo = 0, hi = NT - 1;           // run: largest j with rpre[j] <= e
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (L.rpre[mid] <= e) lo = mid; else hi = mid - 1;
+        if (e < rb.tot) {
+            int m;
+            if ((e >> kBucketShift) < (uint32_t)kBuckets) {
+                m = L.first[e >> kBucketShift];
+                while (m + 1 < rb.nr && L.rpre[m + 1] <= e) ++m;
+            } else {
+                int lo = 0, hi = rb.nr - 1;           // largest m with rpre[m] <= e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (L.rpre[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                m = lo;
             }
-            at = L.rstart[lo] + (e - L.rpre[lo]);
+            at = L.rstart[m] + (e - L.rpre[m]);
             vm |= 1u << u;
         }
         lid[u] = a.ix.ids16[at];
@@ -424,10 +477,10 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
             len = to[c + 1] - s;
             st = (int64_t)i * P * TILE + s;
         }
-        const uint32_t tot = collide_runs<NT>(L, len, st);
-        for (uint32_t e0 = 0; e0 < tot; e0 += NT * kCollideUnroll) {
+        const RunBatch rb = collide_runs<NT>(L, len, st);
+        for (uint32_t e0 = 0; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid[kCollideUnroll];
-            const uint32_t vm = collide_fetch<NT>(a, L, e0, tot, lid);
+            const uint32_t vm = collide_fetch<NT>(a, L, e0, rb, lid);
             collide_count<NT>(L, sc, lid, vm);
         }
         __syncthreads();
@@ -454,8 +507,8 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
     const int64_t rbase = (int64_t)ic * P * TILE;
     uint32_t rs = tob[(int64_t)g * (K + 1)], re = tob[(int64_t)g * (K + 1) + 1];
     uint32_t lid[kCollideUnroll];
-    uint32_t tot = collide_runs<NT>(L, has_run ? re - rs : 0u, rbase + rs);
-    uint32_t vm = collide_fetch<NT>(a, L, 0, tot, lid);
+    RunBatch rb = collide_runs<NT>(L, has_run ? re - rs : 0u, rbase + rs);
+    uint32_t vm = collide_fetch<NT>(a, L, 0, rb, lid);
     {
         const int pn = g + S < P ? g + S : g;
         rs = tob[(int64_t)pn * (K + 1)];
@@ -463,9 +516,9 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
     }
     for (int p = g; p < P; p += S) {
         collide_count<NT>(L, sc, lid, vm);
-        for (uint32_t e0 = NT * kCollideUnroll; e0 < tot; e0 += NT * kCollideUnroll) {
+        for (uint32_t e0 = NT * kCollideUnroll; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid2[kCollideUnroll];
-            const uint32_t vm2 = collide_fetch<NT>(a, L, e0, tot, lid2);
+            const uint32_t vm2 = collide_fetch<NT>(a, L, e0, rb, lid2);
             collide_count<NT>(L, sc, lid2, vm2);
         }
         __syncthreads();
@@ -473,8 +526,8 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
         // prefetch the run offsets of the one after it; every load here is
         // unconditional, so nothing waits for them before the next iteration
         const bool more = p + S < P;
-        tot = collide_runs<NT>(L, (has_run && more) ? re - rs : 0u, rbase + rs);
-        vm = collide_fetch<NT>(a, L, 0, tot, lid);
+        rb = collide_runs<NT>(L, (has_run && more) ? re - rs : 0u, rbase + rs);
+        vm = collide_fetch<NT>(a, L, 0, rb, lid);
         const int pn = p + 2 * S < P ? p + 2 * S : p;
         rs = tob[(int64_t)pn * (K + 1)];
         re = tob[(int64_t)pn * (K + 1) + 1];

@@ -45,6 +45,8 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     const int static_lds = collide_static_lds();
     if (static_lds < 0) return fail(SUCO_E_HIP, "cannot query the collision kernel's attributes");
     tile_max = std::min(tile_max, (max_lds - static_lds) / 256 * 256);
+    // by default keep two collision blocks resident per CU
+    if (!(p && p->tile_max)) tile_max = std::min(tile_max, std::max(256, (max_lds / 2 - static_lds) / 256 * 256));
     if (tile_max < 256 || (int64_t)sk * sk * 4 > max_lds || (int64_t)sk * (sk + 1) * 4 + 4096 > max_lds)
         return fail(SUCO_E_UNSUPPORTED, "the device has too little LDS per work-group for this shape");
     if (p && (p->flags & SUCO_BUILD_BF16) && d % 8)
