@@ -403,21 +403,51 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     const uint32_t nt = L.n_touched;
     const bool sparse = nt <= (uint32_t)kTouchCap;
     const int nw = sparse ? (int)nt : words;
-    for (int t0 = 1; t0 <= ns; t0 += 8) {
-        uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int j = tid; j < nw; j += NT) {
-            const int w = sparse ? (int)L.touched[j] : j;
-            const uint32_t x = sc[w];
-            if (x == 0u) continue;
+    // Counts of bytes >= t, two thresholds per 32-bit counter (16-bit halves:
+    // a thread sees at most 4 * 32 bytes, a wave at most 64 times that).  In
+    // the listed-words case a thread has at most kTouchCap / NT words; they are
+    // kept in registers for the level pass.
+    constexpr int kKeep = kTouchCap / NT;
+    int wk[kKeep];
+    uint32_t xk[kKeep];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                c[u] += __popc((x + (0x80u - (uint32_t)(t0 + u)) * 0x01010101u) & 0x80808080u);
+    for (int q = 0; q < kKeep; ++q) {
+        const int j = tid + q * NT;
+        wk[q] = 0;
+        xk[q] = 0u;
+        if (sparse && j < nw) {
+            wk[q] = L.touched[j];
+            xk[q] = sc[wk[q]];
+        }
+    }
+    for (int t0 = 1; t0 <= ns; t0 += 8) {
+        uint32_t c[4] = {0, 0, 0, 0};
+        auto tally = [&](uint32_t x) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t ta = (uint32_t)(t0 + 2 * v), tb = ta + 1u;
+                c[v] += __popc((x + (0x80u - ta) * 0x01010101u) & 0x80808080u) +
+                        (__popc((x + (0x80u - tb) * 0x01010101u) & 0x80808080u) << 16);
+            }
+        };
+        if (sparse) {
+#pragma unroll
+            for (int q = 0; q < kKeep; ++q)
+                if (xk[q] != 0u) tally(xk[q]);
+        } else {
+            for (int j = tid; j < nw; j += NT) {
+                const uint32_t x = sc[j];
+                if (x != 0u) tally(x);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (t0 + u <= ns) {
-                const uint32_t s = wave_sum(c[u]);
-                if (lane == 0) atomicAdd(&L.G[t0 + u], s);
+        for (int v = 0; v < 4; ++v) {
+            if (t0 + 2 * v <= ns) {
+                const uint32_t sum = wave_sum(c[v]);
+                if (lane == 0) {
+                    atomicAdd(&L.G[t0 + 2 * v], sum & 0xffffu);
+                    if (t0 + 2 * v + 1 <= ns) atomicAdd(&L.G[t0 + 2 * v + 1], sum >> 16);
+                }
             }
         }
     }
@@ -425,14 +455,21 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     for (int t = tid; t <= ns; t += NT) L.cur[t] = L.G[t + 1];
     __syncthreads();
     uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
-    for (int j = tid; j < nw; j += NT) {
-        const int w = sparse ? (int)L.touched[j] : j;
-        const uint32_t x = sc[w];
-        if (x == 0u) continue;
+    auto place = [&](int w, uint32_t x) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint32_t s = (x >> (8 * u)) & 0xffu;
-            if (s != 0u) seg[atomicAdd(&L.cur[s], 1u)] = (uint16_t)(4 * w + u);
+            const uint32_t sv = (x >> (8 * u)) & 0xffu;
+            if (sv != 0u) seg[atomicAdd(&L.cur[sv], 1u)] = (uint16_t)(4 * w + u);
+        }
+    };
+    if (sparse) {
+#pragma unroll
+        for (int q = 0; q < kKeep; ++q)
+            if (xk[q] != 0u) place(wk[q], xk[q]);
+    } else {
+        for (int j = tid; j < nw; j += NT) {
+            const uint32_t x = sc[j];
+            if (x != 0u) place(j, x);
         }
     }
     if (a.scores != nullptr) {
@@ -446,7 +483,9 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : L.G[t];
     __syncthreads();
     if (sparse) {
-        for (int j = tid; j < (int)nt; j += NT) sc[L.touched[j]] = 0u;
+#pragma unroll
+        for (int q = 0; q < kKeep; ++q)
+            if (tid + q * NT < nw) sc[wk[q]] = 0u;
     } else {
         uint4 *z = reinterpret_cast<uint4 *>(sc);
         for (int w = tid; w < (words >> 2); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
