@@ -60,3 +60,8 @@ def test_errors_before_any_device_work():
     assert L.suco_index_free(None) == suco.SUCO_OK
     assert L.suco_index_info(None, None, None, None, None) == suco.SUCO_E_STATE
     assert L.suco_rerank(None, None, 1, None, 5, 1, None, None, None) == suco.SUCO_E_STATE
+    flags = C.c_int32(-1)
+    assert L.suco_index_flags(None, C.byref(flags)) == suco.SUCO_E_STATE and flags.value == -1
+    assert L.suco_query_bf16(None, None, 0, 10, 0.1, 0.1, 0, None, None, None, None, None, None) == suco.SUCO_E_STATE
+    assert L.suco_query_bf16_debug(None, None, 0, 10, 0.1, 0.1, 0, None, None, None, None, None, None, None, None,
+                                   None, None, None) == suco.SUCO_E_STATE

@@ -271,6 +271,7 @@ def test_byte_rows_equal_fp32_rows(suco):
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     a = suco.Index.from_index(Xd, 8, 20, c32, asg)
     b = suco.Index.from_index(Xd, 8, 20, c32, asg, flags=suco.BUILD_NO_BYTE_ROWS)
+    assert a.flags() == suco.INDEX_BYTE_ROWS and b.flags() == 0
     ra = a.query(Qd, 10, 0.02, 0.01)
     rb = b.query(Qd, 10, 0.02, 0.01)
     torch.cuda.synchronize()
