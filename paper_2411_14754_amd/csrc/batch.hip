@@ -245,7 +245,7 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         rp.G = b->rcfg.G; rp.U = b->rcfg.U; rp.part_keys = b->part_keys;
         rp.ids = b->ids_s + (int64_t)c * b->C * b->k;
         rp.dists = b->dists_s + (int64_t)c * b->C * b->k;
-        const Launch La = plan_activate(qp, 0), Lc = plan_collide(qp, t.cap_c), Ls = plan_select(qp, 0),
+        const Launch La = plan_activate(qp, kActivateGrid), Lc = plan_collide(qp, t.cap_c), Ls = plan_select(qp, 0),
                      Lr = plan_rerank(rp, t.cap_r), Lm = plan_merge(rp, 0);
         void *aq[] = {&qp};
         void *ar[] = {&rp};

@@ -131,20 +131,35 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
     const float *q = a.Q + (int64_t)ql * a.ix.d;
 
     // centre distances of both halves (squared L2, FP32, dimension order), or
-    // the ones given by an earlier kernel
+    // the ones given by an earlier kernel.  Query and centre values are loaded
+    // eight dimensions at a time before their FMAs (same order), so a half
+    // costs a few memory round trips rather than one per dimension.
+    const HalfDims hd2[2] = {a.ix.halves[2 * i], a.ix.halves[2 * i + 1]};
     for (int t = tid; t < 2 * sk; t += NT) {
         const int h = t >= sk, c = t - h * sk;
         if (a.Dext) {
             Dr[h][c] = a.Dext[((int64_t)ql * 2 * ns + 2 * i + h) * sk + c];
             continue;
         }
-        const HalfDims hd = a.ix.halves[2 * i + h];
+        const HalfDims hd = hd2[h];
         const float *cp = a.ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
         const float *qp = q + hd.dim0;
         float s = 0.f;
-        for (int j = 0; j < hd.w; ++j) {
-            const float t2 = qp[j] - cp[j];
-            s = fmaf(t2, t2, s);
+        for (int j0 = 0; j0 < hd.w; j0 += 8) {
+            float qv[8], cv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = j0 + u < hd.w;
+                qv[u] = in ? qp[j0 + u] : 0.f;
+                cv[u] = in ? cp[j0 + u] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u < hd.w) {
+                    const float t2 = qv[u] - cv[u];
+                    s = fmaf(t2, t2, s);
+                }
+            }
         }
         Dr[h][c] = s;
     }
@@ -989,7 +1004,7 @@ int collide_static_lds() {
 
 hipError_t launch_activate(const QueryPass &p, hipStream_t s) {
     QueryPass c = p;
-    return launch(plan_activate(p, 0), &c, s);
+    return launch(plan_activate(p, kActivateGrid), &c, s);
 }
 
 hipError_t launch_collide(const QueryPass &p, hipStream_t s) {

@@ -85,6 +85,9 @@ struct Launch {
     dim3 grid, block;
     size_t lds = 0;
 };
+// The activation step runs as a persistent grid of at most this many blocks
+// (one block per (query, subspace) item otherwise spends its time in dispatch).
+constexpr int kActivateGrid = 8192;
 Launch plan_activate(const QueryPass &p, int cap);
 Launch plan_collide(const QueryPass &p, int cap);
 Launch plan_select(const QueryPass &p, int cap);
