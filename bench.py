@@ -753,6 +753,9 @@ def main():
         ms_l = timed(stream_pass, args.steps, max(1, args.warmup))
         value = nq * args.steps / (ms_l / 1e3)
         rec = recall_at(ids, gt)
+        ms_l1 = timed(lambda: suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax, out=(ids, dists)),
+                      args.steps, max(1, args.warmup))
+        log(f"learned, one call: {ms_l1 / args.steps:.3f} ms/step, {nq * args.steps / (ms_l1 / 1e3):.0f} QPS")
         _, _, au = suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax)
         mean_alpha = float(au.double().mean())
         # plain SuCo at the same recall, interpolated on the sweep
@@ -765,6 +768,7 @@ def main():
         log(f"learned+batched: {ms_l / args.steps:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}, "
             f"mean alpha {mean_alpha:.5f}; plain at that recall {plain_eq}")
         learned_info = {"plain_batched_stream_qps": round(nq * args.steps / (ms_pb / 1e3), 1),
+                        "learned_one_call_qps": round(nq * args.steps / (ms_l1 / 1e3), 1),
                         "train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
                         "scale": round(scale, 5), "mean_alpha": round(mean_alpha, 6), "train_s": round(train_s, 2),
                         "batch_sizes": sizes, "plain_qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1),

@@ -43,35 +43,52 @@ __device__ __forceinline__ float bf16r(float x) {
 
 // ------------------------------------------------------------- features --
 __global__ __launch_bounds__(128) void k_features(FeatPass fp) {
-    __shared__ float mins[2 * kMaxNs];
+    __shared__ uint32_t mins[2 * kMaxNs];   // bits of each half's smallest distance (non-negative floats)
+    __shared__ float part[128 / kWave];
     const IndexView ix = fp.ix;
     const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
     const int sk = ix.sk, nh = 2 * ix.ns;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
         const float *qv = fp.Q + (int64_t)q * ix.d;
-        for (int g = threadIdx.x; g < nh; g += blockDim.x) {
+        for (int g = tid; g < nh; g += blockDim.x) mins[g] = 0x7f800000u;
+        __syncthreads();
+        // one (half, centre) pair per thread at a time, with the activation
+        // step's arithmetic: FMA over the half's dimensions in order, values
+        // loaded eight at a time
+        for (int t = tid; t < nh * sk; t += blockDim.x) {
+            const int g = t / sk, c = t - g * sk;
             const HalfDims hd = ix.halves[g];
             const float *qp = qv + hd.dim0;
-            float best = 0.f;
-            for (int c = 0; c < sk; ++c) {
-                const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
-                float s = 0.f;
-                for (int j = 0; j < hd.w; ++j) {
-                    const float t2 = qp[j] - cp[j];
-                    s = fmaf(t2, t2, s);
+            const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
+            float s = 0.f;
+            for (int j0 = 0; j0 < hd.w; j0 += 8) {
+                float a8[8], c8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in = j0 + u < hd.w;
+                    a8[u] = in ? qp[j0 + u] : 0.f;
+                    c8[u] = in ? cp[j0 + u] : 0.f;
                 }
-                best = (c == 0 || s < best) ? s : best;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (j0 + u < hd.w) {
+                        const float t2 = a8[u] - c8[u];
+                        s = fmaf(t2, t2, s);
+                    }
+                }
             }
-            mins[g] = __fsqrt_rn(best);
+            atomicMin(&mins[g], __float_as_uint(s));
         }
+        // query norm: lane-strided partial sums, then a fixed reduction order
+        float nsq = 0.f;
+        for (int j = tid; j < ix.d; j += blockDim.x) nsq = fmaf(qv[j], qv[j], nsq);
+        for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, kWave);
+        if (lane == 0) part[tid / kWave] = nsq;
         __syncthreads();
         float *out = fp.F + (int64_t)q * (nh + 1);
-        for (int g = threadIdx.x; g < nh; g += blockDim.x) out[g] = mins[g];
-        if (threadIdx.x == 0) {
-            float s = 0.f;
-            for (int j = 0; j < ix.d; ++j) s = fmaf(qv[j], qv[j], s);
-            out[nh] = __fsqrt_rn(s);
-        }
+        for (int g = tid; g < nh; g += blockDim.x) out[g] = __fsqrt_rn(__uint_as_float(mins[g]));
+        if (tid == 0) out[nh] = __fsqrt_rn(part[0] + part[1]);
         __syncthreads();
     }
 }

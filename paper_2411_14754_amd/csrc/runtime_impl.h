@@ -194,7 +194,7 @@ inline int rerank_bf16_cfg(int d, int64_t B, RerankCfg *c) {
     const int U = (d8 + G - 1) / G;
     if (U > kMaxU16) return fail(SUCO_E_UNSUPPORTED, "the BF16 re-rank supports d <= 2048");
     c->G = G; c->U = U;
-    c->rpp = 512;
+    c->rpp = 1024;
     c->parts = (int)((B + c->rpp - 1) / c->rpp);
     return SUCO_OK;
 }
@@ -207,7 +207,7 @@ inline int rerank_cfg(int d, int64_t B, RerankCfg *c) {
     const int U = (d4 + G - 1) / G;
     if (U > kMaxU) return fail(SUCO_E_UNSUPPORTED, "the re-rank supports d <= 2048");
     c->G = G; c->U = U;
-    c->rpp = 512;
+    c->rpp = 1024;
     c->parts = (int)((B + c->rpp - 1) / c->rpp);
     return SUCO_OK;
 }

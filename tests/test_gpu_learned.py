@@ -116,6 +116,10 @@ def test_features_match_oracle(suco):
         e = [np.sqrt(oix.centroid_dists(Q[q], g).min()) for g in range(16)]
         e.append(np.sqrt((Q[q].astype(np.float64) ** 2).sum()))
         assert np.allclose(F[q], e, rtol=1e-5, atol=1e-5)
+    # the half distances are the activation step's own values, bit for bit
+    o = ix.query_debug(torch.from_numpy(Q).cuda(), 10, 0.05, 0.005, scores=False, cand=False, cells=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(F[:, :16], o["feat"].cpu().numpy())
     ix.free()
 
 
