@@ -319,9 +319,10 @@ SUCO_API int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, f
  * last read, then resets.  Steps, in order: 0 activate (centre distances and
  * Dynamic Activation), 1 collide (SC-score counting), 2 select (top-B by
  * score), 3 rerank (candidate distances, partial top-k), 4 merge (final top-k),
- * 5 BF16 centre distances, 6 BF16 first re-rank pass, 7 survivors.
- *  ms        host double [8]
- *  launches  host int64 [8] */
+ * 5 BF16 centre distances, 6 BF16 first re-rank pass, 7 survivors, 8 ordering
+ * of a pass's queries by activated points (heaviest first) for step 3.
+ *  ms        host double [9]
+ *  launches  host int64 [9] */
 SUCO_API int suco_profile(suco_index *ix, int enable);
 SUCO_API int suco_profile_read(suco_index *ix, double *ms, int64_t *launches);
 

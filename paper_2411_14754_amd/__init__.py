@@ -29,7 +29,7 @@ EXPORTED = (
     "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags",
 )
 
-STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors")
+STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order")
 
 
 class SucoError(RuntimeError):

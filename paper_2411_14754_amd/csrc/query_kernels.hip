@@ -607,7 +607,8 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     const int RJ = a.runs_per_sub, ns = a.ix.ns;
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        const int ql = item / S, g = item - ql * S;
+        const int rq = item / S, g = item - rq * S;
+        const int ql = a.order ? a.order[rq] : rq;   // heaviest queries first
         // this thread's subspace: activated cell count and its cell of the first batch
         const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
         const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
@@ -617,6 +618,35 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
             collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first);
         }
     }
+}
+
+// ================================================================= order ==
+// One block of kOrderMax threads: the pass's queries sorted by their number of
+// activated points (descending, ties by query), so that the collision step's
+// blocks take the heaviest queries first and a pass does not end waiting for a
+// few large ones (queries with their own collision ratio differ a lot).
+__global__ __launch_bounds__(kOrderMax) void k_order(QueryPass a) {
+    __shared__ uint64_t key[kOrderMax];
+    const int nq = pass_nq(a.nq_dev, a.q_base, a.nq), ns = a.ix.ns;
+    const int t = threadIdx.x;
+    uint64_t w = 0;
+    if (t < nq)
+        for (int i = 0; i < ns; ++i) w += (uint32_t)a.aprime[t * ns + i];
+    // ascending keys: heavier first, then lower query index; empty slots last
+    key[t] = t < nq ? (((~w) & 0xffffffffffull) << 20) | (uint64_t)t : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= kOrderMax; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int j = t ^ stride;
+            if (j > t) {
+                const uint64_t x = key[t], y = key[j];
+                const bool up = (t & size) == 0;
+                if ((x > y) == up) { key[t] = y; key[j] = x; }
+            }
+            __syncthreads();
+        }
+    }
+    if (t < nq) a.order_out[t] = (int32_t)(key[t] & 0xfffffull);
 }
 
 // ================================================================ select ==
@@ -954,6 +984,14 @@ Launch plan_collide(const QueryPass &p, int cap) {
     L.grid = dim3(grid_for(items, cap));
     L.block = dim3(512);
     L.func = reinterpret_cast<const void *>(&k_collide<512>);
+    return L;
+}
+
+Launch plan_order(const QueryPass &p) {
+    Launch L;
+    L.func = reinterpret_cast<const void *>(&k_order);
+    L.grid = dim3(1);
+    L.block = dim3(kOrderMax);
     return L;
 }
 

@@ -221,7 +221,7 @@ struct Carve {
 
 struct Work {
     uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint16_t *lvl; uint8_t *scores;
-    uint32_t *cand; uint64_t *part_keys;
+    uint32_t *cand; uint64_t *part_keys; int32_t *order;
 };
 
 // dense: also room for the dense SC-scores (exported on request only)
@@ -236,6 +236,7 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.lvl = c.take<uint16_t>(C * (size_t)ix->P * ix->TILE);
     w.scores = dense ? c.take<uint8_t>(C * (size_t)ix->P * ix->TILE) : nullptr;
     w.cand = c.take<uint32_t>(C * (size_t)B);
+    w.order = c.take<int32_t>(C);
     w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
     if (bytes) *bytes = c.off;
     return w;
@@ -345,6 +346,11 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
                                         hipMemcpyDeviceToDevice, st));
         }
         HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
+        if (cn <= kOrderMax) {
+            qp.order_out = w.order;
+            HIPCHECK(timed(ix, kOrder, st, [&] { return launch(plan_order(qp), &qp, st); }));
+            qp.order = w.order;
+        }
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
         RerankPass rp{};

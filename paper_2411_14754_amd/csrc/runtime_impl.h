@@ -147,7 +147,7 @@ namespace suco {
 
 inline bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
 
-enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kStages };
+enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kOrder, kStages };
 
 // Launch through `fn`, bracketed by a pair of timing events when profiling is on.
 template <class F>

@@ -54,6 +54,8 @@ struct QueryPass {
     uint8_t *scores;          // [nq][P*TILE] dense scores, or null
     uint32_t *cand;           // [nq][B]
     const float *Dext;        // [nq][2ns][sqrt_k] centre distances computed elsewhere, or null
+    const int32_t *order;     // [nq] order in which the collision step takes the queries, or null
+    int32_t *order_out;       // [nq] written by the ordering kernel
 };
 
 struct RerankPass {
@@ -90,6 +92,8 @@ struct Launch {
 constexpr int kActivateGrid = 8192;
 Launch plan_activate(const QueryPass &p, int cap);
 Launch plan_collide(const QueryPass &p, int cap);
+constexpr int kOrderMax = 1024;   // largest pass the ordering kernel sorts
+Launch plan_order(const QueryPass &p);
 Launch plan_select(const QueryPass &p, int cap);
 Launch plan_rerank(const RerankPass &r, int cap);
 Launch plan_merge(const RerankPass &r, int cap);
