@@ -139,3 +139,47 @@ def test_sift_like_uneven_stream_full_size(suco):
     assert np.array_equal(out_d.cpu().numpy(), p_d)
     b.free()
     ix.free()
+
+
+@pytest.mark.timeout(900)
+def test_deep_like_stream_full_size(suco):
+    """Deep-like n=10,000,000 d=96 unit-norm rows, N_s=8, sqrtK=64, 100,000
+    queries as uneven batches (1..4096), k=10, alpha=0.02, beta=0.002 (the
+    batched workload at its real size): the stream equals the plain path for
+    every query, and 4 sampled queries match the oracle stage by stage."""
+    from parity import check_query
+    W = synth.Workload(4)
+    print("case: deep_like n=1e7 generating", flush=True)
+    X, Qn = W.data(), W.queries()
+    print("case: deep_like oracle build", flush=True)
+    _, c32, asg, _ = oracle.build_index(X, 8, 64, iters=2, seed=1)
+    oix = oracle.Index(X, 8, 64, c32, asg)
+    Xd, Q = torch.from_numpy(X).cuda(), torch.from_numpy(Qn).cuda()
+    ix = suco.Index.from_index(Xd, 8, 64, c32, asg)
+    del asg
+    print("case: deep_like plain, one call", flush=True)
+    p_ids, p_d = plain(ix, Q, 10, 0.02, 0.002)
+    print("case: deep_like batched stream", flush=True)
+    b = suco.Batcher(ix, 4096, 10, 0.002)
+    out_ids = torch.empty((Q.shape[0], 10), dtype=torch.int32, device="cuda")
+    out_d = torch.empty((Q.shape[0], 10), dtype=torch.float32, device="cuda")
+    start = 0
+    for s in W.batch_sizes(Q.shape[0]):
+        b.query(Q[start:start + s], alpha=0.02, out=(out_ids[start:start + s], out_d[start:start + s]))
+        start += s
+    torch.cuda.synchronize()
+    assert np.array_equal(out_ids.cpu().numpy(), p_ids)
+    assert np.array_equal(out_d.cpu().numpy(), p_d)
+    b.free()
+    sample = np.sort(np.random.default_rng(0).choice(Q.shape[0], 4, replace=False))
+    print("case: deep_like GPU stages on the sample", flush=True)
+    o = ix.query_debug(Q[sample].contiguous(), 10, 0.02, 0.002)
+    torch.cuda.synchronize()
+    gs = {key: (v.view(torch.int16).cpu().numpy().view(np.uint16) if v.dtype == torch.uint16 else v.cpu().numpy())
+          for key, v in o.items() if v is not None}
+    del o
+    assert np.array_equal(gs["ids"], p_ids[sample])
+    print("case: deep_like oracle on the sample", flush=True)
+    st = check_query(oix, X, Qn[sample], 10, 0.02, 0.002, gs)
+    assert st["band_queries"] <= 2
+    ix.free()
