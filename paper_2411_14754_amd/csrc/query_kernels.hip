@@ -652,21 +652,23 @@ __global__ __launch_bounds__(kOrderMax) void k_order(QueryPass a) {
 // ================================================================ select ==
 // One block per query.  The threshold is T = max{t : sum_p G_p[t] >= B};
 // every point with score > T is a candidate and, of those with score == T,
-// the R = B - #{score > T} lowest ids.  Tiles are visited in id order.  For
-// each tile the chosen ids are marked in an LDS bitmap (score > T from the
-// front of the tile's list; the level-T ids in a second bitmap, of which the
-// lowest ones are kept when only some are taken) and the bitmap is scanned in
-// id order, so the candidates come out in ascending id order.  When T == 0
-// the points of score 0 are the ones missing from the tile's list.
+// the R = B - #{score > T} lowest ids.  Tiles are visited in id order and each
+// contributes gt (ids above T) plus take (its share of the level-T ids) at an
+// offset known from the histograms.  A tile's chosen ids are marked in an LDS
+// bitmap (score > T from the front of the tile's list; level-T ids in a
+// second bitmap when only some are taken) with a summary bitmap of non-zero
+// words, and the first wave walks the summaries in id order: the work per
+// tile follows the number of candidates, not the tile size, and the bitmaps
+// are cleared through their summaries.  When T == 0 the points of score 0 are
+// the ones missing from the tile's list; such a tile is handled densely.
 template <int NT>
-__device__ __forceinline__ void select_item(const QueryPass &a, const int ql) {
-    extern __shared__ uint32_t bm[];   // two bitmaps of TILE bits
+__device__ __forceinline__ void select_item(const QueryPass &a, const int ql, uint32_t *bm, uint32_t *sum) {
     __shared__ uint32_t Gt[kMaxNs + 2];
     __shared__ uint32_t red[NT / kWave + 1];
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE, H = ns + 2;
-    const int tid = threadIdx.x;
-    const int bwords = TILE >> 5;
-    uint32_t *bmA = bm, *bmT = bm + bwords;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int bwords = TILE >> 5, swords = (bwords + 31) >> 5;   // swords <= 64
+    uint32_t *bmA = bm, *bmT = bm + bwords, *sumA = sum, *sumT = sum + 64;
     const uint32_t B = (uint32_t)a.B;
     const uint32_t *hq = a.hist + (int64_t)ql * P * H;
     for (int t = tid; t < H; t += NT) {
@@ -696,33 +698,18 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql) {
         const int64_t vv = a.ix.n - (int64_t)id0;
         const int valid = (int)(vv < TILE ? vv : TILE);
         const bool partial = take > 0u && (take < E || T == 0);
-        for (int w = tid; w < 2 * bwords; w += NT) bm[w] = 0u;
-        __syncthreads();
-        const uint32_t hiA = (T > 0 && !partial) ? gt + take : gt;
-        for (uint32_t j = tid; j < hiA; j += NT) {
-            const uint32_t lid = seg[j];
-            atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
-        }
-        if (partial && T > 0) {
-            for (uint32_t j = gt + tid; j < gt + E; j += NT) {
+        if (T == 0 && partial) {
+            // fewer than B points collide: the tile's score-0 ids are taken too,
+            // lowest first; dense bitmaps for this tile
+            for (uint32_t j = tid; j < gt; j += NT) {
                 const uint32_t lid = seg[j];
-                atomicOr(&bmT[lid >> 5], 1u << (lid & 31u));
+                atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
             }
-        }
-        __syncthreads();
-        if (partial) {
-            // keep the `take` lowest ties: level-T bits, or for T == 0 the ids
-            // below `valid` that have no score
+            __syncthreads();
             uint32_t cnt = 0;
             for (int w = w0; w < w1; ++w) {
-                uint32_t x;
-                if (T > 0) {
-                    x = bmT[w];
-                } else {
-                    const uint32_t m = (w + 1) * 32 <= valid ? ~0u
-                                       : (w * 32 >= valid ? 0u : (1u << (valid - w * 32)) - 1u);
-                    x = ~bmA[w] & m;
-                }
+                const uint32_t m = (w + 1) * 32 <= valid ? ~0u : (w * 32 >= valid ? 0u : (1u << (valid - w * 32)) - 1u);
+                const uint32_t x = ~bmA[w] & m;
                 bmT[w] = x;
                 cnt += __popc(x);
             }
@@ -736,21 +723,90 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql) {
                     x ^= bit;
                     ++r;
                 }
-                bmA[w] |= keep;   // this thread owns words w0..w1
+                bmA[w] |= keep;
+                bmT[w] = 0u;
             }
             __syncthreads();
-        }
-        uint32_t cnt = 0;
-        for (int w = w0; w < w1; ++w) cnt += __popc(bmA[w]);
-        uint32_t tot;
-        uint32_t pos = base + block_excl_scan<NT>(cnt, red, &tot);
-        for (int w = w0; w < w1; ++w) {
-            uint32_t x = bmA[w];
-            while (x != 0u) {
-                const int b = __ffs(x) - 1;
-                out[pos++] = id0 + (uint32_t)(w * 32 + b);
-                x &= x - 1u;
+            cnt = 0;
+            for (int w = w0; w < w1; ++w) cnt += __popc(bmA[w]);
+            uint32_t pos = base + block_excl_scan<NT>(cnt, red, &tot);
+            for (int w = w0; w < w1; ++w) {
+                uint32_t x = bmA[w];
+                while (x != 0u) {
+                    const int bq = __ffs(x) - 1;
+                    out[pos++] = id0 + (uint32_t)(w * 32 + bq);
+                    x &= x - 1u;
+                }
+                bmA[w] = 0u;
             }
+            base += gt + take;
+            __syncthreads();
+            continue;
+        }
+        // sparse tile: mark, optionally keep the lowest level-T ids, extract
+        const uint32_t hiA = partial ? gt : gt + take;
+        for (uint32_t j = tid; j < hiA; j += NT) {
+            const uint32_t lid = seg[j];
+            atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
+            atomicOr(&sumA[lid >> 10], 1u << ((lid >> 5) & 31u));
+        }
+        if (partial) {
+            for (uint32_t j = gt + tid; j < gt + E; j += NT) {
+                const uint32_t lid = seg[j];
+                atomicOr(&bmT[lid >> 5], 1u << (lid & 31u));
+                atomicOr(&sumT[lid >> 10], 1u << ((lid >> 5) & 31u));
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            if (partial) {
+                // lane l owns summary word l: its level-T ids in id order
+                uint32_t sl = lane < swords ? sumT[lane] : 0u, c = 0;
+                for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bmT[lane * 32 + __ffs(x) - 1]);
+                uint32_t r = c;
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t y = __shfl_up(r, o, kWave);
+                    if (lane >= o) r += y;
+                }
+                r -= c;                                   // level-T ids before this lane's words
+                for (uint32_t x = sl; x != 0u; x &= x - 1u) {
+                    const int w = lane * 32 + __ffs(x) - 1;
+                    uint32_t y = bmT[w], keep = 0u;
+                    while (y != 0u && r < take) {
+                        const uint32_t bit = y & (0u - y);
+                        keep |= bit;
+                        y ^= bit;
+                        ++r;
+                    }
+                    bmT[w] = 0u;
+                    if (keep != 0u) {
+                        bmA[w] |= keep;
+                        sumA[lane] |= 1u << (w & 31);
+                    }
+                }
+                if (lane < swords) sumT[lane] = 0u;
+            }
+            // candidates in id order: lane l writes the ids of its summary word
+            const uint32_t sl = lane < swords ? sumA[lane] : 0u;
+            uint32_t c = 0;
+            for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bmA[lane * 32 + __ffs(x) - 1]);
+            uint32_t r = c;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t y = __shfl_up(r, o, kWave);
+                if (lane >= o) r += y;
+            }
+            uint32_t pos = base + r - c;
+            for (uint32_t x = sl; x != 0u; x &= x - 1u) {
+                const int w = lane * 32 + __ffs(x) - 1;
+                uint32_t y = bmA[w];
+                bmA[w] = 0u;
+                while (y != 0u) {
+                    const int bq = __ffs(y) - 1;
+                    out[pos++] = id0 + (uint32_t)(w * 32 + bq);
+                    y &= y - 1u;
+                }
+            }
+            if (lane < swords) sumA[lane] = 0u;
         }
         base += gt + take;
         __syncthreads();
@@ -759,9 +815,15 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql) {
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
+    extern __shared__ uint32_t bm[];       // two bitmaps of TILE bits
+    __shared__ uint32_t sum[2 * 64];       // their summaries: bit w of word s = bitmap word 32s + w non-zero
     const int items = pass_nq(a.nq_dev, a.q_base, a.nq);
+    if ((int)blockIdx.x >= items) return;
+    for (int w = threadIdx.x; w < 2 * (a.ix.TILE >> 5); w += NT) bm[w] = 0u;
+    for (int w = threadIdx.x; w < 128; w += NT) sum[w] = 0u;
+    __syncthreads();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        select_item<NT>(a, item);
+        select_item<NT>(a, item, bm, sum);
         __syncthreads();
     }
 }

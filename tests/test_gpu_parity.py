@@ -68,7 +68,8 @@ def test_stage_collide_select_from_oracle_cells(suco):
     W = synth.Workload(1)
     X, Q = W.data(), W.queries(40)
     oix, gix = make(X, 8, 16)
-    for alpha, beta, k in ((0.05, 0.005, 10), (0.2, 0.01, 10), (0.01, 0.001, 5), (1.0, 0.003, 10)):
+    # the last case has fewer colliding points than B, so score-0 points are selected too (T = 0)
+    for alpha, beta, k in ((0.05, 0.005, 10), (0.2, 0.01, 10), (0.01, 0.001, 5), (1.0, 0.003, 10), (1e-4, 0.1, 10)):
         rc = oracle_cells(oix, Q, alpha)
         cells, nc = cells_to_gpu_layout([[r[0] for r in row] for row in rc], Q.shape[0], 8, 256)
         ref = oix.query(Q, k, alpha, beta, want_scores=True, want_cand=True)
