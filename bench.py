@@ -467,7 +467,7 @@ def bench_learned_lifted(args, log):
     ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
     dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
     sweep = []
-    for a in (0.0005, 0.001, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.02, 0.03):
+    for a in (0.00001, 0.00002, 0.00005, 0.0001, 0.0002, 0.0005, 0.001, 0.002, 0.005, 0.01, 0.03):
         ms_a = timed_region(lambda: ix.query(Qd, k, a, beta, out=(ids, dists)), 1, 1)
         r = recall_at(ids, gt)
         sweep.append({"alpha": a, "recall": round(r, 5), "qps": round(nq / (ms_a / 1e3), 1)})
@@ -481,7 +481,7 @@ def bench_learned_lifted(args, log):
     t0 = time.time()
     Qt = torch.from_numpy(W.train_queries(m_tr + m_val)).cuda()
     gt_t = exact_topk_float(Xd, Qt, k)
-    grid = learned.alpha_grid(0.0005, 0.03)
+    grid = learned.alpha_grid(0.00001, 0.01, 1.4)
     net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
     amin, amax = grid[0], grid[-1]
     scale = learned.calibrate_scale(ix, net, Qt[m_tr:], gt_t[m_tr:], k, beta, args.target_recall, amin, amax)

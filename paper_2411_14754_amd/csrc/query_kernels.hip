@@ -685,13 +685,38 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
     const int per = (bwords + NT - 1) / NT;
     const int w0 = tid * per < bwords ? tid * per : bwords;
     const int w1 = w0 + per < bwords ? w0 + per : bwords;
-    uint32_t base = 0, eq_before = 0;
-    for (int p = 0; p < P; ++p) {
-        const uint32_t *h = hq + p * H;
-        const uint32_t gt = h[T + 1], E = h[T] - h[T + 1];
-        const uint32_t left = R > eq_before ? R - eq_before : 0u;
-        const uint32_t take = E < left ? E : left;
-        eq_before += E;
+    // Per-tile plan for NT tiles at a time, from the histograms in parallel:
+    // ids above T (gt), at T (E), level-T ids taken (the lowest R overall, so a
+    // tile takes what the tiles before it left) and the tile's output offset.
+    __shared__ uint32_t pl_gt[NT], pl_E[NT], pl_take[NT], pl_base[NT];
+    uint32_t base_carry = 0, eq_carry = 0;
+    for (int p0 = 0; p0 < P; p0 += NT) {
+    const int np = P - p0 < NT ? P - p0 : NT;
+    {
+        uint32_t gt_t = 0, E_t = 0;
+        if (tid < np) {
+            const uint32_t *h = hq + (int64_t)(p0 + tid) * H;
+            gt_t = h[T + 1];
+            E_t = h[T] - gt_t;
+        }
+        uint32_t totE, totS;
+        const uint32_t eqb = eq_carry + block_excl_scan<NT>(E_t, red, &totE);
+        const uint32_t left = R > eqb ? R - eqb : 0u;
+        const uint32_t take_t = E_t < left ? E_t : left;
+        const uint32_t exS = block_excl_scan<NT>(gt_t + take_t, red, &totS);
+        if (tid < np) {
+            pl_gt[tid] = gt_t;
+            pl_E[tid] = E_t;
+            pl_take[tid] = take_t;
+            pl_base[tid] = base_carry + exS;
+        }
+        base_carry += totS;
+        eq_carry += totE;
+        __syncthreads();
+    }
+    for (int pi = 0; pi < np; ++pi) {
+        const int p = p0 + pi;
+        const uint32_t gt = pl_gt[pi], E = pl_E[pi], take = pl_take[pi], base = pl_base[pi];
         if (gt + take == 0u) continue;
         const uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
         const uint32_t id0 = (uint32_t)p * TILE;
@@ -739,7 +764,6 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
                 }
                 bmA[w] = 0u;
             }
-            base += gt + take;
             __syncthreads();
             continue;
         }
@@ -808,8 +832,8 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
             }
             if (lane < swords) sumA[lane] = 0u;
         }
-        base += gt + take;
         __syncthreads();
+    }
     }
 }
 
