@@ -414,7 +414,7 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int words = TILE >> 2;
-    __syncthreads();
+    // the caller's last barrier follows the counting
     const uint32_t nt = L.n_touched;
     const bool sparse = nt <= (uint32_t)kTouchCap;
     const int nw = sparse ? (int)nt : words;
@@ -467,14 +467,13 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
         }
     }
     __syncthreads();
-    for (int t = tid; t <= ns; t += NT) L.cur[t] = L.G[t + 1];
-    __syncthreads();
+    // level s starts at G[s+1]; cur[s] counts the ids placed in it so far
     uint16_t *seg = a.lvl + ((int64_t)ql * P + p) * TILE;
     auto place = [&](int w, uint32_t x) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t sv = (x >> (8 * u)) & 0xffu;
-            if (sv != 0u) seg[atomicAdd(&L.cur[sv], 1u)] = (uint16_t)(4 * w + u);
+            if (sv != 0u) seg[L.G[sv + 1] + atomicAdd(&L.cur[sv], 1u)] = (uint16_t)(4 * w + u);
         }
     };
     if (sparse) {
@@ -505,7 +504,10 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
         uint4 *z = reinterpret_cast<uint4 *>(sc);
         for (int w = tid; w < (words >> 2); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
     }
-    for (int t = tid; t < ns + 2; t += NT) L.G[t] = 0u;
+    for (int t = tid; t < ns + 2; t += NT) {
+        L.G[t] = 0u;
+        L.cur[t] = 0u;
+    }
     if (tid == 0) L.n_touched = 0u;
     __syncthreads();
 }
@@ -601,7 +603,10 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     {
         uint4 *z = reinterpret_cast<uint4 *>(sc);
         for (int w = threadIdx.x; w < (a.ix.TILE >> 4); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
-        for (int t = threadIdx.x; t < a.ix.ns + 2; t += NT) L.G[t] = 0u;
+        for (int t = threadIdx.x; t < a.ix.ns + 2; t += NT) {
+            L.G[t] = 0u;
+            L.cur[t] = 0u;
+        }
         if (threadIdx.x == 0) L.n_touched = 0u;
     }
     const int RJ = a.runs_per_sub, ns = a.ix.ns;
