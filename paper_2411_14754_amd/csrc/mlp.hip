@@ -543,24 +543,6 @@ int suco_mlp_free(suco_mlp *p) {
 }  // extern "C"
 
 // ------------------------------------------------------ learned query --
-namespace {
-struct LearnedBufs {
-    float *F = nullptr, *alpha = nullptr;
-    int64_t cap = 0;
-};
-}  // namespace
-
-struct suco_learned_state {
-    std::mutex mu;
-    LearnedBufs b;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-};
-
-namespace {
-suco_learned_state g_learned_states[1];   // one shared staging area, serialised by its mutex
-}
-
 extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float *Q, int64_t nq, int32_t k,
                                   double beta, float scale, float alpha_min, float alpha_max, int32_t *ids,
                                   float *dists, float *alpha_used, void *stream) {
@@ -575,31 +557,35 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
     if (nq == 0) return SUCO_OK;
     hipStream_t st = (hipStream_t)stream;
-    suco_learned_state &S = g_learned_states[0];
+    // features and alphas are staged in buffers owned by the index (on its device),
+    // serialised by the index's staging mutex
+    suco_index *mix = const_cast<suco_index *>(ix);
+    suco_index::LearnedStage &S = mix->lstage;
     std::lock_guard<std::mutex> lock(S.mu);
     DeviceGuard dg(ix->device);
     if (!S.done) HIPCHECK(hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
-    if (nq * p->n_in > S.b.cap) {
+    if (nq * p->n_in > S.cap_f || nq > S.cap_a) {
         if (S.pending) HIPCHECK(hipEventSynchronize(S.done));
-        if (S.b.F) (void)hipFree(S.b.F);
-        if (S.b.alpha) (void)hipFree(S.b.alpha);
-        S.b = LearnedBufs{};
+        if (S.F) (void)hipFree(S.F);
+        if (S.alpha) (void)hipFree(S.alpha);
+        S.F = nullptr; S.alpha = nullptr; S.cap_f = 0; S.cap_a = 0;
         int rc;
-        if ((rc = dev_alloc(&S.b.F, (size_t)nq * p->n_in)) || (rc = dev_alloc(&S.b.alpha, (size_t)nq))) {
-            if (S.b.F) (void)hipFree(S.b.F);
-            S.b = LearnedBufs{};
+        if ((rc = dev_alloc(&S.F, (size_t)nq * p->n_in)) || (rc = dev_alloc(&S.alpha, (size_t)nq))) {
+            if (S.F) (void)hipFree(S.F);
+            S.F = nullptr;
             return rc;
         }
-        S.b.cap = nq * p->n_in;
+        S.cap_f = nq * p->n_in;
+        S.cap_a = nq;
     }
     if (S.pending) HIPCHECK(hipStreamWaitEvent(st, S.done, 0));
-    int rc = suco_query_features(ix, Q, nq, S.b.F, stream);
+    int rc = suco_query_features(ix, Q, nq, S.F, stream);
     if (rc) return rc;
-    rc = suco_mlp_predict(p, S.b.F, nq, scale, alpha_min, alpha_max, nullptr, S.b.alpha, stream);
+    rc = suco_mlp_predict(p, S.F, nq, scale, alpha_min, alpha_max, nullptr, S.alpha, stream);
     if (rc) return rc;
-    rc = suco_query_alpha(ix, Q, nq, k, S.b.alpha, beta, ids, dists, stream);
+    rc = suco_query_alpha(ix, Q, nq, k, S.alpha, beta, ids, dists, stream);
     if (rc) return rc;
-    if (alpha_used) HIPCHECK(hipMemcpyAsync(alpha_used, S.b.alpha, sizeof(float) * nq, hipMemcpyDeviceToDevice, st));
+    if (alpha_used) HIPCHECK(hipMemcpyAsync(alpha_used, S.alpha, sizeof(float) * nq, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipEventRecord(S.done, st));
     S.pending = true;
     return SUCO_OK;

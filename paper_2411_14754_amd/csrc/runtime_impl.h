@@ -113,6 +113,14 @@ struct suco_index {
     bool pending = false;
     char *arena = nullptr;
     size_t arena_bytes = 0;
+    // staging of suco_query_learned (features and alphas), with its own lock
+    struct LearnedStage {
+        std::mutex mu;
+        float *F = nullptr, *alpha = nullptr;
+        int64_t cap_f = 0, cap_a = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } lstage;
     // optional per-step timing: event pairs around every launch
     struct EvPair { hipEvent_t a, b; int stage; };
     bool prof_on = false;
@@ -128,6 +136,14 @@ struct suco_index {
 
     void release() {
         if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
+        {
+            std::lock_guard<std::mutex> lk(lstage.mu);
+            if (lstage.done) { (void)hipEventSynchronize(lstage.done); (void)hipEventDestroy(lstage.done); }
+            if (lstage.F) (void)hipFree(lstage.F);
+            if (lstage.alpha) (void)hipFree(lstage.alpha);
+            lstage.F = nullptr; lstage.alpha = nullptr; lstage.cap_f = lstage.cap_a = 0;
+            lstage.done = nullptr; lstage.pending = false;
+        }
         for (auto &e : prof_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         prof_pool.clear();
         prof_used = 0;
