@@ -480,3 +480,23 @@ def test_s1_bf16_model_is_distance_of_rounded_values():
         bound = 2 * np.sqrt(plain) * (2.0 ** -8) * (np.linalg.norm(q[d0:d0 + w]) + np.linalg.norm(cen, axis=1)) \
             + ((2.0 ** -8) * (np.linalg.norm(q[d0:d0 + w]) + np.linalg.norm(cen, axis=1))) ** 2
         assert (np.abs(ix.centroid_dists(q, g) - plain) <= bound * (1 + 1e-9)).all()
+
+
+def test_theorem1_higher_score_means_closer_with_probability():
+    # Thm. 1: for independent random points o1, o2 with SC-score(o1) > SC-score(o2),
+    # ||o1 - q|| < ||o2 - q|| with probability at least 1/2 - 1/e^2 for suitable N_s and
+    # alpha.  Checked on i.i.d. Gaussian data (independent subspace distances) with
+    # SC-Linear's exact scores (Alg. 1), over all such pairs of points.
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((2000, 32)).astype(np.float32)
+    Q = rng.standard_normal((4, 32)).astype(np.float32)
+    _, _, sc = oracle.sclinear(X, 8, Q, 10, 0.1, 0.05, want_scores=True)
+    bound = 0.5 - np.exp(-2.0)
+    for qi, q in enumerate(Q):
+        s = sc[qi].astype(np.int64)
+        dist = np.sqrt(((X.astype(np.float64) - q) ** 2).sum(axis=1))
+        higher = s[:, None] > s[None, :]
+        closer = dist[:, None] < dist[None, :]
+        frac = (higher & closer).sum() / higher.sum()
+        assert frac >= bound, (qi, frac)
+        assert frac > 0.5   # better than chance: inverted or shuffled scores fail here
