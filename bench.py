@@ -388,6 +388,9 @@ def bench_batched_deep(args, log):
     plain_ids, plain_d = ids.clone(), dists.clone()
     rec_plain = recall_at(ids[:n_gt], gt)
     log(f"plain: {ms_plain / args.steps:.2f} ms per 100,000 queries, recall@10={rec_plain:.4f}")
+    if args.plain_only:
+        bench_deep_plain(args, log, ix, suco, Qd, X, Q, sp, alpha, ms_plain, rec_plain, plain, build_s)
+        return
     sizes = W.batch_sizes(nq)
     b = suco.Batcher(ix, 4096, k, beta)
 
@@ -436,6 +439,35 @@ def bench_batched_deep(args, log):
                    "plain_one_call": {"qps": round(nq * args.steps / (ms_plain / 1e3), 1),
                                       "recall_at_10_first_10000": round(rec_plain, 5)},
                    "tuning_s": round(tune_s, 2), "tuned": tuned,
+                   "index_build_s": round(build_s, 3)},
+        "kernels": per_kernel, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ix.free()
+
+
+def bench_deep_plain(args, log, ix, suco, Qd, X, Q, sp, alpha, ms_plain, rec_plain, plain, build_s):
+    """The deep_like workload through the plain path only: the whole 100,000-query stream in one call."""
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
+    stage, per_kernel = stage_profile(ix, plain, 1, sb, nq)
+    dom = max(sb, key=lambda t: stage[t][0])
+    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    achieved = per_kernel[dom]["gbs"]
+    roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "deep_like")}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "100,000 queries")
+    line = {
+        "metric": "QPS of 100,000 queries in one call, Deep-like n=10M d=96: plain SuCo on 1 GPU",
+        "value": round(nq * args.steps / (ms_plain / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(ms_plain / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"deep_like n={n} d={d} unit-norm, N_s={ns}, sqrtK={sk}, nq={nq} in one call, "
+                               f"k={k}, alpha={alpha}, beta={beta}",
+                   "form": "plain", "recall_at_10_first_10000": round(rec_plain, 5),
                    "index_build_s": round(build_s, 3)},
         "kernels": per_kernel, "roofline": roofline, "cpu_baseline": cpu,
     }
@@ -560,7 +592,8 @@ def main():
     ap.add_argument("--tile-max", type=int, default=0, help="largest collision tile (0: library default)")
     ap.add_argument("--query-chunk", type=int, default=0, help="queries per pass (0: library default)")
     ap.add_argument("--alpha", type=float, default=None, help="time this alpha and skip the sweep")
-    ap.add_argument("--plain-only", action="store_true", help="report plain SuCo only (no learned+batched)")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="sift_like and deep_like: report plain SuCo only (no learned or batched form)")
     ap.add_argument("--train-queries", type=int, default=20_000)
     ap.add_argument("--val-queries", type=int, default=10_000)
     ap.add_argument("--epochs", type=int, default=25)
