@@ -135,12 +135,8 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
     // eight dimensions at a time before their FMAs (same order), so a half
     // costs a few memory round trips rather than one per dimension.
     const HalfDims hd2[2] = {a.ix.halves[2 * i], a.ix.halves[2 * i + 1]};
-    for (int t = tid; t < 2 * sk; t += NT) {
-        const int h = t >= sk, c = t - h * sk;
-        if (a.Dext) {
-            Dr[h][c] = a.Dext[((int64_t)ql * 2 * ns + 2 * i + h) * sk + c];
-            continue;
-        }
+    auto centre_dist = [&](const int h, const int c) -> float {
+        if (a.Dext) return a.Dext[((int64_t)ql * 2 * ns + 2 * i + h) * sk + c];
         const HalfDims hd = hd2[h];
         const float *cp = a.ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
         const float *qp = q + hd.dim0;
@@ -161,28 +157,105 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
                 }
             }
         }
-        Dr[h][c] = s;
-    }
-    __syncthreads();
-    // ranks: ascending distance, ties by centre id
-    for (int t = tid; t < 2 * sk; t += NT) {
-        const int h = t >= sk, c = t - h * sk;
-        const float v = Dr[h][c];
-        int r = 0;
-        for (int c2 = 0; c2 < sk; ++c2) {
-            const float v2 = Dr[h][c2];
-            r += (v2 < v) || (v2 == v && c2 < c);
+        return s;
+    };
+    if constexpr (NT == kWave) {
+        // one wave, sk <= 64: lane c holds centre c of each half in a register;
+        // its rank (ascending distance, ties by centre id) counts the lanes
+        // before it, read one at a time with readlane
+        const bool live = tid < sk;
+        float v[2] = {0.f, 0.f};
+        if (live && a.Dext) {
+            v[0] = centre_dist(0, tid);
+            v[1] = centre_dist(1, tid);
+        } else if (live) {
+            // both halves' loads issued together, each half summed in its own
+            // dimension order
+            const float *cp[2], *qp[2];
+            int w[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                w[h] = hd2[h].w;
+                cp[h] = a.ix.cent + (int64_t)sk * hd2[h].dim0 + (int64_t)tid * hd2[h].w;
+                qp[h] = q + hd2[h].dim0;
+            }
+            const int wmax = w[0] > w[1] ? w[0] : w[1];
+            for (int j0 = 0; j0 < wmax; j0 += 8) {
+                float qv[2][8], cv[2][8];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool in = j0 + u < w[h];
+                        qv[h][u] = in ? qp[h][j0 + u] : 0.f;
+                        cv[h][u] = in ? cp[h][j0 + u] : 0.f;
+                    }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (j0 + u < w[h]) {
+                            const float t2 = qv[h][u] - cv[h][u];
+                            v[h] = fmaf(t2, t2, v[h]);
+                        }
+                    }
+            }
         }
-        Ds[h][r] = v;
-        Ix[h][r] = c;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int r = 0;
+            for (int c2 = 0; c2 < sk; ++c2) {
+                const float v2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[h]), c2));
+                r += (v2 < v[h]) || (v2 == v[h] && c2 < tid);
+            }
+            if (live) {
+                Ds[h][r] = v[h];
+                Ix[h][r] = tid;
+            }
+        }
+    } else {
+        for (int t = tid; t < 2 * sk; t += NT) {
+            const int h = t >= sk, c = t - h * sk;
+            Dr[h][c] = centre_dist(h, c);
+        }
+        __syncthreads();
+        // ranks: ascending distance, ties by centre id
+        for (int t = tid; t < 2 * sk; t += NT) {
+            const int h = t >= sk, c = t - h * sk;
+            const float v = Dr[h][c];
+            int r = 0;
+            for (int c2 = 0; c2 < sk; ++c2) {
+                const float v2 = Dr[h][c2];
+                r += (v2 < v) || (v2 == v && c2 < c);
+            }
+            Ds[h][r] = v;
+            Ix[h][r] = c;
+        }
     }
     __syncthreads();
-    // cell sizes in rank order, then per-row prefix sums
+    // cell sizes in rank order, eight gathers in flight per thread (a missing
+    // slot reads cell 0 and is not stored), then per-row prefix sums
     const int stride = sk + 1;
     const uint32_t *cs = a.ix.csize + (int64_t)i * K;
-    for (int t = tid; t < sk * sk; t += NT) {
-        const int r1 = t / sk, r2 = t - r1 * sk;
-        Ptab[r1 * stride + r2 + 1] = cs[Ix[0][r1] * sk + Ix[1][r2]];
+    {
+        const int rq = NT / sk, rr = NT - rq * sk;      // NT = rq rows + rr columns
+        int r1 = tid / sk, r2 = tid - r1 * sk;
+        for (int t0 = 0; t0 < sk * sk; t0 += 8 * NT) {
+            uint32_t val[8];
+            int at[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = r1 < sk;
+                at[u] = in ? r1 * stride + r2 + 1 : -1;
+                val[u] = cs[in ? Ix[0][r1] * sk + Ix[1][r2] : 0];
+                r1 += rq;
+                r2 += rr;
+                if (r2 >= sk) { r2 -= sk; ++r1; }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (at[u] >= 0) Ptab[at[u]] = val[u];
+        }
     }
     __syncthreads();
     if (tid < sk) {
@@ -202,33 +275,37 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
     const bool row = tid < sk;
     const float d1 = row ? Ds[0][tid] : 0.f;
     const uint32_t *prow = Ptab + (row ? tid : 0) * stride;
-    auto cnt = [&](float v) -> int {   // #{r2 : d1 + D2s[r2] <= v}
-        int lo2 = 0, hi2 = sk;
-        while (lo2 < hi2) {
-            const int m = (lo2 + hi2) >> 1;
-            if (d1 + Ds[1][m] <= v) lo2 = m + 1; else hi2 = m;
+    // #{r2 : d1 + D2s[r2] <= v}, known to lie in [l2, h2]
+    auto cnt = [&](float v, int l2, int h2) -> int {
+        while (l2 < h2) {
+            const int m = (l2 + h2) >> 1;
+            if (d1 + Ds[1][m] <= v) l2 = m + 1; else h2 = m;
         }
-        return lo2;
+        return l2;
     };
-    // W(lo) < A <= W(hi) throughout
+    auto total = [&](uint32_t w) -> uint32_t {
+        if constexpr (NT == kWave) return wave_total(w);
+        else return block_sum<NT>(w, red);
+    };
+    // W(lo) < A <= W(hi) throughout; every row keeps its counts at lo and hi
+    // (the keys are monotone in both ranks, so each row's count at a value
+    // between them lies between its counts there).  At lo = kmin - 1 ulp no
+    // key is counted; at hi = kmax every key is.
     const float kmin = Ds[0][0] + Ds[1][0];
     const float kmax = Ds[0][sk - 1] + Ds[1][sk - 1];
     int64_t lo = (int64_t)__float_as_uint(kmin) - 1;
     int64_t hi = (int64_t)__float_as_uint(kmax);
     uint32_t Wlo = 0;
+    int cl = 0, ch = row ? sk : 0;
     while (hi - lo > 1) {
         const int64_t mid = lo + ((hi - lo) >> 1);
         const float v = __uint_as_float((uint32_t)mid);
-        uint32_t w = row ? prow[cnt(v)] : 0u;
-        w = block_sum<NT>(w, red);
-        if (w >= A) hi = mid; else { lo = mid; Wlo = w; }
+        const int c = row ? cnt(v, cl, ch) : 0;
+        const uint32_t w = total(row ? prow[c] : 0u);
+        if (w >= A) { hi = mid; ch = c; } else { lo = mid; cl = c; Wlo = w; }
     }
-    // cells with key < v* (= hi) and the tie cells with key == v*
-    int cl = 0, ch = 0;
-    if (row) {
-        cl = lo < 0 ? 0 : cnt(__uint_as_float((uint32_t)lo));
-        ch = cnt(__uint_as_float((uint32_t)hi));
-    }
+    // cells with key < v* (= hi): the first cl of each row; the tie cells with
+    // key == v*: columns [cl, ch)
     const uint32_t tw = row ? prow[ch] - prow[cl] : 0u;
     const uint32_t R = A - Wlo;
     uint32_t tot;
@@ -246,7 +323,7 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
     const uint32_t myw = row ? prow[len] : 0u;
     uint32_t ntot;
     const uint32_t off = block_excl_scan<NT>((uint32_t)len, red, &ntot);
-    const uint32_t ap = block_sum<NT>(myw, red);
+    const uint32_t ap = total(myw);
     uint16_t *out = a.cells + ((int64_t)ql * ns + i) * K;
     if (row) {
         const int c1 = Ix[0][tid] * sk;
