@@ -21,7 +21,8 @@
 
 namespace suco {
 
-// Sum over the block; every thread gets the total.
+// Sum over the block; every thread gets the total.  Like the scans below, it
+// is called by every thread of the block.
 template <int NT>
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red) {
     v = wave_sum(v);
@@ -42,12 +43,7 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red) {
 template <int NT>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
-    }
+    const uint32_t x = wave_incl_scan(v);
     __syncthreads();
     if (lane == kWave - 1) red[w] = x;
     __syncthreads();
@@ -67,12 +63,7 @@ template <int NT>
 __device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint32_t *red2, uint32_t *ea,
                                                  uint32_t *eb, uint32_t *ta, uint32_t *tb) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    uint32_t xa = va, xb = vb;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t ya = __shfl_up(xa, o, kWave), yb = __shfl_up(xb, o, kWave);
-        if (lane >= o) { xa += ya; xb += yb; }
-    }
+    const uint32_t xa = wave_incl_scan(va), xb = wave_incl_scan(vb);
     __syncthreads();
     if (lane == kWave - 1) { red2[2 * w] = xa; red2[2 * w + 1] = xb; }
     __syncthreads();
@@ -284,7 +275,7 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
         return l2;
     };
     auto total = [&](uint32_t w) -> uint32_t {
-        if constexpr (NT == kWave) return wave_total(w);
+        if constexpr (NT == kWave) return wave_sum(w);
         else return block_sum<NT>(w, red);
     };
     // W(lo) < A <= W(hi) throughout; every row keeps its counts at lo and hi

@@ -8,12 +8,6 @@
 
 namespace suco {
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
 // Inclusive prefix sum over the 64 lanes with DPP moves (row shifts within
 // 16-lane rows, then the row broadcasts of lanes 15 and 31); lanes a move
 // does not reach add zero.
@@ -27,8 +21,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-// Sum over the 64 lanes, the same in every lane.
-__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+// Sum over the 64 lanes, the same in every lane (all lanes active).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), kWave - 1);
 }
 
