@@ -945,89 +945,71 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
 // k-th key, so one ballot per iteration finds the few rows that need the
 // (cross-lane) insertion; the others cost nothing more.  The list is the set
 // of the k smallest keys seen, whatever the insertion order (keys are unique).
-template <int NT, bool ROWS8, int UM>
-__device__ __forceinline__ void rerank_item(const RerankPass &r, const int item) {
-    constexpr int NRG = kMaxU / UM;
-    __shared__ uint64_t wl[NT / kWave][kMaxK];
-    const int ql = item / r.parts, part = item - ql * r.parts;
+//
+// Byte rows and a query whose values are all integers in 0..255, with d a
+// multiple of 16 and at most 256: every squared difference and every partial
+// sum of the FP32 computation is an integer below 2^24, so that computation
+// is exact and equals the integer sum of (x - q)^2 = x.x - 2 x.q + q.q, which
+// is taken here with 4-byte dot products (v_dot4_u32_u8) on 16-byte slices:
+// the same keys as the FP32 arithmetic, with a fraction of the instructions.
+constexpr int kIntSlices = 2;                // 16-byte slices per lane
+constexpr int kIntGroups = kMaxU / kIntSlices;   // row groups per wave iteration
+
+__device__ __forceinline__ uint32_t dot16(const uint4 a, const uint4 b, uint32_t c) {
+    c = __builtin_amdgcn_udot4(a.x, b.x, c, false);
+    c = __builtin_amdgcn_udot4(a.y, b.y, c, false);
+    c = __builtin_amdgcn_udot4(a.z, b.z, c, false);
+    return __builtin_amdgcn_udot4(a.w, b.w, c, false);
+}
+
+// Lanes per row of the integer path: the smallest power of two with at most
+// kIntSlices slices per lane (d/16 <= 16, so at most 8).
+__device__ __forceinline__ int int_group(int d16) {
+    int G = 1;
+    while (G * kIntSlices < d16) G *= 2;
+    return G;
+}
+
+template <int NT>
+__device__ __forceinline__ void rerank_rows_int(const RerankPass &r, const uint32_t *cid, const int cn,
+                                                const uint4 (&qb)[kIntSlices], const uint32_t qq, const int G,
+                                                uint64_t &best) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int G = r.G, R = kWave / G, li = lane & (G - 1), slot = lane / G;
-    const int d4 = r.d >> 2, k = r.k;
-    float4 qr[UM];
-    const float4 *q4 = reinterpret_cast<const float4 *>(r.Q + (int64_t)ql * r.d);
+    const int R = kWave / G, li = lane & (G - 1), slot = lane / G;
+    const int d16 = r.d >> 4, k = r.k;
+    for (int base = wv * R * kIntGroups; base < cn; base += (NT / kWave) * R * kIntGroups) {
+        uint32_t id[kIntGroups];
+        bool valid[kIntGroups];
+        uint4 x[kIntGroups][kIntSlices];
 #pragma unroll
-    for (int u = 0; u < UM; ++u) {
-        const int j = li + G * u;
-        qr[u] = (u < r.U && j < d4) ? q4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    uint64_t best = ~0ull;
-    const int64_t rb = (int64_t)part * r.rows_per_part;
-    const int64_t rows = r.rows_dev ? (r.rows_dev[ql] < r.B ? (int64_t)r.rows_dev[ql] : r.B) : r.B;
-    const int64_t re = rb + r.rows_per_part < rows ? rb + r.rows_per_part : rows;
-    const uint32_t *cq = r.cand + (int64_t)ql * r.B;
-    // candidate ids are staged in LDS a chunk at a time (one coalesced read),
-    // so each row's load depends on an LDS read rather than a global one
-    __shared__ uint32_t cid[kRowChunk];
-    for (int64_t cb = rb; cb < re; cb += kRowChunk) {
-    const int cn = (int)(re - cb < kRowChunk ? re - cb : kRowChunk);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cn; t += NT) cid[t] = cq[cb + t];
-    __syncthreads();
-    for (int base = wv * R * NRG; base < cn; base += (NT / kWave) * R * NRG) {
-        uint32_t id[NRG];
-        bool valid[NRG];
-        float4 x[NRG][UM];
-        uint32_t x8[NRG][UM];
-#pragma unroll
-        for (int g = 0; g < NRG; ++g) {
+        for (int g = 0; g < kIntGroups; ++g) {
             const int rw = base + g * R + slot;
             id[g] = rw < cn ? cid[rw] : 0u;
             valid[g] = rw < cn && id[g] < r.n;   // ids outside [0, n) are ignored
             id[g] = valid[g] ? id[g] : 0u;
         }
+        // every load is issued (a slice past the row reads the row's first one
+        // and is not used), so none waits for another
 #pragma unroll
-        for (int g = 0; g < NRG; ++g) {
+        for (int g = 0; g < kIntGroups; ++g)
 #pragma unroll
-            for (int u = 0; u < UM; ++u) {
+            for (int u = 0; u < kIntSlices; ++u) {
                 const int j = li + G * u;
-                const bool in = u < r.U && j < d4;
-                if constexpr (ROWS8) {
-                    x8[g][u] = in ? reinterpret_cast<const uint32_t *>(r.X8 + (int64_t)id[g] * r.d)[j] : 0u;
-                } else {
-                    x[g][u] = in ? reinterpret_cast<const float4 *>(r.X + (int64_t)id[g] * r.d)[j]
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
+                x[g][u] = reinterpret_cast<const uint4 *>(r.X8 + (int64_t)id[g] * r.d)[j < d16 ? j : 0];
             }
-        }
-        uint64_t key[NRG];
+        uint64_t key[kIntGroups];
 #pragma unroll
-        for (int g = 0; g < NRG; ++g) {
-            float acc = 0.f;
+        for (int g = 0; g < kIntGroups; ++g) {
+            uint32_t s = qq;
 #pragma unroll
-            for (int u = 0; u < UM; ++u) {
-                const int j = li + G * u;
-                if (u < r.U && j < d4) {
-                    float4 xv;
-                    if constexpr (ROWS8) {
-                        const uint32_t b = x8[g][u];
-                        xv = make_float4((float)(b & 0xffu), (float)((b >> 8) & 0xffu), (float)((b >> 16) & 0xffu),
-                                         (float)(b >> 24));
-                    } else {
-                        xv = x[g][u];
-                    }
-                    float t;
-                    t = xv.x - qr[u].x; acc = fmaf(t, t, acc);
-                    t = xv.y - qr[u].y; acc = fmaf(t, t, acc);
-                    t = xv.z - qr[u].z; acc = fmaf(t, t, acc);
-                    t = xv.w - qr[u].w; acc = fmaf(t, t, acc);
-                }
-            }
-            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-            key[g] = valid[g] ? (((uint64_t)__float_as_uint(acc) << 32) | id[g]) : ~0ull;
+            for (int u = 0; u < kIntSlices; ++u)
+                if (li + G * u < d16) s += dot16(x[g][u], x[g][u], 0u) - 2u * dot16(x[g][u], qb[u], 0u);
+            s = group_sum(s, G);
+            key[g] = valid[g] ? (((uint64_t)__float_as_uint((float)s) << 32) | id[g]) : ~0ull;
         }
 #pragma unroll
-        for (int g = 0; g < NRG; ++g) {
-            const uint64_t kth = shfl64(best, k - 1);   // every lane takes part in the shuffle
+        for (int g = 0; g < kIntGroups; ++g) {
+            const uint64_t kth = shfl64(best, k - 1);
             uint64_t m = __ballot(li == 0 && key[g] < kth);
             while (m != 0ull) {
                 const int src = __ffsll((unsigned long long)m) - 1;
@@ -1036,6 +1018,143 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
             }
         }
     }
+}
+
+template <int NT, bool ROWS8, int UM>
+__device__ __forceinline__ void rerank_item(const RerankPass &r, const int item) {
+    constexpr int NRG = kMaxU / UM;
+    __shared__ uint64_t wl[NT / kWave][kMaxK];
+    // candidate ids are staged in LDS a chunk at a time (one coalesced read),
+    // so each row's load depends on an LDS read rather than a global one
+    __shared__ uint32_t cid[kRowChunk];
+    const int ql = item / r.parts, part = item - ql * r.parts;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int k = r.k;
+    uint64_t best = ~0ull;
+    const int64_t rb = (int64_t)part * r.rows_per_part;
+    const int64_t rows = r.rows_dev ? (r.rows_dev[ql] < r.B ? (int64_t)r.rows_dev[ql] : r.B) : r.B;
+    const int64_t re = rb + r.rows_per_part < rows ? rb + r.rows_per_part : rows;
+    const uint32_t *cq = r.cand + (int64_t)ql * r.B;
+    auto stage = [&](int64_t cb) -> int {
+        const int cn = (int)(re - cb < kRowChunk ? re - cb : kRowChunk);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += NT) cid[t] = cq[cb + t];
+        __syncthreads();
+        return cn;
+    };
+    bool int_path = false;
+    if constexpr (ROWS8) {
+        if ((r.d & 15) == 0 && r.d <= 256) {
+            const float *qf = r.Q + (int64_t)ql * r.d;
+            bool ok = true;
+            for (int t = threadIdx.x; t < r.d; t += NT) {
+                const float v = qf[t];
+                ok = ok && v >= 0.f && v <= 255.f && v == rintf(v);
+            }
+            int_path = __syncthreads_and(ok);
+        }
+    }
+    if (ROWS8 && int_path) {
+        // the query's slices as bytes and their squared norm
+        const int d16 = r.d >> 4;
+        const int Gi = int_group(d16), lii = lane & (Gi - 1);
+        uint4 qb[kIntSlices];
+        uint32_t qq = 0u;
+#pragma unroll
+        for (int u = 0; u < kIntSlices; ++u) {
+            const int j = lii + Gi * u;
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            if (j < d16) {
+                const float4 *q4s = reinterpret_cast<const float4 *>(r.Q + (int64_t)ql * r.d + 16 * j);
+#pragma unroll
+                for (int v4 = 0; v4 < 4; ++v4) {
+                    const float4 f = q4s[v4];
+                    w[v4] = (uint32_t)f.x | ((uint32_t)f.y << 8) | ((uint32_t)f.z << 16) | ((uint32_t)f.w << 24);
+                }
+            }
+            qb[u] = make_uint4(w[0], w[1], w[2], w[3]);
+            qq = dot16(qb[u], qb[u], qq);
+        }
+        for (int64_t cb = rb; cb < re; cb += kRowChunk) {
+            const int cn = stage(cb);
+            rerank_rows_int<NT>(r, cid, cn, qb, qq, Gi, best);
+        }
+    } else {
+        const int G = r.G, R = kWave / G, li = lane & (G - 1), slot = lane / G;
+        const int d4 = r.d >> 2;
+        float4 qr[UM];
+        const float4 *q4 = reinterpret_cast<const float4 *>(r.Q + (int64_t)ql * r.d);
+#pragma unroll
+        for (int u = 0; u < UM; ++u) {
+            const int j = li + G * u;
+            qr[u] = (u < r.U && j < d4) ? q4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        for (int64_t cb = rb; cb < re; cb += kRowChunk) {
+            const int cn = stage(cb);
+            for (int base = wv * R * NRG; base < cn; base += (NT / kWave) * R * NRG) {
+                uint32_t id[NRG];
+                bool valid[NRG];
+                float4 x[NRG][UM];
+                uint32_t x8[NRG][UM];
+#pragma unroll
+                for (int g = 0; g < NRG; ++g) {
+                    const int rw = base + g * R + slot;
+                    id[g] = rw < cn ? cid[rw] : 0u;
+                    valid[g] = rw < cn && id[g] < r.n;   // ids outside [0, n) are ignored
+                    id[g] = valid[g] ? id[g] : 0u;
+                }
+#pragma unroll
+                for (int g = 0; g < NRG; ++g) {
+#pragma unroll
+                    for (int u = 0; u < UM; ++u) {
+                        const int j = li + G * u;
+                        const bool in = u < r.U && j < d4;
+                        if constexpr (ROWS8) {
+                            x8[g][u] = in ? reinterpret_cast<const uint32_t *>(r.X8 + (int64_t)id[g] * r.d)[j] : 0u;
+                        } else {
+                            x[g][u] = in ? reinterpret_cast<const float4 *>(r.X + (int64_t)id[g] * r.d)[j]
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+                    }
+                }
+                uint64_t key[NRG];
+#pragma unroll
+                for (int g = 0; g < NRG; ++g) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int u = 0; u < UM; ++u) {
+                        const int j = li + G * u;
+                        if (u < r.U && j < d4) {
+                            float4 xv;
+                            if constexpr (ROWS8) {
+                                const uint32_t b = x8[g][u];
+                                xv = make_float4((float)(b & 0xffu), (float)((b >> 8) & 0xffu), (float)((b >> 16) & 0xffu),
+                                                 (float)(b >> 24));
+                            } else {
+                                xv = x[g][u];
+                            }
+                            float t;
+                            t = xv.x - qr[u].x; acc = fmaf(t, t, acc);
+                            t = xv.y - qr[u].y; acc = fmaf(t, t, acc);
+                            t = xv.z - qr[u].z; acc = fmaf(t, t, acc);
+                            t = xv.w - qr[u].w; acc = fmaf(t, t, acc);
+                        }
+                    }
+                    for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+                    key[g] = valid[g] ? (((uint64_t)__float_as_uint(acc) << 32) | id[g]) : ~0ull;
+                }
+#pragma unroll
+                for (int g = 0; g < NRG; ++g) {
+                    const uint64_t kth = shfl64(best, k - 1);   // every lane takes part in the shuffle
+                    uint64_t m = __ballot(li == 0 && key[g] < kth);
+                    while (m != 0ull) {
+                        const int src = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1ull;
+                        topk_insert(best, shfl64(key[g], src), k, lane);
+                    }
+                }
+            }
+        }
     }
     if (lane < k) wl[wv][lane] = best;
     __syncthreads();

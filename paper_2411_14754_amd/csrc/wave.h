@@ -26,6 +26,17 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), kWave - 1);
 }
 
+// Sum over aligned groups of G lanes (G in {1, 2, 4, 8, 16}) with DPP moves
+// (quad permutations, then the half-row and row mirrors); every lane of a
+// group ends with the group's sum.
+__device__ __forceinline__ uint32_t group_sum(uint32_t v, int G) {
+    if (G >= 2) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xb1, 0xf, 0xf, false);    // quad_perm 1,0,3,2
+    if (G >= 4) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4e, 0xf, 0xf, false);    // quad_perm 2,3,0,1
+    if (G >= 8) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xf, 0xf, false);   // row_half_mirror
+    if (G >= 16) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xf, 0xf, false);  // row_mirror
+    return v;
+}
+
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     uint32_t lo = __shfl((uint32_t)v, src, kWave);
     uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);

@@ -281,5 +281,18 @@ def test_byte_rows_equal_fp32_rows(suco):
     oix = oracle.Index(X, 8, 20, c32, asg)
     ref = oix.query(Q, 10, 0.02, 0.01)
     assert np.array_equal(ra[0].cpu().numpy(), ref["ids"])
+    # queries that are not all bytes (a fraction, a value above 255) take the
+    # FP32 arithmetic on the byte rows, mixed in one batch with byte queries
+    Qm = Q.copy()
+    Qm[::2, 3] += 0.5
+    Qm[1::4, 7] = 256.0
+    Qmd = torch.from_numpy(Qm).cuda()
+    ra = a.query(Qmd, 10, 0.02, 0.01)
+    rb = b.query(Qmd, 10, 0.02, 0.01)
+    torch.cuda.synchronize()
+    assert np.array_equal(ra[0].cpu().numpy(), rb[0].cpu().numpy())
+    assert np.array_equal(ra[1].cpu().numpy(), rb[1].cpu().numpy())
+    ref = oix.query(Qm, 10, 0.02, 0.01)
+    check_topk(X, Qm, ra[0].cpu().numpy(), ra[1].cpu().numpy(), ref["ids"], ref["dists"], 10)
     a.free()
     b.free()
