@@ -378,14 +378,17 @@ constexpr int kBuckets = 1024;      // positions beyond kBuckets << kBucketShift
 
 template <int NT>
 struct CollideLds {
-    uint32_t G[kMaxNs + 2];
-    uint32_t cur[kMaxNs + 2];
+    // per-tile counters, two sets used by alternate tiles: a tile resets the
+    // next tile's set while it builds its own lists, so no barrier is needed
+    // between the end of one tile and the counting of the next
+    uint32_t G[2][kMaxNs + 2];
+    uint32_t cur[2][kMaxNs + 2];
     int64_t rstart[NT];          // start in ids16 of each non-empty run of the batch (compacted)
     uint32_t rpre[NT];           // ids before each of those runs in the batch
     uint32_t red[2 * (NT / kWave) + 2];
     uint16_t first[kBuckets];    // run holding position b << kBucketShift
     uint16_t touched[kTouchCap];
-    uint32_t n_touched;
+    uint32_t n_touched[2];
 };
 
 struct RunBatch {
@@ -450,7 +453,7 @@ __device__ __forceinline__ uint32_t collide_fetch(const QueryPass &a, const Coll
 // +1 on the scores of the fetched ids; words touched for the first time are listed.
 template <int NT>
 __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, const uint32_t (&lid)[kCollideUnroll],
-                                              const uint32_t vm) {
+                                              const uint32_t vm, const int b) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
 #pragma unroll
@@ -463,7 +466,7 @@ __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, c
         if (m != 0ull) {
             const int leader = __ffsll((unsigned long long)m) - 1;
             uint32_t base = 0u;
-            if (lane == leader) base = atomicAdd(&L.n_touched, (uint32_t)__popcll(m));
+            if (lane == leader) base = atomicAdd(&L.n_touched[b], (uint32_t)__popcll(m));
             base = __shfl(base, leader, kWave);
             if (first) {
                 const uint32_t pos = base + (uint32_t)__popcll(m & lanes_below);
@@ -473,18 +476,23 @@ __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, c
     }
 }
 
-// After the counting of tile p: tile histogram, level lists, optional dense
-// scores; then the scores, G and the touched list are reset for the next tile.
-// Starts and ends with a barrier.
+// After the counting of tile p (counters of set b): tile histogram, level
+// lists, optional dense scores; the scores are left zero for the next tile and
+// the other counter set is reset for it.  Starts with a barrier.  When the
+// tile's words were listed and no dense scores are written, each listed word
+// is read once into a register and zeroed at once, and the function ends
+// without a barrier (the next tile's counting touches nothing this tile still
+// reads); otherwise it ends with one after clearing the scores.
 template <int NT>
 __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
-                                               const int p) {
+                                               const int p, const int b) {
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int words = TILE >> 2;
     // the caller's last barrier follows the counting
-    const uint32_t nt = L.n_touched;
+    const uint32_t nt = L.n_touched[b];
     const bool sparse = nt <= (uint32_t)kTouchCap;
+    const bool early = sparse && a.scores == nullptr;
     const int nw = sparse ? (int)nt : words;
     // Counts of bytes >= t, two thresholds per 32-bit counter (16-bit halves:
     // a thread sees at most 4 * 32 bytes, a wave at most 64 times that).  In
@@ -501,8 +509,16 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
         if (sparse && j < nw) {
             wk[q] = L.touched[j];
             xk[q] = sc[wk[q]];
+            if (early) sc[wk[q]] = 0u;
         }
     }
+    // the other set was last used by the tile before this one, which every
+    // wave finished before the barrier that ended this tile's counting
+    for (int t = tid; t < ns + 2; t += NT) {
+        L.G[b ^ 1][t] = 0u;
+        L.cur[b ^ 1][t] = 0u;
+    }
+    if (tid == 0) L.n_touched[b ^ 1] = 0u;
     for (int t0 = 1; t0 <= ns; t0 += 8) {
         uint32_t c[4] = {0, 0, 0, 0};
         auto tally = [&](uint32_t x) {
@@ -528,8 +544,8 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
             if (t0 + 2 * v <= ns) {
                 const uint32_t sum = wave_sum(c[v]);
                 if (lane == 0) {
-                    atomicAdd(&L.G[t0 + 2 * v], sum & 0xffffu);
-                    if (t0 + 2 * v + 1 <= ns) atomicAdd(&L.G[t0 + 2 * v + 1], sum >> 16);
+                    atomicAdd(&L.G[b][t0 + 2 * v], sum & 0xffffu);
+                    if (t0 + 2 * v + 1 <= ns) atomicAdd(&L.G[b][t0 + 2 * v + 1], sum >> 16);
                 }
             }
         }
@@ -541,7 +557,7 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t sv = (x >> (8 * u)) & 0xffu;
-            if (sv != 0u) seg[L.G[sv + 1] + atomicAdd(&L.cur[sv], 1u)] = (uint16_t)(4 * w + u);
+            if (sv != 0u) seg[L.G[b][sv + 1] + atomicAdd(&L.cur[b][sv], 1u)] = (uint16_t)(4 * w + u);
         }
     };
     if (sparse) {
@@ -562,7 +578,8 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     const int64_t t0 = (int64_t)p * TILE;
     const int64_t valid = a.ix.n - t0 < TILE ? a.ix.n - t0 : TILE;
     uint32_t *h = a.hist + ((int64_t)ql * P + p) * (ns + 2);
-    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : L.G[t];
+    for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : L.G[b][t];
+    if (early) return;
     __syncthreads();
     if (sparse) {
 #pragma unroll
@@ -572,11 +589,6 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
         uint4 *z = reinterpret_cast<uint4 *>(sc);
         for (int w = tid; w < (words >> 2); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
     }
-    for (int t = tid; t < ns + 2; t += NT) {
-        L.G[t] = 0u;
-        L.cur[t] = 0u;
-    }
-    if (tid == 0) L.n_touched = 0u;
     __syncthreads();
 }
 
@@ -584,7 +596,7 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
 // cells than one batch holds): runs are reloaded batch by batch.
 template <int NT>
 __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
-                                             const int p, const int my_nc, const int c_first) {
+                                             const int p, const int my_nc, const int c_first, int &b) {
     const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
     const int RJ = a.runs_per_sub;
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
@@ -605,11 +617,12 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
         for (uint32_t e0 = 0; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid[kCollideUnroll];
             const uint32_t vm = collide_fetch<NT>(a, L, e0, rb, lid);
-            collide_count<NT>(L, sc, lid, vm);
+            collide_count<NT>(L, sc, lid, vm, b);
         }
         __syncthreads();
     }
-    collide_finish<NT>(a, L, sc, ql, p);
+    collide_finish<NT>(a, L, sc, ql, p, b);
+    b ^= 1;
 }
 
 // The tiles of one (query, tile group) when every subspace's activated cells
@@ -620,7 +633,8 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
 // for them before they are needed.
 template <int NT>
 __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc,
-                                                        const int ql, const int g, const int my_nc, const int c_first) {
+                                                        const int ql, const int g, const int my_nc, const int c_first,
+                                                        int &b) {
     const int P = a.ix.P, K = a.ix.K, TILE = a.ix.TILE, S = a.tgroups;
     const int RJ = a.runs_per_sub, ns = a.ix.ns;
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
@@ -639,11 +653,11 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
         re = tob[(int64_t)pn * (K + 1) + 1];
     }
     for (int p = g; p < P; p += S) {
-        collide_count<NT>(L, sc, lid, vm);
+        collide_count<NT>(L, sc, lid, vm, b);
         for (uint32_t e0 = NT * kCollideUnroll; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid2[kCollideUnroll];
             const uint32_t vm2 = collide_fetch<NT>(a, L, e0, rb, lid2);
-            collide_count<NT>(L, sc, lid2, vm2);
+            collide_count<NT>(L, sc, lid2, vm2, b);
         }
         __syncthreads();
         // stage the next tile of the group (an empty one after the last) and
@@ -655,7 +669,8 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
         const int pn = p + 2 * S < P ? p + 2 * S : p;
         rs = tob[(int64_t)pn * (K + 1)];
         re = tob[(int64_t)pn * (K + 1) + 1];
-        collide_finish<NT>(a, L, sc, ql, p);
+        collide_finish<NT>(a, L, sc, ql, p, b);
+        b ^= 1;
     }
 }
 
@@ -672,11 +687,12 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
         uint4 *z = reinterpret_cast<uint4 *>(sc);
         for (int w = threadIdx.x; w < (a.ix.TILE >> 4); w += NT) z[w] = make_uint4(0u, 0u, 0u, 0u);
         for (int t = threadIdx.x; t < a.ix.ns + 2; t += NT) {
-            L.G[t] = 0u;
-            L.cur[t] = 0u;
+            L.G[0][t] = 0u;
+            L.cur[0][t] = 0u;
         }
-        if (threadIdx.x == 0) L.n_touched = 0u;
+        if (threadIdx.x == 0) L.n_touched[0] = 0u;
     }
+    int b = 0;                         // counter set of the block's next tile
     const int RJ = a.runs_per_sub, ns = a.ix.ns;
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
@@ -686,9 +702,9 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
         const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
         const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
         if (__syncthreads_or(my_nc > RJ)) {
-            for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first);
+            for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first, b);
         } else {
-            collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first);
+            collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first, b);
         }
     }
 }
