@@ -108,6 +108,92 @@ __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
 // cells with key < v* are taken, and among the cells with key == v* the
 // first ones in (r1, r2) order until A is reached.  The result is exactly the
 // prefix Alg. 3 retrieves, computed without a serial walk.
+// Small budgets (one wave, sqrt_k <= 64): Alg. 3's walk itself.  Lane c holds
+// the row of first-half centre c; the second half's centres are sorted only
+// as far as kWalkCols (ascending distance, ties by id), with the sizes of the
+// row's cells in those columns gathered ahead.  Each step takes the smallest
+// frontier key (d1 + d2 of a row's next column; equal keys go to the row of
+// smaller d1, then smaller centre id, which is the rank order), so the cells
+// come in exactly the order the bisection's prefix is defined by, and the walk
+// stops at the cell that brings the count to A.  A row that would need a
+// column past kWalkCols, or a walk longer than kWalkSteps, returns false and
+// the caller takes the general path.
+constexpr int kWalkCols = 8;
+constexpr int kWalkSteps = 64;
+constexpr int kWalkRatio = 16;   // walk when A*K <= kWalkRatio*n (about that many cells of average size)
+
+__device__ __forceinline__ bool activate_walk(const QueryPass &a, const int ql, const int i, const float v0,
+                                              const float v1, const bool live, const uint32_t A) {
+    const int sk = a.ix.sk, K = a.ix.K, ns = a.ix.ns, lane = threadIdx.x;
+    const uint32_t kNone = 0xffffffffu;          // above every finite non-negative float's bits
+    const int ncol = sk < kWalkCols ? sk : kWalkCols;
+    // the second half's first ncol centres in rank order (uniform values)
+    uint32_t b1 = live ? __float_as_uint(v1) : kNone;
+    float D2[kWalkCols];
+    int I2[kWalkCols];
+#pragma unroll
+    for (int j = 0; j < kWalkCols; ++j) {
+        D2[j] = 0.f;
+        I2[j] = 0;
+        if (j < ncol) {
+            const uint32_t m = wave_min(b1);
+            const int r = __ffsll((unsigned long long)__ballot(b1 == m)) - 1;
+            D2[j] = __uint_as_float(m);
+            I2[j] = r;
+            if (lane == r) b1 = kNone;
+        }
+    }
+    // sizes of this row's cells in those columns
+    const uint32_t *cs = a.ix.csize + (int64_t)i * K;
+    uint32_t sz[kWalkCols];
+#pragma unroll
+    for (int j = 0; j < kWalkCols; ++j) sz[j] = cs[(live ? lane * sk : 0) + I2[j]];
+    const uint32_t v0b = live ? __float_as_uint(v0) : kNone;
+    int ptr = 0;
+    uint32_t kb = live ? __float_as_uint(v0 + D2[0]) : kNone;
+    uint32_t cur = live ? sz[0] : 0u;
+    uint32_t W = 0;
+    for (int step = 0;; ++step) {
+        if (step == kWalkSteps) return false;
+        const uint32_t m = wave_min(kb);
+        uint64_t cand = __ballot(kb == m);
+        if (__popcll(cand) > 1) {
+            const uint32_t mv = wave_min(kb == m ? v0b : kNone);
+            cand = __ballot(kb == m && v0b == mv);
+        }
+        const int r = __ffsll((unsigned long long)cand) - 1;
+        W += (uint32_t)__builtin_amdgcn_readlane((int)cur, r);
+        const int np = __builtin_amdgcn_readlane(ptr, r) + 1;
+        if (lane == r) ptr = np;                      // the cell is taken
+        if (W >= A) break;
+        if (np == ncol && ncol < sk) return false;    // its row's next column is not sorted here
+        if (lane == r) {
+            float d2 = D2[0];
+            uint32_t c = sz[0];
+#pragma unroll
+            for (int j = 1; j < kWalkCols; ++j)
+                if (np == j) { d2 = D2[j]; c = sz[j]; }
+            kb = np < ncol ? __float_as_uint(v0 + d2) : kNone;
+            cur = c;
+        }
+    }
+    const uint32_t incl = wave_incl_scan((uint32_t)ptr);
+    const uint32_t off = incl - (uint32_t)ptr;
+    const uint32_t ntot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    const uint32_t d1min = wave_min(v0b);
+    uint16_t *out = a.cells + ((int64_t)ql * ns + i) * K;
+#pragma unroll
+    for (int j = 0; j < kWalkCols; ++j)
+        if (j < ptr) out[off + j] = (uint16_t)(lane * sk + I2[j]);
+    if (a.feat != nullptr && lane < 2)
+        a.feat[(int64_t)ql * 2 * ns + 2 * i + lane] = __fsqrt_rn(lane == 0 ? __uint_as_float(d1min) : D2[0]);
+    if (lane == 0) {
+        a.ncells[ql * ns + i] = (int32_t)ntot;
+        a.aprime[ql * ns + i] = (int32_t)W;
+    }
+    return true;
+}
+
 template <int NT>
 __device__ __forceinline__ void activate_item(const QueryPass &a, const int item) {
     extern __shared__ uint32_t Ptab[];          // [sk][sk+1] row prefix sums of sizes
@@ -151,9 +237,10 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
         return s;
     };
     if constexpr (NT == kWave) {
-        // one wave, sk <= 64: lane c holds centre c of each half in a register;
-        // its rank (ascending distance, ties by centre id) counts the lanes
-        // before it, read one at a time with readlane
+        // one wave, sk <= 64: lane c holds centre c of each half in a register.
+        // A small budget is taken by the walk; otherwise a centre's rank
+        // (ascending distance, ties by centre id) counts the lanes before it,
+        // read one at a time with readlane
         const bool live = tid < sk;
         float v[2] = {0.f, 0.f};
         if (live && a.Dext) {
@@ -192,6 +279,11 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
                     }
             }
         }
+        const double alpha0 = a.alpha_qd ? a.alpha_qd[ql] : (a.alpha_q ? (double)a.alpha_q[ql] : a.alpha);
+        const uint32_t A0 = count_A_dev(alpha0, a.ix.n);
+        if ((uint64_t)A0 * (uint64_t)K <= (uint64_t)kWalkRatio * (uint64_t)a.ix.n &&
+            activate_walk(a, ql, i, v[0], v[1], live, A0))
+            return;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             int r = 0;
