@@ -1092,33 +1092,38 @@ __device__ __forceinline__ void rerank_rows_int(const RerankPass &r, const uint3
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int R = kWave / G, li = lane & (G - 1), slot = lane / G;
     const int d16 = r.d >> 4, k = r.k;
+    const bool full = d16 == G * kIntSlices;   // every lane's slices lie in the row
     for (int base = wv * R * kIntGroups; base < cn; base += (NT / kWave) * R * kIntGroups) {
         uint32_t id[kIntGroups];
         bool valid[kIntGroups];
         uint4 x[kIntGroups][kIntSlices];
+        // the LDS reads and the row loads are all issued before any is waited
+        // for: a slot past the chunk reads an id it does not use, a slice past
+        // the row reads the row's first one and is not counted
 #pragma unroll
         for (int g = 0; g < kIntGroups; ++g) {
             const int rw = base + g * R + slot;
-            id[g] = rw < cn ? cid[rw] : 0u;
+            id[g] = cid[rw < kRowChunk ? rw : kRowChunk - 1];
             valid[g] = rw < cn && id[g] < r.n;   // ids outside [0, n) are ignored
-            id[g] = valid[g] ? id[g] : 0u;
         }
-        // every load is issued (a slice past the row reads the row's first one
-        // and is not used), so none waits for another
 #pragma unroll
-        for (int g = 0; g < kIntGroups; ++g)
+        for (int g = 0; g < kIntGroups; ++g) {
+            id[g] = valid[g] ? id[g] : 0u;
 #pragma unroll
             for (int u = 0; u < kIntSlices; ++u) {
                 const int j = li + G * u;
                 x[g][u] = reinterpret_cast<const uint4 *>(r.X8 + (int64_t)id[g] * r.d)[j < d16 ? j : 0];
             }
+        }
         uint64_t key[kIntGroups];
 #pragma unroll
         for (int g = 0; g < kIntGroups; ++g) {
             uint32_t s = qq;
 #pragma unroll
-            for (int u = 0; u < kIntSlices; ++u)
-                if (li + G * u < d16) s += dot16(x[g][u], x[g][u], 0u) - 2u * dot16(x[g][u], qb[u], 0u);
+            for (int u = 0; u < kIntSlices; ++u) {
+                const uint32_t t = dot16(x[g][u], x[g][u], 0u) - 2u * dot16(x[g][u], qb[u], 0u);
+                s += (full || li + G * u < d16) ? t : 0u;
+            }
             s = group_sum(s, G);
             key[g] = valid[g] ? (((uint64_t)__float_as_uint((float)s) << 32) | id[g]) : ~0ull;
         }
