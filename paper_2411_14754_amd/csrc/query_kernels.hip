@@ -542,28 +542,38 @@ __device__ __forceinline__ uint32_t collide_fetch(const QueryPass &a, const Coll
     return vm;
 }
 
-// +1 on the scores of the fetched ids; words touched for the first time are listed.
+// +1 on the scores of the fetched ids; words touched for the first time are
+// listed.  All slots' atomics are issued before any result is used, and the
+// first touches of all slots are appended with one atomic per wave.
 template <int NT>
 __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, const uint32_t (&lid)[kCollideUnroll],
                                               const uint32_t vm, const int b) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
+    uint32_t old[kCollideUnroll];
 #pragma unroll
     for (int u = 0; u < kCollideUnroll; ++u) {
-        const bool v = (vm >> u) & 1u;
-        uint32_t old = 1u;
-        if (v) old = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
-        const bool first = v && old == 0u;
-        const uint64_t m = __ballot(first);
-        if (m != 0ull) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0u;
-            if (lane == leader) base = atomicAdd(&L.n_touched[b], (uint32_t)__popcll(m));
-            base = __shfl(base, leader, kWave);
-            if (first) {
-                const uint32_t pos = base + (uint32_t)__popcll(m & lanes_below);
+        old[u] = 1u;
+        if ((vm >> u) & 1u) old[u] = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
+    }
+    uint64_t m[kCollideUnroll];
+    uint32_t nfirst = 0u;
+#pragma unroll
+    for (int u = 0; u < kCollideUnroll; ++u) {
+        m[u] = __ballot(old[u] == 0u);
+        nfirst += (uint32_t)__popcll(m[u]);
+    }
+    if (nfirst != 0u) {
+        uint32_t base = 0u;
+        if (lane == 0) base = atomicAdd(&L.n_touched[b], nfirst);
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
+#pragma unroll
+        for (int u = 0; u < kCollideUnroll; ++u) {
+            if (old[u] == 0u) {
+                const uint32_t pos = base + (uint32_t)__popcll(m[u] & lanes_below);
                 if (pos < (uint32_t)kTouchCap) L.touched[pos] = (uint16_t)(lid[u] >> 2);
             }
+            base += (uint32_t)__popcll(m[u]);
         }
     }
 }
