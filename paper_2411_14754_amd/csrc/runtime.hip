@@ -62,8 +62,11 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->TILE = (int)((per + 255) / 256 * 256);
     ix->P = (int)((n + ix->TILE - 1) / ix->TILE);
     const int64_t span = (int64_t)ix->P * ix->TILE;
+    // Queries per pass: the level lists take 2 bytes per point and query, and
+    // passes as large as that allows (up to 16 GiB of lists, 16384 queries)
+    // cost less per query than small ones (fewer launches, fuller grids).
     if (p && p->query_chunk > 0) ix->chunk = p->query_chunk;
-    else ix->chunk = (int)std::clamp<int64_t>((int64_t(1) << 31) / (2 * span), 16, 1024);
+    else ix->chunk = (int)std::clamp<int64_t>((int64_t(1) << 34) / (2 * span), 16, 16384);
     ix->halves_h = make_layout(d, ns);
     if ((rc = dev_alloc(&ix->X, (size_t)n * d)) || (rc = dev_alloc(&ix->cent, (size_t)sk * d)) ||
         (rc = dev_alloc(&ix->halves, (size_t)2 * ns)) ||
@@ -296,7 +299,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
     const int parts = std::max(c32.parts, c16.parts);
     std::lock_guard<std::mutex> lock(ix->mu);
     DeviceGuard dg(ix->device);
-    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    const size_t C = (size_t)pass_size(nq, ix->chunk);
     const int nh = 2 * ix->ns;
     const bool dense = dbg && dbg->scores;
     // BF16 buffers follow the common workspace
@@ -555,7 +558,7 @@ int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells
     const int64_t B = count_B_host(beta, ix->n, k);
     std::lock_guard<std::mutex> lock(ix->mu);
     DeviceGuard dg(ix->device);
-    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    const size_t C = (size_t)pass_size(nq, ix->chunk);
     size_t bytes = 0;
     carve(ix, nullptr, C, B, k, 1, scores != nullptr, &bytes);
     int rc = ensure_arena(ix, bytes);
@@ -599,7 +602,7 @@ int suco_rerank(const suco_index *cix, const float *Q, int64_t nq, const int32_t
     if ((rc = rerank_cfg(ix->d, B, &c))) return rc;
     std::lock_guard<std::mutex> lock(ix->mu);
     DeviceGuard dg(ix->device);
-    const size_t C = (size_t)std::min<int64_t>(nq, ix->chunk);
+    const size_t C = (size_t)pass_size(nq, ix->chunk);
     size_t bytes = 0;
     carve(ix, nullptr, C, B, k, c.parts, false, &bytes);
     if ((rc = ensure_arena(ix, bytes))) return rc;

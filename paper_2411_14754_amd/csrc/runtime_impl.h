@@ -199,6 +199,13 @@ inline int tile_groups(int64_t nq, int P) {
     return (int)std::clamp<int64_t>(s, 1, P);
 }
 
+// Queries per pass: nq split into as few passes of at most `chunk` as
+// possible, all of the same size but the last.
+inline int64_t pass_size(int64_t nq, int chunk) {
+    const int64_t passes = (nq + chunk - 1) / chunk;
+    return (nq + passes - 1) / passes;
+}
+
 struct RerankCfg { int G, U, parts; int64_t rpp; };
 
 // BF16 first pass: G lanes per row, U slices of 8 values per lane.
