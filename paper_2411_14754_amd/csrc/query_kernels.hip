@@ -467,6 +467,14 @@ constexpr int kCollideUnroll = 4;
 constexpr int kTouchCap = 4096;
 constexpr int kBucketShift = 6;     // run lookup table: one entry per 64 consecutive id positions
 constexpr int kBuckets = 1024;      // positions beyond kBuckets << kBucketShift use a binary search
+// Levels 1..kPruneLevels-1 may be left out of a tile's lists: a tile need not
+// list its ids of score s when the block's earlier tiles of the query (lower
+// ids) already hold at least B ids of score >= s.  Then either the threshold
+// T exceeds s, or T == s and those earlier tiles hold at least
+// B - (their own #{score > s}) >= B - #{score > T} = R ids of level s; the
+// selection takes the R lowest level-T ids, all of which lie there, and none
+// of this tile's.  The tile's histogram still counts every point.
+constexpr int kPruneLevels = 32;
 
 template <int NT>
 struct CollideLds {
@@ -481,6 +489,7 @@ struct CollideLds {
     uint16_t first[kBuckets];    // run holding position b << kBucketShift
     uint16_t touched[kTouchCap];
     uint32_t n_touched[2];
+    uint32_t Gc[kPruneLevels];   // #{score >= s} over the block's earlier tiles of its query
 };
 
 struct RunBatch {
@@ -596,6 +605,11 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     const bool sparse = nt <= (uint32_t)kTouchCap;
     const bool early = sparse && a.scores == nullptr;
     const int nw = sparse ? (int)nt : words;
+    // levels 1..s0 are not listed (see kPruneLevels); Gc was last written by
+    // the previous tile's finish, before the barrier that ended this counting
+    uint32_t s0 = 0;
+    for (int sl = (ns < kPruneLevels - 1 ? ns : kPruneLevels - 1); sl >= 1; --sl)
+        if (L.Gc[sl] >= (uint32_t)a.B) { s0 = (uint32_t)sl; break; }
     // Counts of bytes >= t, two thresholds per 32-bit counter (16-bit halves:
     // a thread sees at most 4 * 32 bytes, a wave at most 64 times that).  In
     // the listed-words case a thread has at most kTouchCap / NT words; they are
@@ -659,7 +673,7 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t sv = (x >> (8 * u)) & 0xffu;
-            if (sv != 0u) seg[L.G[b][sv + 1] + atomicAdd(&L.cur[b][sv], 1u)] = (uint16_t)(4 * w + u);
+            if (sv > s0) seg[L.G[b][sv + 1] + atomicAdd(&L.cur[b][sv], 1u)] = (uint16_t)(4 * w + u);
         }
     };
     if (sparse) {
@@ -681,6 +695,8 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
     const int64_t valid = a.ix.n - t0 < TILE ? a.ix.n - t0 : TILE;
     uint32_t *h = a.hist + ((int64_t)ql * P + p) * (ns + 2);
     for (int t = tid; t < ns + 2; t += NT) h[t] = t == 0 ? (uint32_t)valid : L.G[b][t];
+    // every wave read Gc above, before the barrier after the histogram
+    for (int t = 1 + tid; t < kPruneLevels && t <= ns; t += NT) L.Gc[t] += L.G[b][t];
     if (early) return;
     __syncthreads();
     if (sparse) {
@@ -803,7 +819,11 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
         // this thread's subspace: activated cell count and its cell of the first batch
         const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
         const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
-        if (__syncthreads_or(my_nc > RJ)) {
+        const bool batched = __syncthreads_or(my_nc > RJ);
+        // a new query: no earlier tiles (read after the next barrier, the one
+        // that ends the counting of its first tile)
+        for (int t = threadIdx.x; t < kPruneLevels; t += NT) L.Gc[t] = 0u;
+        if (batched) {
             for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first, b);
         } else {
             collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first, b);
