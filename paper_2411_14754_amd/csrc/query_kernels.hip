@@ -475,6 +475,15 @@ constexpr int kBuckets = 1024;      // positions beyond kBuckets << kBucketShift
 // selection takes the R lowest level-T ids, all of which lie there, and none
 // of this tile's.  The tile's histogram still counts every point.
 constexpr int kPruneLevels = 32;
+// With N_s <= kIncLevels the tile histogram is gathered while counting: the
+// atomic add returns the byte's old value o, and that increment is exactly
+// one of the #{score >= o+1} points, so G[t] = #{increments with o = t-1}.  A
+// thread keeps 8-bit counts per level in two 64-bit registers; they cannot
+// overflow while a tile gives a thread at most 255 increments (a batch of
+// runs with m ids gives a thread at most ceil(m / NT)); tiles with more are
+// tallied from their words instead.
+constexpr int kIncLevels = 16;
+constexpr uint32_t kIncMax = 255;
 
 template <int NT>
 struct CollideLds {
@@ -553,10 +562,11 @@ __device__ __forceinline__ uint32_t collide_fetch(const QueryPass &a, const Coll
 
 // +1 on the scores of the fetched ids; words touched for the first time are
 // listed.  All slots' atomics are issued before any result is used, and the
-// first touches of all slots are appended with one atomic per wave.
+// first touches of all slots are appended with one atomic per wave.  With
+// `inc`, each increment is also counted at its level in hc (see kIncLevels).
 template <int NT>
 __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, const uint32_t (&lid)[kCollideUnroll],
-                                              const uint32_t vm, const int b) {
+                                              const uint32_t vm, const int b, const bool inc, uint64_t (&hc)[2]) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
     uint32_t old[kCollideUnroll];
@@ -564,6 +574,15 @@ __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, c
     for (int u = 0; u < kCollideUnroll; ++u) {
         old[u] = 1u;
         if ((vm >> u) & 1u) old[u] = atomicAdd(&sc[lid[u] >> 2], 1u << ((lid[u] & 3u) << 3));
+    }
+    if (inc) {
+#pragma unroll
+        for (int u = 0; u < kCollideUnroll; ++u) {
+            if (((vm >> u) & 1u) == 0u) continue;
+            const uint32_t o = (old[u] >> ((lid[u] & 3u) << 3)) & 0xffu;   // < N_s <= kIncLevels
+            const uint64_t one = 1ull << ((o & 7u) << 3);
+            if (o < 8u) hc[0] += one; else hc[1] += one;
+        }
     }
     uint64_t m[kCollideUnroll];
     uint32_t nfirst = 0u;
@@ -596,7 +615,7 @@ __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, c
 // reads); otherwise it ends with one after clearing the scores.
 template <int NT>
 __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
-                                               const int p, const int b) {
+                                               const int p, const int b, const bool inc, uint64_t (&hc)[2]) {
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int words = TILE >> 2;
@@ -635,7 +654,22 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
         L.cur[b ^ 1][t] = 0u;
     }
     if (tid == 0) L.n_touched[b ^ 1] = 0u;
-    for (int t0 = 1; t0 <= ns; t0 += 8) {
+    if (inc) {
+        // two levels per wave sum, in 16-bit halves (a wave counts at most
+        // 64 * 255 increments per level)
+#pragma unroll
+        for (int t0 = 1; t0 <= kIncLevels; t0 += 2) {
+            if (t0 > ns) break;
+            const uint32_t fa = (uint32_t)(hc[(t0 - 1) >> 3] >> (((t0 - 1) & 7) * 8)) & 0xffu;
+            const uint32_t fb = (uint32_t)(hc[t0 >> 3] >> ((t0 & 7) * 8)) & 0xffu;
+            const uint32_t sum = wave_sum(fa | (t0 + 1 <= ns ? fb << 16 : 0u));
+            if (lane == 0) {
+                atomicAdd(&L.G[b][t0], sum & 0xffffu);
+                if (t0 + 1 <= ns) atomicAdd(&L.G[b][t0 + 1], sum >> 16);
+            }
+        }
+    }
+    for (int t0 = 1; !inc && t0 <= ns; t0 += 8) {
         uint32_t c[4] = {0, 0, 0, 0};
         auto tally = [&](uint32_t x) {
 #pragma unroll
@@ -721,6 +755,9 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
     const bool has_i = i < ns;
     const uint16_t *my_cells = a.cells + ((int64_t)ql * ns + (has_i ? i : 0)) * K;
     const uint32_t *to = a.ix.toffs + ((int64_t)(has_i ? i : 0) * P + p) * (K + 1);
+    const bool levels = ns <= kIncLevels;
+    uint64_t hc[2] = {0ull, 0ull};
+    uint32_t per_thread = 0;                                // ids per thread in this tile, at most (capped)
     for (int jb = 0; __syncthreads_or(jb < my_nc); jb += RJ) {
         const int j = jb + jj;
         uint32_t len = 0;
@@ -732,14 +769,16 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
             st = (int64_t)i * P * TILE + s;
         }
         const RunBatch rb = collide_runs<NT>(L, len, st);
+        const uint32_t per = (rb.tot + NT - 1) / NT;       // this batch's ids per thread, at most
+        per_thread = per <= kIncMax - per_thread ? per_thread + per : kIncMax + 1;
         for (uint32_t e0 = 0; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid[kCollideUnroll];
             const uint32_t vm = collide_fetch<NT>(a, L, e0, rb, lid);
-            collide_count<NT>(L, sc, lid, vm, b);
+            collide_count<NT>(L, sc, lid, vm, b, levels, hc);
         }
         __syncthreads();
     }
-    collide_finish<NT>(a, L, sc, ql, p, b);
+    collide_finish<NT>(a, L, sc, ql, p, b, levels && per_thread <= kIncMax, hc);
     b ^= 1;
 }
 
@@ -770,12 +809,15 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
         rs = tob[(int64_t)pn * (K + 1)];
         re = tob[(int64_t)pn * (K + 1) + 1];
     }
+    const bool levels = ns <= kIncLevels;
     for (int p = g; p < P; p += S) {
-        collide_count<NT>(L, sc, lid, vm, b);
+        uint64_t hc[2] = {0ull, 0ull};
+        const bool inc = levels && (rb.tot + NT - 1) / NT <= kIncMax;
+        collide_count<NT>(L, sc, lid, vm, b, inc, hc);
         for (uint32_t e0 = NT * kCollideUnroll; e0 < rb.tot; e0 += NT * kCollideUnroll) {
             uint32_t lid2[kCollideUnroll];
             const uint32_t vm2 = collide_fetch<NT>(a, L, e0, rb, lid2);
-            collide_count<NT>(L, sc, lid2, vm2, b);
+            collide_count<NT>(L, sc, lid2, vm2, b, inc, hc);
         }
         __syncthreads();
         // stage the next tile of the group (an empty one after the last) and
@@ -787,7 +829,7 @@ __device__ __forceinline__ void collide_tiles_pipelined(const QueryPass &a, Coll
         const int pn = p + 2 * S < P ? p + 2 * S : p;
         rs = tob[(int64_t)pn * (K + 1)];
         re = tob[(int64_t)pn * (K + 1) + 1];
-        collide_finish<NT>(a, L, sc, ql, p, b);
+        collide_finish<NT>(a, L, sc, ql, p, b, inc, hc);
         b ^= 1;
     }
 }

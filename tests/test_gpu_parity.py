@@ -229,6 +229,34 @@ def test_deterministic_repeat(suco):
     gix.free()
 
 
+def test_tie_level_left_out_of_later_tiles(suco):
+    """Many tiles and a tie at level 1 (fewer than B points score 2 or more):
+    the collision step leaves the level-1 ids of later tiles out of its lists
+    once the block's earlier tiles hold B of them.  2,048 queries in one pass
+    take one block per query (every tile seen in order); a sample of 24 takes
+    several blocks per query.  Both give the oracle's candidates."""
+    W = synth.Workload(2)
+    X, Q = W.data(200_000), W.queries(2048)
+    _, c32, asg, _ = oracle.build_index(X, 8, 50, iters=4, seed=1)
+    oix = oracle.Index(X, 8, 50, c32, asg)
+    gix = suco.Index.from_index(torch.from_numpy(X).cuda(), 8, 50, c32, asg, tile_max=4096)
+    alpha, beta = 0.003, 0.005
+    o = gix.query_debug(torch.from_numpy(Q).cuda(), 10, alpha, beta, scores=False, cells=False)
+    torch.cuda.synchronize()
+    full = to_np(o)
+    del o
+    sample = np.sort(np.random.default_rng(1).choice(Q.shape[0], 24, replace=False))
+    gs = debug(gix, Q[sample], 10, alpha, beta)
+    for key in ("ids", "dists", "cand"):
+        assert np.array_equal(full[key][sample], gs[key]), key
+    B = oracle.count_B(beta, X.shape[0], 10)
+    ge2 = (gs["scores"] >= 2).sum(axis=1)
+    assert (ge2 < B).all()                                  # the threshold is 1 for the sample
+    st = check_query(oix, X, Q[sample], 10, alpha, beta, gs)
+    assert st["band_queries"] <= 3
+    gix.free()
+
+
 # ----------------------------------------------------------- full size --
 def test_sift_like_full_size_sampled(suco):
     """SIFT-like n=1,000,000 d=128, N_s=8, sqrtK=50, 10,000 queries in one call
