@@ -1048,11 +1048,11 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
     uint32_t *sumA = sum + wv * 128, *sumT = sumA + 64;
     const uint32_t B = (uint32_t)a.B;
     const uint32_t *hq = a.hist + (int64_t)ql * P * H;
-    for (int t = tid; t < H; t += NT) {
-        uint32_t s = 0;
-        for (int pp = 0; pp < P; ++pp) s += hq[pp * H + t];
-        Gt[t] = s;
-    }
+    // Gt[t] = sum over the tiles of G_p[t]: the P*H histogram words are read
+    // by all threads at once (contiguous) and added up in LDS
+    for (int t = tid; t < H; t += NT) Gt[t] = 0u;
+    __syncthreads();
+    for (int j = tid; j < P * H; j += NT) atomicAdd(&Gt[j % H], hq[j]);
     __syncthreads();
     int T = 0;
     for (int t = ns; t >= 0; --t)
