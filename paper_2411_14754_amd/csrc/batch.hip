@@ -239,7 +239,7 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         qp.nq_dev = b->nq_dev;
         qp.q_base = c * b->C;
         qp.cells = b->cells; qp.ncells = b->ncells; qp.aprime = b->aprime; qp.hist = b->hist; qp.lvl = b->lvl;
-        if (C <= kOrderMax) { qp.order_out = b->order; qp.order = b->order; }
+        if (C <= kOrderWide) { qp.order_out = b->order; qp.order = b->order; }
         qp.cand = b->cand;
         RerankPass &rp = bk->rps[c];
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = b->cand; rp.B = b->B; rp.n = ix->n; rp.d = ix->d; rp.k = b->k;

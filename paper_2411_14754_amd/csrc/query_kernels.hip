@@ -465,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
 // words are touched the passes scan the whole tile instead.
 constexpr int kCollideUnroll = 4;
 constexpr int kTouchCap = 4096;
-constexpr int kBucketShift = 6;     // run lookup table: one entry per 64 consecutive id positions
+constexpr int kBucketShift = 5;     // run lookup table: one entry per 32 consecutive id positions
 constexpr int kBuckets = 1024;      // positions beyond kBuckets << kBucketShift use a binary search
 // Levels 1..kPruneLevels-1 may be left out of a tile's lists: a tile need not
 // list its ids of score s when the block's earlier tiles of the query (lower
@@ -508,7 +508,7 @@ struct RunBatch {
 
 // Scan one run per thread (length len at ids16 offset st) into the block's run
 // table: the non-empty runs are compacted in slot order, and a table gives for
-// every 64th position the run that holds it.  Ends with a barrier.
+// every 32nd position the run that holds it.  Ends with a barrier.
 template <int NT>
 __device__ __forceinline__ RunBatch collide_runs(CollideLds<NT> &L, uint32_t len, int64_t st) {
     uint32_t ex, idx, tot, nr;
@@ -527,7 +527,7 @@ __device__ __forceinline__ RunBatch collide_runs(CollideLds<NT> &L, uint32_t len
 
 // Issue the loads of ids e0 + u*NT + tid (u < kCollideUnroll) of the run table;
 // bit u of the result says whether slot u holds an id.  An id's run is the
-// table's run for its 64-position bucket or one of the next few (runs are at
+// table's run for its 32-position bucket or one of the next few (runs are at
 // least one id long); past the table a binary search finds it.  The loads are
 // unconditional (an empty slot reads entry 0) so that no later instruction has
 // to wait for them before they are used.
@@ -900,6 +900,36 @@ __global__ __launch_bounds__(kOrderMax) void k_order(QueryPass a) {
         }
     }
     if (t < nq) a.order_out[t] = (int32_t)(key[t] & 0xfffffull);
+}
+
+// Wider passes (up to kOrderWide queries): the queries bucketed by
+// floor(log2(activated points)), heaviest bucket first; inside a bucket the
+// order is whatever the atomics give, which only decides which block takes
+// which query first (every query's results are its own).
+__global__ __launch_bounds__(1024) void k_order_wide(QueryPass a) {
+    __shared__ uint32_t cnt[32];
+    __shared__ uint8_t key[kOrderWide];
+    const int nq = pass_nq(a.nq_dev, a.q_base, a.nq), ns = a.ix.ns;
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += 1024) {
+        uint32_t w = 0;
+        for (int i = 0; i < ns; ++i) w += (uint32_t)a.aprime[q * ns + i];
+        const uint32_t kq = (uint32_t)__clz(w | 1u);      // 31 - floor(log2 w): heavier first
+        key[q] = (uint8_t)kq;
+        atomicAdd(&cnt[kq], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int j = 0; j < 32; ++j) {
+            const uint32_t c = cnt[j];
+            cnt[j] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += 1024) a.order_out[atomicAdd(&cnt[key[q]], 1u)] = q;
 }
 
 // ================================================================ select ==
@@ -1459,9 +1489,10 @@ Launch plan_collide(const QueryPass &p, int cap) {
 
 Launch plan_order(const QueryPass &p) {
     Launch L;
-    L.func = reinterpret_cast<const void *>(&k_order);
+    L.func = p.nq <= kOrderMax ? reinterpret_cast<const void *>(&k_order)
+                               : reinterpret_cast<const void *>(&k_order_wide);
     L.grid = dim3(1);
-    L.block = dim3(kOrderMax);
+    L.block = dim3(1024);
     return L;
 }
 

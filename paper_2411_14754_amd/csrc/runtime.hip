@@ -349,7 +349,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
                                         hipMemcpyDeviceToDevice, st));
         }
         HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
-        if (cn <= kOrderMax) {
+        if (cn <= kOrderWide) {
             qp.order_out = w.order;
             HIPCHECK(timed(ix, kOrder, st, [&] { return launch(plan_order(qp), &qp, st); }));
             qp.order = w.order;

@@ -93,6 +93,7 @@ constexpr int kActivateGrid = 8192;
 Launch plan_activate(const QueryPass &p, int cap);
 Launch plan_collide(const QueryPass &p, int cap);
 constexpr int kOrderMax = 1024;   // largest pass the ordering kernel sorts
+constexpr int kOrderWide = 16384; // largest pass the bucketed ordering kernel takes
 Launch plan_order(const QueryPass &p);
 Launch plan_select(const QueryPass &p, int cap);
 Launch plan_rerank(const RerankPass &r, int cap);
