@@ -938,25 +938,24 @@ __global__ __launch_bounds__(1024) void k_order_wide(QueryPass a) {
 // the R = B - #{score > T} lowest ids.  Tiles contribute in id order: each
 // takes gt (its ids above T) plus take (its share of the level-T ids) at an
 // offset known from the histograms, so the tiles are independent and each
-// wave of the block takes its own tiles with its own LDS bitmaps (no block
-// barrier inside a tile).  A tile's chosen ids are marked in a bitmap (score
-// > T from the front of the tile's list; level-T ids in a second bitmap when
-// only some are taken) with a summary bitmap of non-zero words, and the wave
-// walks the summaries in id order: the work per tile follows the number of
-// candidates, not the tile size, and the bitmaps are cleared through their
-// summaries.  When T == 0 the points of score 0 are the ones missing from the
-// tile's list; such a tile is handled densely.
+// wave of the block takes its own tiles with its own LDS bitmap (no block
+// barrier inside a tile).  A tile's chosen ids are marked in the bitmap (score
+// > T from the front of the tile's list, level-T ids up to a cut) with a
+// summary bitmap of non-zero words, and the wave walks the summaries in id
+// order: the work per tile follows the number of candidates, not the tile
+// size, and the bitmap is cleared through its summary.  When only some of the
+// tile's level-T ids are taken, they are first marked alone to find the cut
+// (the id of the take-th lowest).  When T == 0 the points of score 0 are the
+// ones missing from the tile's list; such a tile is handled densely.
 struct SelectTile {
     int p;
     uint32_t gt, E, take, base;
 };
 
-// One wave: the candidates of tile t.p in id order at out + t.base.  bmA, bmT
-// (TILE bits each) and sumA, sumT (64 words each) are the wave's own and are
-// left zero.
+// One wave: the candidates of tile t.p in id order at out + t.base.  bm
+// (TILE bits) and sm (64 words) are the wave's own and are left zero.
 __device__ __forceinline__ void select_tile(const QueryPass &a, const int ql, const int T, const SelectTile t,
-                                            uint32_t *bmA, uint32_t *bmT, uint32_t *sumA, uint32_t *sumT,
-                                            uint32_t *out) {
+                                            uint32_t *bm, uint32_t *sm, uint32_t *out) {
     const int P = a.ix.P, TILE = a.ix.TILE;
     const int lane = threadIdx.x & (kWave - 1);
     const int bwords = TILE >> 5, swords = (bwords + 31) >> 5;   // swords <= 64
@@ -965,105 +964,110 @@ __device__ __forceinline__ void select_tile(const QueryPass &a, const int ql, co
     const int64_t vv = a.ix.n - (int64_t)id0;
     const int valid = (int)(vv < TILE ? vv : TILE);
     const bool partial = t.take > 0u && (t.take < t.E || T == 0);
+    auto mark = [&](uint32_t lid) {
+        atomicOr(&bm[lid >> 5], 1u << (lid & 31u));
+        atomicOr(&sm[lid >> 10], 1u << ((lid >> 5) & 31u));
+    };
     if (T == 0 && partial) {
         // fewer than B points collide: the tile's score-0 ids are taken too,
-        // lowest first; dense bitmaps, a range of words per lane
+        // lowest first; dense bitmap, a range of words per lane
         const int per = (bwords + kWave - 1) / kWave;
         const int w0 = lane * per < bwords ? lane * per : bwords;
         const int w1 = w0 + per < bwords ? w0 + per : bwords;
         for (uint32_t j = lane; j < t.gt; j += kWave) {
             const uint32_t lid = seg[j];
-            atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
+            atomicOr(&bm[lid >> 5], 1u << (lid & 31u));
         }
         __builtin_amdgcn_wave_barrier();
-        uint32_t cnt = 0;
-        for (int w = w0; w < w1; ++w) {
+        auto zeros = [&](int w) {   // this word's score-0 ids inside the tile
             const uint32_t m = (w + 1) * 32 <= valid ? ~0u : (w * 32 >= valid ? 0u : (1u << (valid - w * 32)) - 1u);
-            const uint32_t x = ~bmA[w] & m;
-            bmT[w] = x;
-            cnt += __popc(x);
-        }
+            return ~bm[w] & m;
+        };
+        uint32_t cnt = 0;
+        for (int w = w0; w < w1; ++w) cnt += __popc(zeros(w));
         uint32_t r = wave_incl_scan(cnt) - cnt;
         for (int w = w0; w < w1; ++w) {
-            uint32_t x = bmT[w], keep = 0u;
+            uint32_t x = zeros(w), keep = 0u;
             while (x != 0u && r < t.take) {
                 const uint32_t bit = x & (0u - x);
                 keep |= bit;
                 x ^= bit;
                 ++r;
             }
-            bmA[w] |= keep;
-            bmT[w] = 0u;
+            bm[w] |= keep;
         }
         cnt = 0;
-        for (int w = w0; w < w1; ++w) cnt += __popc(bmA[w]);
+        for (int w = w0; w < w1; ++w) cnt += __popc(bm[w]);
         uint32_t pos = t.base + wave_incl_scan(cnt) - cnt;
         for (int w = w0; w < w1; ++w) {
-            uint32_t x = bmA[w];
+            uint32_t x = bm[w];
             while (x != 0u) {
                 const int bq = __ffs(x) - 1;
                 out[pos++] = id0 + (uint32_t)(w * 32 + bq);
                 x &= x - 1u;
             }
-            bmA[w] = 0u;
+            bm[w] = 0u;
         }
         __builtin_amdgcn_wave_barrier();
         return;
     }
-    // sparse tile: mark, optionally keep the lowest level-T ids, extract
-    const uint32_t hiA = partial ? t.gt : t.gt + t.take;
-    for (uint32_t j = lane; j < hiA; j += kWave) {
-        const uint32_t lid = seg[j];
-        atomicOr(&bmA[lid >> 5], 1u << (lid & 31u));
-        atomicOr(&sumA[lid >> 10], 1u << ((lid >> 5) & 31u));
-    }
+    // sparse tile.  Some of the level-T ids: mark them all, find the id of
+    // the take-th lowest (cut) by walking the summaries in id order, clear.
+    uint32_t cut = 0xffffffffu;
     if (partial) {
-        for (uint32_t j = t.gt + lane; j < t.gt + t.E; j += kWave) {
-            const uint32_t lid = seg[j];
-            atomicOr(&bmT[lid >> 5], 1u << (lid & 31u));
-            atomicOr(&sumT[lid >> 10], 1u << ((lid >> 5) & 31u));
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (partial) {
-        // lane l owns summary word l: its level-T ids in id order
-        const uint32_t sl = lane < swords ? sumT[lane] : 0u;
+        for (uint32_t j = t.gt + lane; j < t.gt + t.E; j += kWave) mark(seg[j]);
+        __builtin_amdgcn_wave_barrier();
+        // lane l owns summary word l
+        const uint32_t sl = lane < swords ? sm[lane] : 0u;
         uint32_t c = 0;
-        for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bmT[lane * 32 + __ffs(x) - 1]);
+        for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bm[lane * 32 + __ffs(x) - 1]);
         uint32_t r = wave_incl_scan(c) - c;               // level-T ids before this lane's words
+        uint32_t mine = 0u;                               // cut + 1 in the lane that holds it
         for (uint32_t x = sl; x != 0u; x &= x - 1u) {
             const int w = lane * 32 + __ffs(x) - 1;
-            uint32_t y = bmT[w], keep = 0u;
-            while (y != 0u && r < t.take) {
-                const uint32_t bit = y & (0u - y);
-                keep |= bit;
-                y ^= bit;
-                ++r;
+            const uint32_t y = bm[w];
+            bm[w] = 0u;
+            const uint32_t cy = (uint32_t)__popc(y);
+            if (r < t.take && r + cy >= t.take) {
+                // the cut lies in this word: its (take - r)-th set bit
+                uint32_t z = y;
+                for (uint32_t k2 = t.take - r; k2 > 1u; --k2) z &= z - 1u;
+                mine = 1u + (uint32_t)(w * 32 + __ffs(z) - 1);
             }
-            bmT[w] = 0u;
-            if (keep != 0u) {
-                bmA[w] |= keep;
-                sumA[lane] |= 1u << (w & 31);
-            }
+            r += cy;
         }
-        if (lane < swords) sumT[lane] = 0u;
+        if (lane < swords) sm[lane] = 0u;
+        // exactly one lane found it (0 < take < E, and the tile lists its E
+        // level-T ids whenever it takes some of them)
+        const uint64_t who = __ballot(mine != 0u);
+        if (who != 0ull) cut = (uint32_t)__builtin_amdgcn_readlane((int)mine, __ffsll((unsigned long long)who) - 1) - 1u;
+        __builtin_amdgcn_wave_barrier();
     }
+    // mark the candidates: ids above T, and the level-T ids up to the cut
+    const uint32_t hiA = partial ? t.gt : t.gt + t.take;
+    for (uint32_t j = lane; j < hiA; j += kWave) mark(seg[j]);
+    if (partial)
+        for (uint32_t j = t.gt + lane; j < t.gt + t.E; j += kWave) {
+            const uint32_t lid = seg[j];
+            if (lid <= cut) mark(lid);
+        }
+    __builtin_amdgcn_wave_barrier();
     // candidates in id order: lane l writes the ids of its summary word
-    const uint32_t sl = lane < swords ? sumA[lane] : 0u;
+    const uint32_t sl = lane < swords ? sm[lane] : 0u;
     uint32_t c = 0;
-    for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bmA[lane * 32 + __ffs(x) - 1]);
+    for (uint32_t x = sl; x != 0u; x &= x - 1u) c += __popc(bm[lane * 32 + __ffs(x) - 1]);
     uint32_t pos = t.base + wave_incl_scan(c) - c;
     for (uint32_t x = sl; x != 0u; x &= x - 1u) {
         const int w = lane * 32 + __ffs(x) - 1;
-        uint32_t y = bmA[w];
-        bmA[w] = 0u;
+        uint32_t y = bm[w];
+        bm[w] = 0u;
         while (y != 0u) {
             const int bq = __ffs(y) - 1;
             out[pos++] = id0 + (uint32_t)(w * 32 + bq);
             y &= y - 1u;
         }
     }
-    if (lane < swords) sumA[lane] = 0u;
+    if (lane < swords) sm[lane] = 0u;
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -1074,8 +1078,7 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE, H = ns + 2;
     const int tid = threadIdx.x, wv = tid / kWave;
     const int bwords = TILE >> 5;
-    uint32_t *bmA = bm + (int64_t)wv * 2 * bwords, *bmT = bmA + bwords;
-    uint32_t *sumA = sum + wv * 128, *sumT = sumA + 64;
+    uint32_t *bmw = bm + (int64_t)wv * bwords, *smw = sum + wv * 64;
     const uint32_t B = (uint32_t)a.B;
     const uint32_t *hq = a.hist + (int64_t)ql * P * H;
     // Gt[t] = sum over the tiles of G_p[t]: the P*H histogram words are read
@@ -1121,7 +1124,7 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
         for (int pi = wv; pi < np; pi += NT / kWave) {
             const SelectTile t{p0 + pi, pl_gt[pi], pl_E[pi], pl_take[pi], pl_base[pi]};
             if (t.gt + t.take == 0u) continue;
-            select_tile(a, ql, T, t, bmA, bmT, sumA, sumT, out);
+            select_tile(a, ql, T, t, bmw, smw, out);
         }
         __syncthreads();
     }
@@ -1129,12 +1132,12 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
-    extern __shared__ uint32_t bm[];       // per wave: two bitmaps of TILE bits
-    __shared__ uint32_t sum[(NT / kWave) * 128];   // per wave: their summaries (bit w of word s = bitmap word 32s + w non-zero)
+    extern __shared__ uint32_t bm[];       // per wave: a bitmap of TILE bits
+    __shared__ uint32_t sum[(NT / kWave) * 64];    // per wave: its summary (bit w of word s = bitmap word 32s + w non-zero)
     const int items = pass_nq(a.nq_dev, a.q_base, a.nq);
     if ((int)blockIdx.x >= items) return;
-    for (int w = threadIdx.x; w < (NT / kWave) * 2 * (a.ix.TILE >> 5); w += NT) bm[w] = 0u;
-    for (int w = threadIdx.x; w < (NT / kWave) * 128; w += NT) sum[w] = 0u;
+    for (int w = threadIdx.x; w < (NT / kWave) * (a.ix.TILE >> 5); w += NT) bm[w] = 0u;
+    for (int w = threadIdx.x; w < (NT / kWave) * 64; w += NT) sum[w] = 0u;
     __syncthreads();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         select_item<NT>(a, item, bm, sum);
@@ -1497,12 +1500,12 @@ Launch plan_order(const QueryPass &p) {
 }
 
 // Two waves per selection block: more blocks fit a CU than with four (each
-// wave brings TILE/4 bytes of bitmaps), and that measured faster.
+// wave brings TILE/8 bytes of bitmap), and that measured faster.
 constexpr int kSelectThreads = 128;
 
 Launch plan_select(const QueryPass &p, int cap) {
     Launch L;
-    L.lds = (size_t)(kSelectThreads / kWave) * (p.ix.TILE / 4);
+    L.lds = (size_t)(kSelectThreads / kWave) * (p.ix.TILE / 8);
     L.grid = dim3(grid_for(p.nq, cap));
     L.block = dim3(kSelectThreads);
     L.func = reinterpret_cast<const void *>(&k_select<kSelectThreads>);
