@@ -58,7 +58,12 @@ typedef struct suco_build_params {
     int32_t tile_max;   /* most point ids per collision tile, a multiple of 256 in
                            [256, 65536]; 0 means 65536.  Each query's SC-scores are
                            counted tile by tile in on-chip memory.                    */
-    int32_t query_chunk;/* queries processed per internal pass; 0 means automatic    */
+    int32_t query_chunk;/* queries processed per internal pass; 0 means automatic:
+                           as many as 16 GiB of per-query workspace (2 bytes per
+                           point and query) allow, at most 16384; a query call's
+                           nq is split into equal passes of at most this many.
+                           The workspace is allocated by the index on first use
+                           and kept until suco_index_free.                         */
     int32_t flags;      /* SUCO_BUILD_* bits                                          */
 } suco_build_params;
 

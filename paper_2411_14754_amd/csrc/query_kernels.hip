@@ -1,17 +1,18 @@
 // gfx950 kernels of the SuCo query path (k-ANN Query, Alg. 4, with Dynamic
-// Activation, Alg. 3).  One pass over a chunk of queries is four launches:
+// Activation, Alg. 3).  One pass over a chunk of queries is these launches:
 //
-//   activate  one wave-group per (query, subspace): centre distances of both
-//             halves, their ranks, and the activated cell set (Alg. 4 first
-//             loop body and Alg. 3)
-//   collide   one work-group per (query, id tile): SC-scores of the tile's
-//             points counted in LDS (Alg. 4 counting loops), per-tile
-//             histogram of scores
-//   select    one work-group per (query, id tile): global score threshold
-//             from the tile histograms, stable compaction of the candidates
+//   activate  one wave per (query, subspace): centre distances of both halves
+//             and the activated cell set (Alg. 4 first loop body and Alg. 3),
+//             by Alg. 3's walk for small budgets or a bisection over the key
+//   order     one block: the pass's queries, heaviest first
+//   collide   one work-group per (query, group of id tiles): SC-scores of a
+//             tile's points counted in LDS (Alg. 4 counting loops), per-tile
+//             histogram of scores, non-zero ids listed by score level
+//   select    one work-group per query, one wave per tile: global score
+//             threshold from the tile histograms, candidates in ascending id
 //             (Alg. 4 "sort SC_scores", first beta*n)
-//   rerank    gathered FP32 distances of the candidates with per-wave top-k
-//             lists, then a per-query merge (Alg. 4 last lines)
+//   rerank    gathered distances of the candidates with per-wave top-k lists,
+//   merge     then a per-query merge (Alg. 4 last lines)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
