@@ -711,14 +711,23 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
             if (sv > s0) seg[L.G[b][sv + 1] + atomicAdd(&L.cur[b][sv], 1u)] = (uint16_t)(4 * w + u);
         }
     };
+    // a word is skipped at once when none of its bytes exceeds s0: bytes are
+    // at most N_s <= 127, so b + (127 - s0) sets bit 7 exactly when b > s0,
+    // without a carry into the next byte
+    const uint32_t above = (0x7fu - s0) * 0x01010101u;
+    auto listed = [&](uint32_t x) { return ((x + above) & 0x80808080u) != 0u; };
     if (sparse) {
 #pragma unroll
         for (int q = 0; q < kKeep; ++q)
-            if (xk[q] != 0u) place(wk[q], xk[q]);
+            if (listed(xk[q])) place(wk[q], xk[q]);
     } else {
-        for (int j = tid; j < nw; j += NT) {
-            const uint32_t x = sc[j];
-            if (x != 0u) place(j, x);
+        const uint4 *sc4 = reinterpret_cast<const uint4 *>(sc);
+        for (int j4 = tid; j4 < (nw >> 2); j4 += NT) {
+            const uint4 x = sc4[j4];
+            if (listed(x.x)) place(4 * j4, x.x);
+            if (listed(x.y)) place(4 * j4 + 1, x.y);
+            if (listed(x.z)) place(4 * j4 + 2, x.z);
+            if (listed(x.w)) place(4 * j4 + 3, x.w);
         }
     }
     if (a.scores != nullptr) {
@@ -749,7 +758,8 @@ __device__ __forceinline__ void collide_finish(const QueryPass &a, CollideLds<NT
 // cells than one batch holds): runs are reloaded batch by batch.
 template <int NT>
 __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> &L, uint32_t *sc, const int ql,
-                                             const int p, const int my_nc, const int c_first, int &b) {
+                                             const int p, const int my_nc, const int c_first, const int c_second,
+                                             int &b) {
     const int P = a.ix.P, ns = a.ix.ns, K = a.ix.K, TILE = a.ix.TILE;
     const int RJ = a.runs_per_sub;
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
@@ -764,7 +774,7 @@ __device__ __forceinline__ void collide_tile(const QueryPass &a, CollideLds<NT> 
         uint32_t len = 0;
         int64_t st = 0;
         if (has_i && j < my_nc) {
-            const int c = jb == 0 ? c_first : (int)my_cells[j];
+            const int c = jb == 0 ? c_first : (jb == RJ ? c_second : (int)my_cells[j]);
             const uint32_t s = to[c];
             len = to[c + 1] - s;
             st = (int64_t)i * P * TILE + s;
@@ -867,7 +877,9 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
         // that ends the counting of its first tile)
         for (int t = threadIdx.x; t < kPruneLevels; t += NT) L.Gc[t] = 0u;
         if (batched) {
-            for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first, b);
+            // the second batch's cell is kept too (it is the same for every tile)
+            const int c_second = jj + RJ < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj + RJ] : 0;
+            for (int p = g; p < a.ix.P; p += S) collide_tile<NT>(a, L, sc, ql, p, my_nc, c_first, c_second, b);
         } else {
             collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first, b);
         }
