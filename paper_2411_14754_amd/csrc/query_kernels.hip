@@ -452,14 +452,15 @@ __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
 // tile (ids are stored tile-major).  The block loads up to NT run descriptors
 // at once into LDS (one thread per run), scans their lengths, and then the
 // threads take the flattened ids of all those runs, kCollideUnroll at a time
-// with their loads issued together, each finding its run by a binary search
-// over the run prefix.  A query's first batch of cells is read once and kept
-// in registers for all its tiles.
-// The block then counts G[t] = #{score >= t} with 7-bit SWAR compares and
-// lists every point of non-zero score, as its tile-local id, grouped by score
-// level in descending order: level s occupies [G[s+1], G[s]) of the tile's
-// list.  Points of score 0 are not written; the dense scores are written only
-// when asked for.
+// with their loads issued together, each finding its run through a table of
+// every 32nd position (or a binary search past it).  A query's first batches
+// of cells are read once and kept in registers for all its tiles.
+// The block then has G[t] = #{score >= t} (from the counting atomics' old
+// values, or by 7-bit SWAR compares over the words) and lists every point of
+// non-zero score, as its tile-local id, grouped by score level in descending
+// order: level s occupies [G[s+1], G[s]) of the tile's list.  Points of score
+// 0 are not written, nor the levels the selection can no longer take (see
+// kPruneLevels); the dense scores are written only when asked for.
 // Words of the tile touched by the counting are listed as they are first
 // incremented (a wave appends its first touches with one atomic), so the
 // passes after the counting visit only those words; when more than kTouchCap

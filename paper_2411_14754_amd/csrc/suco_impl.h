@@ -50,7 +50,8 @@ struct QueryPass {
     int32_t *aprime;          // [nq][ns]
     float *feat;              // [nq][2ns] or null
     uint32_t *hist;           // [nq][P][ns+2] tile counts of score >= t
-    uint16_t *lvl;            // [nq][P][TILE] non-zero-score tile-local ids by level
+    uint16_t *lvl;            // [nq][P][TILE] non-zero-score tile-local ids by level (the levels the
+                              //   selection can no longer take are left out)
     uint8_t *scores;          // [nq][P*TILE] dense scores, or null
     uint32_t *cand;           // [nq][B]
     const float *Dext;        // [nq][2ns][sqrt_k] centre distances computed elsewhere, or null
