@@ -119,7 +119,7 @@ __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
 // stops at the cell that brings the count to A.  A row that would need a
 // column past kWalkCols, or a walk longer than kWalkSteps, returns false and
 // the caller takes the general path.
-constexpr int kWalkCols = 8;
+constexpr int kWalkCols = 12;
 constexpr int kWalkSteps = 64;
 constexpr int kWalkRatio = 16;   // walk when A*K <= kWalkRatio*n (about that many cells of average size)
 
