@@ -163,9 +163,8 @@ __global__ void k_cent_to_f32(const double *c64, float *c32, int64_t m) {
 
 // One wave per (tile, subspace): counting sort of the tile's ids by cell,
 // stable (ids ascending inside each cell), written tile-major.
-__global__ __launch_bounds__(64) void k_imi_build(const uint8_t *assign, int64_t n, int ns, int sk,
-                                                   int P, int TILE, uint32_t *toffs, uint16_t *ids16,
-                                                   uint32_t *csize) {
+__global__ __launch_bounds__(64) void k_imi_build(const uint8_t *assign, int64_t n, int sk, int P, int TILE,
+                                                   uint32_t *toffs, uint16_t *ids16, uint32_t *csize) {
     extern __shared__ uint32_t cur[];          // [K]
     const int p = blockIdx.x, i = blockIdx.y, lane = threadIdx.x, K = sk * sk;
     const int64_t t0 = (int64_t)p * TILE;
@@ -267,8 +266,8 @@ hipError_t launch_cent_to_f32(const double *c64, float *c32, int64_t m, hipStrea
 hipError_t launch_imi_build(const uint8_t *assign, int64_t n, int ns, int sk, int P, int TILE,
                             uint32_t *toffs, uint16_t *ids16, uint32_t *csize, hipStream_t s) {
     const size_t lds = sizeof(uint32_t) * (size_t)sk * sk;
-    hipLaunchKernelGGL(k_imi_build, dim3((unsigned)P, (unsigned)ns), dim3(kWave), lds, s, assign, n, ns,
-                       sk, P, TILE, toffs, ids16, csize);
+    hipLaunchKernelGGL(k_imi_build, dim3((unsigned)P, (unsigned)ns), dim3(kWave), lds, s, assign, n, sk, P, TILE,
+                       toffs, ids16, csize);
     return hipGetLastError();
 }
 

@@ -471,7 +471,6 @@ int suco_mlp_train_epoch(suco_mlp *p, const float *F, const float *t, int64_t m,
     int rc = ensure_rows(p, batch);
     if (rc) return rc;
     double lsum = 0.0;
-    int64_t nb = 0;
     for (int64_t r0 = 0; r0 < m; r0 += batch) {
         const int mb = (int)std::min<int64_t>(batch, m - r0);
         const TrainRows a = rows_args(p, F, t, order, mb, r0);
@@ -487,7 +486,6 @@ int suco_mlp_train_epoch(suco_mlp *p, const float *F, const float *t, int64_t m,
             HIPCHECK(hipStreamSynchronize(st));
             lsum += (double)l * mb;
         }
-        ++nb;
     }
     p->wb_valid = false;
     if (mean_loss) *mean_loss = (float)(lsum / (double)m);
