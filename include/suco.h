@@ -60,8 +60,9 @@ typedef struct suco_build_params {
                            counted tile by tile in on-chip memory.                    */
     int32_t query_chunk;/* queries processed per internal pass; 0 means automatic:
                            as many as 16 GiB of per-query workspace (2 bytes per
-                           point and query) allow, at most 16384; a query call's
-                           nq is split into equal passes of at most this many.
+                           point, 2 bytes per cell and subspace) allow, at most
+                           16384; a query call's nq is split into equal passes
+                           of at most this many.
                            The workspace is allocated by the index on first use
                            and kept until suco_index_free.                         */
     int32_t flags;      /* SUCO_BUILD_* bits                                          */

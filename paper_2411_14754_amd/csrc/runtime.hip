@@ -62,11 +62,13 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->TILE = (int)((per + 255) / 256 * 256);
     ix->P = (int)((n + ix->TILE - 1) / ix->TILE);
     const int64_t span = (int64_t)ix->P * ix->TILE;
-    // Queries per pass: the level lists take 2 bytes per point and query, and
-    // passes as large as that allows (up to 16 GiB of lists, 16384 queries)
-    // cost less per query than small ones (fewer launches, fuller grids).
+    // Queries per pass: a pass's workspace takes, per query, 2 bytes per point
+    // (level lists), 2 bytes per cell and subspace (activated cells) and the
+    // tile histograms; passes as large as 16 GiB of that allows (at most 16384
+    // queries) cost less per query than small ones (fewer launches, fuller grids).
+    const int64_t per_query = 2 * span + 2 * (int64_t)ns * sk * sk + 4 * (int64_t)ix->P * (ns + 2);
     if (p && p->query_chunk > 0) ix->chunk = p->query_chunk;
-    else ix->chunk = (int)std::clamp<int64_t>((int64_t(1) << 34) / (2 * span), 16, 16384);
+    else ix->chunk = (int)std::clamp<int64_t>((int64_t(1) << 34) / per_query, 16, 16384);
     ix->halves_h = make_layout(d, ns);
     if ((rc = dev_alloc(&ix->X, (size_t)n * d)) || (rc = dev_alloc(&ix->cent, (size_t)sk * d)) ||
         (rc = dev_alloc(&ix->halves, (size_t)2 * ns)) ||
