@@ -98,8 +98,9 @@ SUCO_API int64_t suco_count_B(double beta, int64_t n, int32_t k);
  * ids in ascending order.  Centres are stored in FP32 (rounded once).
  *
  *  D      device [n][d] float32, copied into the index.
- *  limits 1 <= n < 2^31; 2 <= d; 1 <= n_s <= min(127, d/2);
- *         1 <= sqrt_k <= 128 and sqrt_k <= n.
+ *  limits 1 <= n < 2^31; 2 <= d; 1 <= n_s <= d/2; 1 <= sqrt_k <= n
+ *         (SUCO_E_INVAL otherwise).  The kernels take n_s <= 127 and
+ *         sqrt_k <= 128 (SUCO_E_UNSUPPORTED beyond).
  *  out    receives the new handle (unchanged on error).
  */
 SUCO_API int suco_build(const float *D, int64_t n, int32_t d, int32_t n_s, int32_t sqrt_k,
@@ -134,6 +135,24 @@ SUCO_API int suco_index_flags(const suco_index *ix, int32_t *flags);
 /* Release an index (NULL is accepted).  Waits for its pending queries. */
 SUCO_API int suco_index_free(suco_index *ix);
 
+/* Save an index to a file and load it back (the output of Create Index,
+ * Alg. 2, with the data it indexes), so that a query process need not run
+ * k-means again.  The file holds a 64-byte header (magic "SUCOIDX1", version
+ * 1, n, d, n_s, sqrt_k, the SUCO_BUILD_* flags, tile_max and query_chunk the
+ * index was built with, and a 64-bit checksum of the rest), then the FP32
+ * centres (layout of suco_build_from_index), the assignments as bytes
+ * [2*n_s][n] and D [n][d] FP32, each section zero-padded to a multiple of 8
+ * bytes; little-endian.  Save writes `path`.tmp and renames it; it
+ * synchronises the index's device.  Load checks the header and the file size
+ * before any device work, rebuilds the index from the stored centres and
+ * assignments (as suco_build_from_index), and fails with SUCO_E_INVAL if the
+ * checksum does not match.  p overrides the stored build parameters (NULL:
+ * those recorded in the file).  A loaded index answers every query bitwise
+ * as the saved one did.
+ *  path  host NUL-terminated file name. */
+SUCO_API int suco_index_save(const suco_index *ix, const char *path);
+SUCO_API int suco_index_load(const char *path, const suco_build_params *p, void *stream, suco_index **out);
+
 /* ---------------------------------------------------------------- query --
  * k-ANN Query (Alg. 4 with Dynamic Activation, Alg. 3), one batch:
  *  1. per subspace, squared distances from each query half to the sqrt_k
@@ -149,15 +168,19 @@ SUCO_API int suco_index_free(suco_index *ix);
  *  Q      device [nq][d] float32 queries.
  *  ids    device [nq][k] int32 result point ids, nearest first.
  *  dists  device [nq][k] float32 Euclidean (not squared) distances.
- *  limits nq >= 0 (0 is a no-op), 1 <= k <= 64, k <= n, 0 < alpha <= 1,
- *         0 < beta <= 1.
+ *  limits nq >= 0 (0 is a no-op), 1 <= k <= n, 0 < alpha <= 1,
+ *         0 < beta <= 1 (SUCO_E_INVAL otherwise); the kernels take k <= 64
+ *         (SUCO_E_UNSUPPORTED beyond).
  */
 SUCO_API int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
                double beta, int32_t *ids, float *dists, void *stream);
 
 /* As suco_query with one collision ratio per query: alpha_q device [nq]
- * float32, each in (0, 1]; query j activates A_j = max(1, ceil(alpha_q[j]*n))
- * points per subspace (the value is widened to FP64 before the product). */
+ * float32, each meant to lie in (0, 1]; query j activates
+ * A_j = max(1, ceil(alpha_q[j]*n)) points per subspace (the value is widened
+ * to FP64 before the product).  Device values are not checked on the host:
+ * a value above 1, +inf or NaN activates every cell (A_j = n) and a value
+ * <= 0 activates A_j = 1 point. */
 SUCO_API int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, int32_t k,
                      const float *alpha_q, double beta, int32_t *ids, float *dists, void *stream);
 
@@ -274,7 +297,7 @@ SUCO_API int suco_batcher_free(suco_batcher *b);
  *     distance from the query half to its nearest centre, then the query norm;
  *   x = (f - mu) / sigma; h1 = GELU(W1 x + b1); h2 = GELU(W2 h1 + b2);
  *   y = W3 h2 + b3 (y predicts log alpha); GELU(x) = x * Phi(x);
- *   alpha = clamp(scale * exp(y), alpha_min, alpha_max).
+ *   alpha = clamp(scale * exp(y), alpha_min, alpha_max) (NaN gives alpha_max).
  * Parameters are one FP32 array in the order W1 [H][n_in], b1 [H], W2 [H][H],
  * b2 [H], W3 [H], b3 [1]; H = 128.  Training runs in FP32 on the GPU (mean
  * squared error, Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias

@@ -62,8 +62,8 @@ def lib():
         L.so_argsort.argtypes = [P, i32, P]
         L.so_da.restype = i64
         L.so_da.argtypes = [P, i32, P, P, P, P, i64, i32, P, P]
-        L.so_da_literal_trace.restype = i64
-        L.so_da_literal_trace.argtypes = [P, i32, P, P, P, P, i64, P, P, P]
+        L.so_da_trace.restype = i64
+        L.so_da_trace.argtypes = [P, i32, P, P, P, P, i64, P, P, P]
         L.so_select.argtypes = [P, i64, i64, P]
         L.so_rerank.argtypes = [P, i32, P, P, i64, i32, P, P]
         L.so_query.argtypes = [P, P, i64, i32, P, C.c_double, i32, P, P, P, P, P, P, i32]
@@ -194,14 +194,15 @@ class Index:
         return cells[: nc[0]].copy(), int(ap)
 
     def da_trace(self, i, d1, i1, d2, i2, A):
-        """Alg. 3 literally; also the number of active first-half rows after each round."""
+        """Form 0 of Dynamic Activation (Alg. 3's retrieval order, walked row by row); also the
+        number of first-half rows Alg. 3 has activated after each round."""
         cells = np.zeros(self.K, np.int32)
         trace = np.zeros(self.K, np.int32)
         nc = np.zeros(1, np.int64)
         d1 = np.ascontiguousarray(d1, np.float64); d2 = np.ascontiguousarray(d2, np.float64)
         i1 = np.ascontiguousarray(i1, np.int32); i2 = np.ascontiguousarray(i2, np.int32)
-        ap = lib().so_da_literal_trace(self.h, i, _p(d1), _p(i1), _p(d2), _p(i2), int(A), _p(cells),
-                                       _p(nc), _p(trace))
+        ap = lib().so_da_trace(self.h, i, _p(d1), _p(i1), _p(d2), _p(i2), int(A), _p(cells),
+                               _p(nc), _p(trace))
         return cells[: nc[0]].copy(), int(ap), trace[: nc[0]].copy()
 
     def query(self, Q, k, alpha, beta, form=0, want_scores=False, want_cand=False, nthreads=None):

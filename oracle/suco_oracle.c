@@ -26,11 +26,11 @@
 #define EXPORT __attribute__((visibility("default")))
 
 /* ------------------------------------------------------------------------ */
-/* Counts A and B (Alg. 3 stop test "retrieved >= alpha*n"; Alg. 1/4 loops    */
-/* "z = 1 to beta*n").  READING: A = ceil(alpha*n), B = floor(beta*n), both   */
-/* in FP64 with a 1e-9 guard against representation error (0.03*1e6 is       */
-/* 30000.000000000004), A >= 1, and B raised to k so that "top-k of the       */
-/* candidates" is defined.                                                    */
+/* Counts A and B.  Alg. 3 stops once the retrieved points reach alpha*n;    */
+/* Alg. 1 and Alg. 4 take the first beta*n points of the score order.        */
+/* READING: A = ceil(alpha*n), B = floor(beta*n), both in FP64 with a 1e-9   */
+/* guard against representation error (0.03*1e6 is 30000.000000000004),     */
+/* A >= 1, and B raised to k so that a top-k of the candidates exists.       */
 /* ------------------------------------------------------------------------ */
 EXPORT int64_t so_count_A(double alpha, int64_t n) {
     int64_t a = (int64_t)ceil(alpha * (double)n - 1e-9);
@@ -49,7 +49,7 @@ EXPORT int64_t so_count_B(double beta, int64_t n, int k) {
 /* ------------------------------------------------------------------------ */
 /* Subspace division (Sec. 3.2 contiguous division, a special case of        */
 /* Def. 3; the last subspace takes the remaining dimensions) and the split   */
-/* of each subspace into two halves (Alg. 2, "divide S_i into S_i^1, S_i^2").*/
+/* of each subspace into the two halves Alg. 2 clusters separately.         */
 /* READING: half 1 = first floor(s_i/2) dims, half 2 = the rest.            */
 /* Output: for half g = 2*i + h, its first dim and its width.               */
 /* ------------------------------------------------------------------------ */
@@ -269,8 +269,8 @@ EXPORT const int64_t *so_index_offs(const so_index *ix) { return ix->offs; }
 EXPORT const int32_t *so_index_ids(const so_index *ix) { return ix->ids; }
 
 /* ------------------------------------------------------------------------ */
-/* Alg. 4, "calculate the distance between each centroid ... and q_1^i":     */
-/* squared distances from the query's half g to the sqrtK FP32 centres.      */
+/* Alg. 4, first loop: squared distances from the query's half g to the     */
+/* sqrtK FP32 centres of that half.                                          */
 /* READING: squared L2, so that dists1 + dists2 is the squared distance to   */
 /* the cell's product centre.                                                */
 /* ------------------------------------------------------------------------ */
@@ -293,7 +293,7 @@ EXPORT void so_centroid_dists(const so_index *ix, const float *q, int g, double 
  * distances, from the query half and centres first rounded to BF16. */
 EXPORT void so_index_set_s1_bf16(so_index *ix, int on) { ix->s1_bf16 = on != 0; }
 
-/* Alg. 4, "obtain the indices of sorted dists in ascending order".
+/* Alg. 4, first loop: the centres of a half ordered by ascending distance.
  * READING: ties by centre id. */
 static int cmp_by_dist_then_id(const void *a, const void *b, void *ctx) {
     const double *dd = (const double *)ctx;
@@ -315,46 +315,44 @@ EXPORT void so_argsort(const double *dist, int sk, int *idx) {
 /* their count, and the number of points retrieved A' (whole cells, >= A).   */
 /* ------------------------------------------------------------------------ */
 
-/* Form 0: Alg. 3 as written, with READINGS for what it leaves open:
- *  - active_dists starts at +inf except entry 0 (line 1 leaves it unset);
- *  - when a row's column pointer passes the last column the row is set to
- *    +inf (lines 15-17 would otherwise retrieve the same cell again);
- *  - the argmin of line 6 takes the first minimum. */
-static int64_t da_literal(const so_index *ix, int i, const double *d1, const int *idx1,
-                          const double *d2, const int *idx2, int64_t A, int32_t *cells, int64_t *ncells,
-                          int32_t *active_trace) {
+/* Form 0: the retrieval order by its definition, walked row by row.  Alg. 3
+ * takes cells in ascending key order (Sec. 4.2: a smaller distance sum is
+ * retrieved earlier), and with the READINGS on what it leaves open (ties of
+ * the argmin to the first row, an exhausted row never taken again) that order
+ * is ascending (key, r1, r2).  Inside one row r1 the keys are non-decreasing
+ * in r2 because the second half's distances are sorted, so each row's
+ * untaken cells begin at a column pointer; the next cell of the whole order is
+ * the smallest (key, r1) among the rows' pointer cells.  The walk takes it,
+ * advances that row's pointer and stops once the retrieved points reach A.
+ * active_trace[t], if given, is the number of first-half rows Alg. 3 has
+ * activated after round t: row r + 1 joins when cell (r, 0) is retrieved, so
+ * it is 1 + the rows whose column 0 is taken, at most sqrtK. */
+static int64_t da_frontier(const so_index *ix, int i, const double *d1, const int *idx1,
+                           const double *d2, const int *idx2, int64_t A, int32_t *cells, int64_t *ncells,
+                           int32_t *active_trace) {
     int sk = ix->sk;
     const int64_t *off = ix->offs + (int64_t)i * (ix->K + 1);
-    int *act_idx = (int *)malloc(sizeof(int) * sk);
-    double *act_d = (double *)malloc(sizeof(double) * sk);
-    for (int r = 0; r < sk; ++r) { act_idx[r] = 0; act_d[r] = INFINITY; }
+    int *col = (int *)calloc((size_t)sk, sizeof(int));   /* next untaken column of each row */
     int64_t retrieved = 0, nc = 0;
-    int nact = 1;                                   /* rows activated so far */
-    act_idx[0] = 0;
-    act_d[0] = d1[idx1[0]] + d2[idx2[0]];
+    int started = 0;                                     /* rows whose column 0 is taken */
     for (;;) {
-        int pos = 0;
-        for (int r = 1; r < sk; ++r)
-            if (act_d[r] < act_d[pos]) pos = r;
-        if (act_d[pos] == INFINITY) break;          /* every cell retrieved */
-        int cell = idx1[pos] * sk + idx2[act_idx[pos]];
+        int best = -1;
+        double bkey = 0.0;
+        for (int r = 0; r < sk; ++r) {
+            if (col[r] == sk) continue;                  /* row exhausted */
+            double key = d1[idx1[r]] + d2[idx2[col[r]]];
+            if (best < 0 || key < bkey) { best = r; bkey = key; }   /* equal keys: smaller r1 */
+        }
+        if (best < 0) break;                             /* every cell taken */
+        int cell = idx1[best] * sk + idx2[col[best]];
+        if (col[best] == 0) started += 1;
+        col[best] += 1;
         cells[nc++] = cell;
         retrieved += off[cell + 1] - off[cell];
+        if (active_trace) active_trace[nc - 1] = started + 1 < sk ? started + 1 : sk;
         if (retrieved >= A) break;
-        if (act_idx[pos] == 0 && pos < sk - 1) {
-            act_idx[pos + 1] = 0;
-            act_d[pos + 1] = d1[idx1[pos + 1]] + d2[idx2[0]];
-            nact = pos + 2;
-        }
-        if (act_idx[pos] < sk - 1) {
-            act_idx[pos] += 1;
-            act_d[pos] = d1[idx1[pos]] + d2[idx2[act_idx[pos]]];
-        } else {
-            act_d[pos] = INFINITY;
-        }
-        if (active_trace) active_trace[nc - 1] = nact;
     }
-    free(act_idx); free(act_d);
+    free(col);
     *ncells = nc;
     return retrieved;
 }
@@ -458,14 +456,14 @@ static int64_t da_multiseq(const so_index *ix, int i, const double *d1, const in
 
 EXPORT int64_t so_da(const so_index *ix, int i, const double *d1, const int *idx1, const double *d2,
                      const int *idx2, int64_t A, int form, int32_t *cells, int64_t *ncells) {
-    if (form == 0) return da_literal(ix, i, d1, idx1, d2, idx2, A, cells, ncells, NULL);
+    if (form == 0) return da_frontier(ix, i, d1, idx1, d2, idx2, A, cells, ncells, NULL);
     if (form == 1) return da_sortall(ix, i, d1, idx1, d2, idx2, A, cells, ncells);
     return da_multiseq(ix, i, d1, idx1, d2, idx2, A, cells, ncells);
 }
 
 /* ------------------------------------------------------------------------ */
-/* Selection (Alg. 4, "sort SC_scores in descending order" and take the     */
-/* first beta*n).  READING: sort by (score descending, id ascending) and    */
+/* Selection (Alg. 4): the points ordered by descending SC-score, the first  */
+/* beta*n kept.  READING: order by (score descending, id ascending) and     */
 /* keep exactly B.  Output in that order.                                    */
 /* ------------------------------------------------------------------------ */
 static int cmp_u64(const void *a, const void *b) {
@@ -525,7 +523,7 @@ EXPORT int so_query(const so_index *ix, const float *Q, int64_t nq, int k, const
     for (int64_t qi = 0; qi < nq; ++qi) {
         const float *q = Q + qi * d;
         int64_t A = so_count_A(alpha[qi], n);
-        uint8_t *sc = (uint8_t *)calloc((size_t)n, 1);                /* line 1 */
+        uint8_t *sc = (uint8_t *)calloc((size_t)n, 1);
         double *d1 = (double *)malloc(sizeof(double) * sk), *d2 = (double *)malloc(sizeof(double) * sk);
         int *i1 = (int *)malloc(sizeof(int) * sk), *i2 = (int *)malloc(sizeof(int) * sk);
         int32_t *cells = (int32_t *)malloc(sizeof(int32_t) * K);
@@ -554,12 +552,12 @@ EXPORT int so_query(const so_index *ix, const float *Q, int64_t nq, int k, const
     return rc;
 }
 
-/* Alg. 3 as written, also reporting after each retrieval round how many rows
- * of the first half have been activated (the running example of Fig. 5). */
-EXPORT int64_t so_da_literal_trace(const so_index *ix, int i, const double *d1, const int *idx1,
+/* Form 0, also reporting after each retrieval round how many rows of the
+ * first half Alg. 3 has activated (the running example of Fig. 5). */
+EXPORT int64_t so_da_trace(const so_index *ix, int i, const double *d1, const int *idx1,
                                    const double *d2, const int *idx2, int64_t A, int32_t *cells,
                                    int64_t *ncells, int32_t *active_trace) {
-    return da_literal(ix, i, d1, idx1, d2, idx2, A, cells, ncells, active_trace);
+    return da_frontier(ix, i, d1, idx1, d2, idx2, A, cells, ncells, active_trace);
 }
 
 /* Activated cells of one query in one subspace, exposed for stage tests. */

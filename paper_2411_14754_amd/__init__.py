@@ -26,7 +26,7 @@ EXPORTED = (
     "suco_batcher_free", "suco_mlp_num_params", "suco_mlp_create", "suco_mlp_set_norm", "suco_mlp_get_params",
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
-    "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags",
+    "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags", "suco_index_save", "suco_index_load",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order")
@@ -74,6 +74,8 @@ def lib():
         L.suco_index_info.argtypes = [P, P, P, P, P]
         L.suco_index_free.argtypes = [P]
         L.suco_index_flags.argtypes = [P, P]
+        L.suco_index_save.argtypes = [P, C.c_char_p]
+        L.suco_index_load.argtypes = [C.c_char_p, C.POINTER(BuildParams), P, C.POINTER(P)]
         L.suco_query.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
         L.suco_query_alpha.argtypes = [P, P, i64, i32, P, dbl, P, P, P]
         L.suco_query_debug.argtypes = [P, P, i64, i32, P, dbl, dbl, P, P, P, P, P, P, P, P, P]
@@ -183,6 +185,22 @@ class Index:
         _check(lib().suco_build_from_index(px, n, d, n_s, sqrt_k, cent.ctypes.data_as(P),
                                            asg.ctypes.data_as(P), C.byref(prm), _stream(stream), C.byref(h)))
         return cls(h.value, n, d, n_s, sqrt_k)
+
+    def save(self, path: str):
+        """Write the index and its data to `path` (see suco_index_save)."""
+        _check(lib().suco_index_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str, tile_max=None, query_chunk=None, flags=None, stream=None) -> "Index":
+        """Read an index saved by save(); keyword arguments override the stored build parameters."""
+        h = C.c_void_p()
+        prm = None
+        if tile_max is not None or query_chunk is not None or flags is not None:
+            prm = C.byref(cls._params(0, 0, tile_max or 0, query_chunk or 0, flags or 0))
+        _check(lib().suco_index_load(os.fsencode(path), prm, _stream(stream), C.byref(h)))
+        n, d, ns, sk = i64(), i32(), i32(), i32()
+        _check(lib().suco_index_info(h, C.byref(n), C.byref(d), C.byref(ns), C.byref(sk)))
+        return cls(h.value, n.value, d.value, ns.value, sk.value)
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -311,7 +311,8 @@ int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, doub
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
     if (!out) return fail(SUCO_E_INVAL, "out must not be NULL");
     if (max_batch < 1 || max_batch > 65536) return fail(SUCO_E_INVAL, "max_batch must be in [1, 65536]");
-    if (k < 1 || k > kMaxK || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, min(64, n)]");
+    if (k < 1 || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, n]");
+    if (k > kMaxK) return fail(SUCO_E_UNSUPPORTED, "the kernels take k <= 64");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
     suco_batcher *b = new (std::nothrow) suco_batcher();
     if (!b) return fail(SUCO_E_NOMEM, "host allocation failed");

@@ -120,7 +120,8 @@ __global__ __launch_bounds__(kH) void k_mlp_infer(InferPass ip) {
             const float yv = w.b3[0] + red[0] + red[1];
             if (ip.y) ip.y[r] = yv;
             float a = ip.scale * expf(yv);
-            a = a < ip.amin ? ip.amin : (a > ip.amax ? ip.amax : a);
+            // a NaN prediction takes the largest budget, like +inf
+            a = a <= ip.amax ? (a >= ip.amin ? a : ip.amin) : ip.amax;
             if (ip.alpha) ip.alpha[r] = a;
             if (ip.alpha64) ip.alpha64[r] = (double)a;
         }
@@ -551,7 +552,8 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
     if (!(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))
         return fail(SUCO_E_INVAL, "need 0 < alpha_min <= alpha_max <= 1");
     if (nq < 0 || (nq > 0 && (!Q || !ids || !dists))) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
-    if (k < 1 || k > kMaxK || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, min(64, n)]");
+    if (k < 1 || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, n]");
+    if (k > kMaxK) return fail(SUCO_E_UNSUPPORTED, "the kernels take k <= 64");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
     if (nq == 0) return SUCO_OK;
     hipStream_t st = (hipStream_t)stream;

@@ -10,7 +10,7 @@
 //             histogram of scores, non-zero ids listed by score level
 //   select    one work-group per query, one wave per tile: global score
 //             threshold from the tile histograms, candidates in ascending id
-//             (Alg. 4 "sort SC_scores", first beta*n)
+//             (Alg. 4 selection: the first beta*n of the score order)
 //   rerank    gathered distances of the candidates with per-wave top-k lists,
 //   merge     then a per-query merge (Alg. 4 last lines)
 #include <hip/hip_runtime.h>
@@ -84,8 +84,12 @@ __device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint3
 }
 
 // A = max(1, ceil(alpha*n - 1e-9)), capped at n, in FP64 without contraction.
+// A per-query alpha is not validated on the host: above 1, +inf and NaN
+// activate every point, and alpha <= 0 activates one.
 __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
 #pragma clang fp contract(off)
+    if (!(alpha <= 1.0)) return (uint32_t)n;
+    if (!(alpha > 0.0)) return 1u;
     double prod = alpha * (double)n;
     double v = ceil(prod - 1e-9);
     int64_t a = (int64_t)v;

@@ -1,17 +1,22 @@
 // Host side of the SuCo library: argument validation, the index object, the
 // query workspace and the launch sequences behind the C ABI in suco.h.
+#include <cstdio>
+
 #include "runtime_impl.h"
 
 using namespace suco;
 
 namespace {
 
+// Shapes the problem admits (INVAL otherwise) and, among them, those the
+// kernels take (UNSUPPORTED otherwise).
 int check_shape(int64_t n, int32_t d, int32_t ns, int32_t sk) {
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(SUCO_E_INVAL, "n must be in [1, 2^31)");
     if (d < 2) return fail(SUCO_E_INVAL, "d must be >= 2");
-    if (ns < 1 || ns > kMaxNs || ns > d / 2) return fail(SUCO_E_INVAL, "n_s must be in [1, min(127, d/2)]");
-    if (sk < 1 || sk > kMaxSqrtK) return fail(SUCO_E_INVAL, "sqrt_k must be in [1, 128]");
-    if (sk > n) return fail(SUCO_E_INVAL, "sqrt_k must not exceed n");
+    if (ns < 1 || ns > d / 2) return fail(SUCO_E_INVAL, "n_s must be in [1, d/2]");
+    if (sk < 1 || sk > n) return fail(SUCO_E_INVAL, "sqrt_k must be in [1, n]");
+    if (ns > kMaxNs) return fail(SUCO_E_UNSUPPORTED, "the kernels take n_s <= 127");
+    if (sk > kMaxSqrtK) return fail(SUCO_E_UNSUPPORTED, "the kernels take sqrt_k <= 128");
     return SUCO_OK;
 }
 
@@ -28,8 +33,9 @@ std::vector<HalfDims> make_layout(int d, int ns) {
     return h;
 }
 
-// Allocate the index object and copy the dataset; tiles are chosen so that a
-// multiple of 8 tiles (one group per XCD) covers the ids when n is large.
+// Allocate the index object and copy the dataset (D == null: the caller fills
+// X); tiles are chosen so that a multiple of 8 tiles (one group per XCD)
+// covers the ids when n is large.
 int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_build_params *p,
                  hipStream_t st, suco_index **out) {
     int rc = check_shape(n, d, ns, sk);
@@ -57,6 +63,8 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->n = n; ix->d = d; ix->ns = ns; ix->sk = sk; ix->K = sk * sk;
     ix->no_byte_rows = p && (p->flags & SUCO_BUILD_NO_BYTE_ROWS);
     ix->want_bf16 = p && (p->flags & SUCO_BUILD_BF16);
+    ix->tile_req = p ? p->tile_max : 0;
+    ix->chunk_req = p ? std::max(0, p->query_chunk) : 0;
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
     const int64_t per = (n + P0 - 1) / P0;
     ix->TILE = (int)((per + 255) / 256 * 256);
@@ -83,7 +91,7 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
         ix->release(); delete ix;
         return fail(SUCO_E_HIP, "hipEventCreate failed");
     }
-    hipError_t e = hipMemcpyAsync(ix->X, D, sizeof(float) * n * d, hipMemcpyDeviceToDevice, st);
+    hipError_t e = D ? hipMemcpyAsync(ix->X, D, sizeof(float) * n * d, hipMemcpyDeviceToDevice, st) : hipSuccess;
     if (e == hipSuccess)
         e = hipMemcpyAsync(ix->halves, ix->halves_h.data(), sizeof(HalfDims) * 2 * ns, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(ix->csize, 0, sizeof(uint32_t) * ns * ix->K, st);
@@ -211,6 +219,194 @@ int run_kmeans(suco_index *ix, int iters, uint64_t seed, hipStream_t st) {
     return SUCO_OK;
 }
 
+
+// ----------------------------------------------------------- persistence --
+// File layout (little-endian): a 64-byte header, then the FP32 centres
+// [sqrt_k*d], the assignments as bytes [2*n_s][n] and the data [n][d] FP32,
+// each section zero-padded to a multiple of 8 bytes.  The header's checksum
+// covers everything after the header: a 64-bit word hash (h = (h ^ w) *
+// 0x100000001b3 over the little-endian 8-byte words, h0 = 0xcbf29ce484222325,
+// the FNV-1a constants).
+struct FileHeader {
+    char magic[8];          // "SUCOIDX1"
+    uint32_t version;       // 1
+    uint32_t header_bytes;  // 64
+    int64_t n;
+    int32_t d, ns, sk;
+    int32_t flags;          // SUCO_BUILD_* bits the index was built with
+    int32_t tile_max, query_chunk;
+    uint64_t checksum;
+    uint8_t pad[8];
+};
+static_assert(sizeof(FileHeader) == 64, "file header is 64 bytes");
+constexpr char kFileMagic[8] = {'S', 'U', 'C', 'O', 'I', 'D', 'X', '1'};
+constexpr uint64_t kHashInit = 0xcbf29ce484222325ULL, kHashMul = 0x100000001b3ULL;
+
+inline uint64_t pad8(uint64_t b) { return (b + 7) & ~uint64_t(7); }
+
+struct WordHash {
+    uint64_t h = kHashInit;
+    void add(const void *p, size_t bytes) {   // bytes: a multiple of 8
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t t = 0; t < bytes; t += 8) {
+            uint64_t w;
+            std::memcpy(&w, b + t, 8);
+            h = (h ^ w) * kHashMul;
+        }
+    }
+};
+
+struct File {
+    FILE *f = nullptr;
+    ~File() { if (f) std::fclose(f); }
+};
+
+// Write `bytes` from `src` followed by zero padding to a multiple of 8, hashing both.
+bool write_section(FILE *f, const void *src, uint64_t bytes, WordHash &hs) {
+    const uint64_t full = bytes / 8 * 8, rest = bytes - full;
+    if (full && std::fwrite(src, 1, full, f) != full) return false;
+    hs.add(src, full);
+    if (rest) {
+        uint8_t tail[8] = {0};
+        std::memcpy(tail, static_cast<const uint8_t *>(src) + full, rest);
+        if (std::fwrite(tail, 1, 8, f) != 8) return false;
+        hs.add(tail, 8);
+    }
+    return true;
+}
+
+bool read_section(FILE *f, void *dst, uint64_t bytes, WordHash &hs) {
+    const uint64_t full = bytes / 8 * 8, rest = bytes - full;
+    if (full && std::fread(dst, 1, full, f) != full) return false;
+    hs.add(dst, full);
+    if (rest) {
+        uint8_t tail[8];
+        if (std::fread(tail, 1, 8, f) != 8) return false;
+        hs.add(tail, 8);
+        std::memcpy(static_cast<uint8_t *>(dst) + full, tail, rest);
+        for (uint64_t t = rest; t < 8; ++t)
+            if (tail[t]) return false;
+    }
+    return true;
+}
+
+// Rows of X are moved between the device and the file through a pinned buffer.
+constexpr size_t kStageBytes = size_t(64) << 20;
+
+int save_index(const suco_index *ix, const char *path) {
+    DeviceGuard dg(ix->device);
+    const std::string tmp = std::string(path) + ".tmp";
+    File out;
+    out.f = std::fopen(tmp.c_str(), "wb");
+    if (!out.f) return fail(SUCO_E_INVAL, std::string("cannot open ") + tmp + " for writing");
+    FileHeader h{};
+    std::memcpy(h.magic, kFileMagic, 8);
+    h.version = 1; h.header_bytes = sizeof(FileHeader);
+    h.n = ix->n; h.d = ix->d; h.ns = ix->ns; h.sk = ix->sk;
+    h.flags = (ix->no_byte_rows ? SUCO_BUILD_NO_BYTE_ROWS : 0) | (ix->want_bf16 ? SUCO_BUILD_BF16 : 0);
+    h.tile_max = ix->tile_req; h.query_chunk = ix->chunk_req;
+    if (std::fwrite(&h, sizeof h, 1, out.f) != 1) return fail(SUCO_E_INVAL, "write failed: " + tmp);
+    WordHash hs;
+    std::vector<uint8_t> a8((size_t)2 * ix->ns * ix->n);
+    HIPCHECK(hipMemcpy(a8.data(), ix->assign, a8.size(), hipMemcpyDeviceToHost));
+    if (!write_section(out.f, ix->cent_h.data(), sizeof(float) * ix->cent_h.size(), hs) ||
+        !write_section(out.f, a8.data(), a8.size(), hs))
+        return fail(SUCO_E_INVAL, "write failed: " + tmp);
+    const uint64_t xbytes = sizeof(float) * (uint64_t)ix->n * ix->d;
+    void *stage = nullptr;
+    HIPCHECK(hipHostMalloc(&stage, kStageBytes, hipHostMallocDefault));
+    int rc = SUCO_OK;
+    // whole 8-byte words per chunk; the tail (and its padding) is written last
+    const uint64_t words = xbytes / 8 * 8;
+    for (uint64_t off = 0; off < words && rc == SUCO_OK; off += kStageBytes) {
+        const uint64_t len = std::min<uint64_t>(kStageBytes, words - off);
+        hipError_t e = hipMemcpy(stage, reinterpret_cast<const char *>(ix->X) + off, len, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(SUCO_E_HIP, std::string("reading X: ") + hipGetErrorString(e));
+        else if (!write_section(out.f, stage, len, hs)) rc = fail(SUCO_E_INVAL, "write failed: " + tmp);
+    }
+    if (rc == SUCO_OK && xbytes > words) {
+        hipError_t e = hipMemcpy(stage, reinterpret_cast<const char *>(ix->X) + words, xbytes - words,
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(SUCO_E_HIP, std::string("reading X: ") + hipGetErrorString(e));
+        else if (!write_section(out.f, stage, xbytes - words, hs)) rc = fail(SUCO_E_INVAL, "write failed: " + tmp);
+    }
+    (void)hipHostFree(stage);
+    if (rc) return rc;
+    h.checksum = hs.h;
+    if (std::fseek(out.f, 0, SEEK_SET) != 0 || std::fwrite(&h, sizeof h, 1, out.f) != 1 || std::fflush(out.f) != 0)
+        return fail(SUCO_E_INVAL, "write failed: " + tmp);
+    std::fclose(out.f);
+    out.f = nullptr;
+    if (std::rename(tmp.c_str(), path) != 0) return fail(SUCO_E_INVAL, std::string("cannot rename to ") + path);
+    return SUCO_OK;
+}
+
+// Header and size checks come first, before any device work.
+int load_index(const char *path, const suco_build_params *pin, hipStream_t st, suco_index **out) {
+    File in;
+    in.f = std::fopen(path, "rb");
+    if (!in.f) return fail(SUCO_E_INVAL, std::string("cannot open ") + path);
+    FileHeader h{};
+    if (std::fread(&h, sizeof h, 1, in.f) != 1 || std::memcmp(h.magic, kFileMagic, 8) != 0 || h.version != 1 ||
+        h.header_bytes != sizeof(FileHeader))
+        return fail(SUCO_E_INVAL, std::string(path) + " is not a SuCo index file");
+    int rc = check_shape(h.n, h.d, h.ns, h.sk);
+    if (rc) return fail(rc, std::string(path) + ": " + g_err);
+    const uint64_t cbytes = sizeof(float) * (uint64_t)h.sk * h.d, abytes = (uint64_t)2 * h.ns * h.n,
+                   xbytes = sizeof(float) * (uint64_t)h.n * h.d;
+    const uint64_t want = sizeof(FileHeader) + pad8(cbytes) + pad8(abytes) + pad8(xbytes);
+    if (std::fseek(in.f, 0, SEEK_END) != 0) return fail(SUCO_E_INVAL, std::string("cannot seek in ") + path);
+    const long long size = std::ftell(in.f);
+    if (size < 0 || (uint64_t)size != want)
+        return fail(SUCO_E_INVAL, std::string(path) + ": size " + std::to_string(size) + " bytes, expected " +
+                                      std::to_string(want));
+    if (std::fseek(in.f, sizeof(FileHeader), SEEK_SET) != 0) return fail(SUCO_E_INVAL, "seek failed");
+    WordHash hs;
+    std::vector<float> cent((size_t)h.sk * h.d);
+    std::vector<uint8_t> a8((size_t)abytes);
+    if (!read_section(in.f, cent.data(), cbytes, hs) || !read_section(in.f, a8.data(), abytes, hs))
+        return fail(SUCO_E_INVAL, std::string(path) + ": read failed or bad padding");
+    for (uint8_t a : a8)
+        if (a >= h.sk) return fail(SUCO_E_INVAL, std::string(path) + ": assignment out of [0, sqrt_k)");
+    suco_build_params p{};
+    if (pin) p = *pin;
+    else { p.flags = h.flags; p.tile_max = h.tile_max; p.query_chunk = h.query_chunk; }
+    suco_index *ix = nullptr;
+    if ((rc = index_common(nullptr, h.n, h.d, h.ns, h.sk, &p, st, &ix))) return rc;
+    auto drop = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        ix->release();
+        delete ix;
+        return code;
+    };
+    void *stage = nullptr;
+    if (hipHostMalloc(&stage, kStageBytes, hipHostMallocDefault) != hipSuccess)
+        return drop(fail(SUCO_E_NOMEM, "pinned staging buffer"));
+    // whole 8-byte words per chunk, then the tail with its padding
+    const uint64_t words = xbytes / 8 * 8;
+    auto upload = [&](uint64_t off, uint64_t len) {
+        if (!read_section(in.f, stage, len, hs)) return fail(SUCO_E_INVAL, std::string(path) + ": read failed");
+        hipError_t e = hipMemcpyAsync(reinterpret_cast<char *>(ix->X) + off, stage, len, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(SUCO_E_HIP, std::string("uploading X: ") + hipGetErrorString(e));
+        return SUCO_OK;
+    };
+    for (uint64_t off = 0; off < words && rc == SUCO_OK; off += kStageBytes)
+        rc = upload(off, std::min<uint64_t>(kStageBytes, words - off));
+    if (rc == SUCO_OK && xbytes > words) rc = upload(words, xbytes - words);
+    (void)hipHostFree(stage);
+    if (rc) return drop(rc);
+    if (hs.h != h.checksum) return drop(fail(SUCO_E_INVAL, std::string(path) + ": checksum mismatch"));
+    ix->cent_h = cent;
+    hipError_t e = hipMemcpyAsync(ix->cent, cent.data(), cbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ix->assign, a8.data(), abytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return drop(fail(SUCO_E_HIP, std::string("index upload: ") + hipGetErrorString(e)));
+    if ((rc = finish_index(ix, st))) return drop(rc);
+    *out = ix;
+    return SUCO_OK;
+}
+
 // ------------------------------------------------------------ workspace --
 struct Carve {
     char *base;
@@ -268,7 +464,8 @@ int check_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, dou
                 float *dists) {
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
     if (nq < 0) return fail(SUCO_E_INVAL, "nq must be >= 0");
-    if (k < 1 || k > kMaxK || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, min(64, n)]");
+    if (k < 1 || k > ix->n) return fail(SUCO_E_INVAL, "k must be in [1, n]");
+    if (k > kMaxK) return fail(SUCO_E_UNSUPPORTED, "the kernels take k <= 64");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SUCO_E_INVAL, "beta must be in (0, 1]");
     if (nq > 0 && (!Q || !ids || !dists)) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
     return SUCO_OK;
@@ -478,6 +675,17 @@ int suco_index_export(const suco_index *ix, float *centroids, int32_t *assign) {
         for (size_t t = 0; t < a8.size(); ++t) assign[t] = a8[t];
     }
     return SUCO_OK;
+}
+
+int suco_index_save(const suco_index *ix, const char *path) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (!path) return fail(SUCO_E_INVAL, "path must not be NULL");
+    return save_index(ix, path);
+}
+
+int suco_index_load(const char *path, const suco_build_params *p, void *stream, suco_index **out) {
+    if (!path || !out) return fail(SUCO_E_INVAL, "path and out must not be NULL");
+    return load_index(path, p, (hipStream_t)stream, out);
 }
 
 int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, int32_t *sqrt_k) {

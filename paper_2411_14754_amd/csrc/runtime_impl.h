@@ -32,8 +32,11 @@ inline int fail(int code, const std::string &msg) {
 
 constexpr uint64_t kMagic = 0x5375436f49647831ULL;
 
+// alpha above 1, +inf and NaN activate every point; alpha <= 0 activates one.
 inline int64_t count_A_host(double alpha, int64_t n) {
 #pragma clang fp contract(off)
+    if (!(alpha <= 1.0)) return n;
+    if (!(alpha > 0.0)) return 1;
     double prod = alpha * (double)n;
     int64_t a = (int64_t)std::ceil(prod - 1e-9);
     return std::min<int64_t>(std::max<int64_t>(a, 1), n);
@@ -102,6 +105,8 @@ struct suco_index {
     uint8_t *X8 = nullptr;          // byte copy of X when every coordinate is an integer in 0..255
     bool no_byte_rows = false;
     bool want_bf16 = false;
+    int tile_req = 0;               // tile_max and query_chunk as the caller gave them (0 = automatic),
+    int chunk_req = 0;              //   recorded by suco_index_save
     // BF16 split precision (built on request)
     uint16_t *Xb = nullptr;         // [n][d] BF16 copy of X
     float *xerr = nullptr;          // [n] upper bound of |bf16(x) - x|

@@ -7,8 +7,10 @@ ranks cells by FP32 keys and candidates by FP32 distances, the oracle by FP64.
  * Cells: for a (query, subspace) the two activated sets may differ only in
    "band" cells, whose FP64 key is within 1e-5 (relative) of the oracle's
    cutoff key.  Where that happens the scores of the affected points may
-   differ; the comparison then re-runs the oracle's selection and re-rank on
-   the GPU's own scores and checks the GPU's candidates and top-k against that.
+   differ; the GPU's scores must then equal the counts over its own activated
+   cells in the oracle's inverted multi-index (Def. 4 on those cells), its A'
+   their summed sizes, and the oracle's selection and re-rank, re-run on those
+   scores, must give the GPU's candidates and top-k.
  * Top-k: ids must be identical unless distances tie within 1e-5 relative;
    in that case the GPU's list must be a valid top-k: its FP64 distances must
    equal the oracle's sorted top-k distances within 1e-5 relative.
@@ -77,6 +79,23 @@ def check_topk(X, Q, ids, dists, ref_ids, ref_dists, k):
         assert np.allclose(dists[q], true, rtol=REL, atol=1e-6)
 
 
+def scores_from_cells(oix, gpu_cells, gpu_ncells, q):
+    """SC-scores of query q counted over the given activated cells in the
+    oracle's IMI (a point scores once per subspace whose activated cells hold
+    it), and the points in those cells per subspace."""
+    if not hasattr(oix, "_imi"):
+        oix._imi = (oix.offs(), oix.ids())
+    offs, ids = oix._imi
+    sc = np.zeros(oix.n, np.int64)
+    sizes = np.zeros(oix.ns, np.int64)
+    for i in range(oix.ns):
+        for c in gpu_cells[q, i, :gpu_ncells[q, i]].tolist():
+            a, b = int(offs[i, c]), int(offs[i, c + 1])
+            sc[ids[i, a:b]] += 1
+            sizes[i] += b - a
+    return sc, sizes
+
+
 def check_query(oix, X, Q, k, alpha, beta, gpu, key_tol=None):
     """Full comparison of a GPU query_debug result with the oracle.  Returns stats.
     key_tol [nq][ns], if given, widens each (query, subspace) band by that absolute amount."""
@@ -97,6 +116,10 @@ def check_query(oix, X, Q, k, alpha, beta, gpu, key_tol=None):
                        ref["dists"][q:q + 1], k)
         else:
             n_band += 1
+            # the GPU's scores are the counts over its own cells, A' their sizes
+            sc, sizes = scores_from_cells(oix, gpu["cells"], gpu["ncells"], q)
+            assert np.array_equal(g_sc[q].astype(np.int64), sc), f"query {q}: SC-scores of its own cells"
+            assert np.array_equal(np.asarray(gpu["aprime"][q], np.int64), sizes), f"query {q}: A'"
             # conditional parity: the oracle's selection and re-rank on the GPU's scores
             c = oracle.select(g_sc[q], B)
             assert np.array_equal(np.sort(gpu["cand"][q]), np.sort(c)), f"query {q}: conditional candidates"

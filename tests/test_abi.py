@@ -65,3 +65,55 @@ def test_errors_before_any_device_work():
     assert L.suco_query_bf16(None, None, 0, 10, 0.1, 0.1, 0, None, None, None, None, None, None) == suco.SUCO_E_STATE
     assert L.suco_query_bf16_debug(None, None, 0, 10, 0.1, 0.1, 0, None, None, None, None, None, None, None, None,
                                    None, None, None) == suco.SUCO_E_STATE
+
+
+def test_shape_limits_inval_vs_unsupported():
+    # admitted by the problem but past the kernels: SUCO_E_UNSUPPORTED; outside
+    # the problem: SUCO_E_INVAL; both before any device work
+    L = suco.lib()
+    out = C.c_void_p()
+    D = C.c_void_p(16)          # never dereferenced: the shape check comes first
+    assert L.suco_build(D, 1000, 512, 200, 8, None, None, C.byref(out)) == suco.SUCO_E_UNSUPPORTED
+    assert L.suco_build(D, 1000, 512, 300, 8, None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert L.suco_build(D, 1000, 64, 8, 129, None, None, C.byref(out)) == suco.SUCO_E_UNSUPPORTED
+    assert L.suco_build(D, 100, 64, 8, 101, None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert L.suco_build(D, 0, 64, 8, 1, None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert out.value is None
+
+
+def test_count_A_outside_the_unit_interval():
+    # a per-query alpha is not checked on the host; the documented reading:
+    # above 1, +inf and NaN activate everything, <= 0 activates one point
+    assert suco.count_A(float("nan"), 1000) == 1000
+    assert suco.count_A(float("inf"), 1000) == 1000
+    assert suco.count_A(2.0, 1000) == 1000
+    assert suco.count_A(0.0, 1000) == 1
+    assert suco.count_A(-0.5, 1000) == 1
+
+
+def test_index_load_rejects_bad_files_before_device_work(tmp_path):
+    import struct
+    L = suco.lib()
+    out = C.c_void_p()
+    missing = str(tmp_path / "missing.suco").encode()
+    assert L.suco_index_load(missing, None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert b"cannot open" in L.suco_last_error()
+    bad = tmp_path / "bad.suco"
+    bad.write_bytes(b"NOTANIDX" + bytes(56))
+    assert L.suco_index_load(str(bad).encode(), None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert b"not a SuCo index" in L.suco_last_error()
+    # a valid header whose file is too short for its shape
+    hdr = b"SUCOIDX1" + struct.pack("<IIqiiiiiiQ8x", 1, 64, 100, 8, 2, 4, 0, 0, 0, 0)
+    assert len(hdr) == 64
+    short = tmp_path / "short.suco"
+    short.write_bytes(hdr + bytes(100))
+    assert L.suco_index_load(str(short).encode(), None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert b"expected" in L.suco_last_error()
+    # a shape past the kernels in the header
+    hdr2 = b"SUCOIDX1" + struct.pack("<IIqiiiiiiQ8x", 1, 64, 1000, 512, 200, 4, 0, 0, 0, 0)
+    big = tmp_path / "big.suco"
+    big.write_bytes(hdr2)
+    assert L.suco_index_load(str(big).encode(), None, None, C.byref(out)) == suco.SUCO_E_UNSUPPORTED
+    assert L.suco_index_save(None, missing) == suco.SUCO_E_STATE
+    assert L.suco_index_load(None, None, None, C.byref(out)) == suco.SUCO_E_INVAL
+    assert out.value is None

@@ -73,6 +73,38 @@ def test_adam_step_matches_oracle(suco):
         assert np.allclose(after[k][big], ref.p[k][big], atol=1e-6, rtol=1e-6), k
 
 
+def test_adam_several_steps_match_oracle(suco):
+    # seven consecutive mini-batch steps over two epochs (a permuted order with
+    # batches of 32, then row order with batches of 48, 48 and 32): moment decay
+    # and bias correction past the first step, and the Adam state kept between
+    # epochs, against the FP64 oracle taking the same batches with one state
+    rng = np.random.default_rng(4)
+    n_in, m = 9, 128
+    net = suco.MLP(n_in, seed=6)
+    F = rng.normal(size=(m, n_in)).astype(np.float32)
+    t = rng.normal(size=m).astype(np.float32)
+    perm = rng.permutation(m).astype(np.int32)
+    ref = MLP64(split(net.params().astype(np.float64), n_in))
+    state = {}
+    batches = [perm[i:i + 32] for i in range(0, m, 32)] + [np.arange(i, min(m, i + 48)) for i in range(0, m, 48)]
+    gmin = {k: np.full_like(v, np.inf) for k, v in ref.p.items()}
+    gmax = {k: 0.0 for k in ref.p}
+    for rows in batches:
+        _, g = ref.loss_and_grad(F[rows], t[rows])
+        for k in PARAM_NAMES:
+            gmin[k] = np.minimum(gmin[k], np.abs(g[k]))
+            gmax[k] = max(gmax[k], float(np.abs(g[k]).max()))
+        ref.adam_step(g, state, lr=1e-3)
+    Fd, td = torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda()
+    net.train_epoch(Fd, td, batch=32, lr=1e-3, order=torch.from_numpy(perm).cuda())
+    net.train_epoch(Fd, td, batch=48, lr=1e-3)
+    after = split(net.params().astype(np.float64), n_in)
+    for k in PARAM_NAMES:
+        big = gmin[k] > 1e-4 * gmax[k]
+        assert big.mean() > 0.5, k
+        assert np.allclose(after[k][big], ref.p[k][big], atol=2e-6, rtol=1e-5), k
+
+
 def test_training_reduces_loss_on_a_learnable_target(suco):
     rng = np.random.default_rng(2)
     n_in, m = 17, 8192

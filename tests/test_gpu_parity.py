@@ -196,6 +196,74 @@ def test_per_query_alpha(suco):
     gix.free()
 
 
+def test_per_query_alpha_outside_the_unit_interval(suco):
+    """Device alphas are not checked on the host: above 1, +inf and NaN give the
+    results of alpha = 1, and values <= 0 those of one activated point."""
+    W = synth.Workload(1)
+    X, Q = W.data(6000), W.queries(6)
+    _, gix = make(X, 8, 12)
+    Qd = torch.from_numpy(Q).cuda()
+    odd = np.array([np.nan, np.inf, 2.0, 0.0, -1.0, -np.inf], np.float32)
+    ids, d = gix.query_alpha(Qd, 10, torch.from_numpy(odd).cuda(), 0.01)
+    top, _ = gix.query(Qd, 10, 1.0, 0.01)
+    one, _ = gix.query(Qd, 10, 1.0 / 6000, 0.01)
+    torch.cuda.synchronize()
+    ids, top, one = ids.cpu().numpy(), top.cpu().numpy(), one.cpu().numpy()
+    assert np.array_equal(ids[:3], top[:3])
+    assert np.array_equal(ids[3:], one[3:])
+    gix.free()
+
+
+def test_save_load_round_trip(suco, tmp_path):
+    """suco_index_save / suco_index_load: the loaded index exports the saved
+    centres and assignments (the oracle's, for an imported index), keeps its
+    flags, and answers every query bitwise as the saved one; a corrupted file
+    is refused by its checksum."""
+    W = synth.Workload(1)
+    X, Q = W.data(), W.queries(64)
+    oix, gix = make(X, 8, 16, iters=8)
+    Qd = torch.from_numpy(Q).cuda()
+    path = str(tmp_path / "mix.suco")
+    gix.save(path)
+    lix = suco.Index.load(path)
+    assert (lix.n, lix.d, lix.ns, lix.sqrt_k) == (gix.n, gix.d, gix.ns, gix.sqrt_k)
+    c0, a0 = gix.export()
+    c1, a1 = lix.export()
+    assert np.array_equal(c0.view(np.uint32), c1.view(np.uint32)) and np.array_equal(a0, a1)
+    assert np.array_equal(c1, oix.cent32) and np.array_equal(a1, oix.assign)
+    assert lix.flags() == gix.flags()
+    r0 = gix.query(Qd, 10, 0.05, 0.005)
+    r1 = lix.query(Qd, 10, 0.05, 0.005)
+    torch.cuda.synchronize()
+    assert np.array_equal(r0[0].cpu().numpy(), r1[0].cpu().numpy())
+    assert np.array_equal(r0[1].cpu().numpy(), r1[1].cpu().numpy())
+    lix.free()
+    # a GPU-built BF16 index on integer data keeps its byte rows and BF16 copy
+    Xi = synth.Workload(2).data(20_000)
+    bix = suco.Index.build(torch.from_numpy(Xi).cuda(), 8, 10, iters=3, flags=suco.BUILD_BF16)
+    bpath = str(tmp_path / "bf16.suco")
+    bix.save(bpath)
+    blix = suco.Index.load(bpath)
+    assert blix.flags() == bix.flags() == suco.INDEX_BYTE_ROWS | suco.INDEX_BF16
+    Qi = torch.from_numpy(synth.Workload(2).queries(32)).cuda()
+    s0 = bix.query_bf16(Qi, 10, 0.02, 0.01)
+    s1 = blix.query_bf16(Qi, 10, 0.02, 0.01)
+    torch.cuda.synchronize()
+    assert np.array_equal(s0["ids"].cpu().numpy(), s1["ids"].cpu().numpy())
+    assert np.array_equal(s0["dists"].cpu().numpy(), s1["dists"].cpu().numpy())
+    bix.free()
+    blix.free()
+    # one flipped byte in the data section
+    raw = bytearray(open(path, "rb").read())
+    raw[-100] ^= 0x40
+    bad = str(tmp_path / "bad.suco")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(suco.SucoError) as e:
+        suco.Index.load(bad)
+    assert e.value.code == suco.SUCO_E_INVAL and "checksum" in str(e.value)
+    gix.free()
+
+
 def test_empty_batch_and_errors(suco):
     W = synth.Workload(1)
     X = W.data(1000)
@@ -205,7 +273,10 @@ def test_empty_batch_and_errors(suco):
     assert ids.shape == (0, 5)
     Q = torch.zeros((2, 128), device="cuda")
     with pytest.raises(suco.SucoError) as e:
-        gix.query(Q, 65, 0.1, 0.1)
+        gix.query(Q, 65, 0.1, 0.1)                  # valid k, past the kernels' top-k lists
+    assert e.value.code == suco.SUCO_E_UNSUPPORTED
+    with pytest.raises(suco.SucoError) as e:
+        gix.query(Q, 1001, 0.1, 0.1)                # k > n
     assert e.value.code == suco.SUCO_E_INVAL
     with pytest.raises(suco.SucoError):
         gix.query(Q, 5, 0.0, 0.1)
@@ -258,10 +329,11 @@ def test_tie_level_left_out_of_later_tiles(suco):
 
 
 # ----------------------------------------------------------- full size --
-def test_sift_like_full_size_sampled(suco):
-    """SIFT-like n=1,000,000 d=128, N_s=8, sqrtK=50, 10,000 queries in one call
-    (the benchmark's launch configuration); 24 sampled queries are compared with
-    the oracle stage by stage."""
+@pytest.fixture(scope="module")
+def sift1m(suco):
+    """SIFT-like n=1,000,000 d=128 (integers 0..255), N_s=8, sqrtK=50: the
+    oracle's index, the same index on the GPU, 10,000 queries, and the exact
+    top-50 of the first 512 queries (FP64 products, exact for these integers)."""
     W = synth.Workload(2)
     print("case: sift_like n=1e6 generating", flush=True)
     X, Q = W.data(), W.queries()
@@ -269,26 +341,152 @@ def test_sift_like_full_size_sampled(suco):
     _, c32, asg, _ = oracle.build_index(X, 8, 50, iters=6, seed=1)
     oix = oracle.Index(X, 8, 50, c32, asg)
     gix = suco.Index.from_index(torch.from_numpy(X).cuda(), 8, 50, c32, asg)
-    print("case: sift_like GPU query, full batch", flush=True)
-    o = gix.query_debug(torch.from_numpy(Q).cuda(), 10, 0.03, 0.005, scores=False, cells=False)
+    del asg
+    print("case: sift_like exact top-50 of 512 queries", flush=True)
+    X64 = X.astype(np.float64)
+    xx = (X64 * X64).sum(axis=1)
+    gt = np.zeros((512, 50), np.int64)
+    for q0 in range(0, 512, 64):
+        q = Q[q0:q0 + 64].astype(np.float64)
+        d2 = xx[None, :] - 2.0 * (q @ X64.T) + (q * q).sum(axis=1)[:, None]
+        part = np.argpartition(d2, 100, axis=1)[:, :101]
+        for r in range(q.shape[0]):
+            cand = part[r][np.lexsort((part[r], d2[r, part[r]]))]
+            assert d2[r, cand[49]] < d2[r, cand[100]]     # no tie crosses the shortlist's end
+            gt[q0 + r] = cand[:50]
+    del X64
+    yield dict(X=X, Q=Q, oix=oix, gix=gix, gt=gt)
+    gix.free()
+
+
+def _full_and_sample(gix, Q, k, alpha, beta, alpha_q=None, seed=0):
+    Qd = torch.from_numpy(Q).cuda()
+    aq = torch.from_numpy(alpha_q).cuda() if alpha_q is not None else None
+    o = gix.query_debug(Qd, k, alpha, beta, alpha_q=aq, scores=False, cells=False)
     torch.cuda.synchronize()
     full = to_np(o)
     del o
-    sample = np.sort(np.random.default_rng(0).choice(Q.shape[0], 24, replace=False))
-    print("case: sift_like GPU query, sample with every stage exported", flush=True)
-    gs = debug(gix, Q[sample], 10, 0.03, 0.005)
+    sample = np.sort(np.random.default_rng(seed).choice(Q.shape[0], 24, replace=False))
+    gs = debug(gix, Q[sample], k, alpha, beta, alpha_q=None if alpha_q is None else alpha_q[sample])
     for key in ("ids", "dists", "cand", "ncells", "aprime", "feat"):
         assert np.array_equal(full[key][sample], gs[key]), key        # batching does not change results
-    print("case: sift_like oracle on the sample", flush=True)
+    return full, sample, gs
+
+
+def _full_batch_properties(full, n, k, alpha, beta):
+    B = oracle.count_B(beta, n, k)
+    A = np.array([oracle.count_A(float(a), n) for a in np.ravel(alpha)])
+    assert (full["aprime"] >= (A if A.size == 1 else A[:, None])).all()
+    assert (np.diff(full["cand"], axis=1) > 0).all() and full["cand"].shape[1] == B
+    assert ((full["cand"] >= 0) & (full["cand"] < n)).all()
+
+
+def test_sift_like_full_size_sampled(suco, sift1m):
+    """10,000 queries in one call at alpha=0.03 (the bisection path of the
+    activation step); 24 sampled queries compared with the oracle stage by stage."""
+    X, Q, oix, gix = sift1m["X"], sift1m["Q"], sift1m["oix"], sift1m["gix"]
+    print("case: sift_like alpha=0.03 full batch and sample", flush=True)
+    full, sample, gs = _full_and_sample(gix, Q, 10, 0.03, 0.005)
+    print("case: sift_like alpha=0.03 oracle on the sample", flush=True)
     st = check_query(oix, X, Q[sample], 10, 0.03, 0.005, gs)
     assert st["band_queries"] <= 3
     assert (gs["scores"].sum(axis=1, dtype=np.int64) == gs["aprime"].sum(axis=1)).all()
-    # properties that hold for every query of the batch
-    B = oracle.count_B(0.005, X.shape[0], 10)
-    assert (full["aprime"] >= oracle.count_A(0.03, X.shape[0])).all()
-    assert (np.diff(full["cand"], axis=1) > 0).all() and full["cand"].shape[1] == B
-    assert ((full["cand"] >= 0) & (full["cand"] < X.shape[0])).all()
-    gix.free()
+    _full_batch_properties(full, X.shape[0], 10, 0.03, 0.005)
+
+
+def _recall(ids, gt, k):
+    return float(np.mean([len(set(a[:k].tolist()) & set(b[:k].tolist())) / k for a, b in zip(ids, gt)]))
+
+
+def test_sift_like_operating_point(suco, sift1m):
+    """The benchmark's operating point: alpha=0.003 (Alg. 3's walk in the
+    activation step), beta=0.005, k=10, 10,000 queries in one call.  24 sampled
+    queries stage by stage; over the first 512 queries the GPU's recall@10 is
+    within 0.001 of the oracle's (both against the exact top-10)."""
+    X, Q, oix, gix, gt = sift1m["X"], sift1m["Q"], sift1m["oix"], sift1m["gix"], sift1m["gt"]
+    print("case: sift_like alpha=0.003 full batch and sample", flush=True)
+    full, sample, gs = _full_and_sample(gix, Q, 10, 0.003, 0.005, seed=1)
+    print("case: sift_like alpha=0.003 oracle on the sample", flush=True)
+    st = check_query(oix, X, Q[sample], 10, 0.003, 0.005, gs)
+    assert st["band_queries"] <= 3
+    _full_batch_properties(full, X.shape[0], 10, 0.003, 0.005)
+    print("case: sift_like alpha=0.003 oracle on 512 queries", flush=True)
+    ref = oix.query(Q[:512], 10, 0.003, 0.005)
+    r_gpu, r_ref = _recall(full["ids"][:512], gt, 10), _recall(ref["ids"], gt, 10)
+    print(f"recall@10 GPU {r_gpu:.5f} oracle {r_ref:.5f}", flush=True)
+    assert abs(r_gpu - r_ref) <= 0.001
+
+
+def test_sift_like_learned_range_alphas(suco, sift1m):
+    """Per-query alphas drawn log-uniformly in [0.0005, 0.01] (the range the
+    learned budget uses; both activation paths occur), 10,000 queries in one
+    call: 24 sampled queries stage by stage against the oracle on the same
+    alphas, and the recall rule over the first 512 queries."""
+    X, Q, oix, gix, gt = sift1m["X"], sift1m["Q"], sift1m["oix"], sift1m["gix"], sift1m["gt"]
+    rng = np.random.default_rng(7)
+    aq = np.exp(rng.uniform(np.log(0.0005), np.log(0.01), Q.shape[0])).astype(np.float32)
+    print("case: sift_like per-query alpha full batch and sample", flush=True)
+    full, sample, gs = _full_and_sample(gix, Q, 10, 0.0, 0.005, alpha_q=aq, seed=2)
+    print("case: sift_like per-query alpha oracle on the sample", flush=True)
+    st = check_query(oix, X, Q[sample], 10, aq[sample].astype(np.float64), 0.005, gs)
+    assert st["band_queries"] <= 3
+    _full_batch_properties(full, X.shape[0], 10, aq.astype(np.float64), 0.005)
+    ref = oix.query(Q[:512], 10, aq[:512].astype(np.float64), 0.005)
+    r_gpu, r_ref = _recall(full["ids"][:512], gt, 10), _recall(ref["ids"], gt, 10)
+    print(f"recall@10 GPU {r_gpu:.5f} oracle {r_ref:.5f}", flush=True)
+    assert abs(r_gpu - r_ref) <= 0.001
+
+
+def test_sift_like_k50(suco, sift1m):
+    """k=50 (the other k of the SIFT-like workload) at alpha=0.01: sampled
+    queries stage by stage and the recall@50 rule over the first 512 queries."""
+    X, Q, oix, gix, gt = sift1m["X"], sift1m["Q"], sift1m["oix"], sift1m["gix"], sift1m["gt"]
+    print("case: sift_like k=50 alpha=0.01 full batch and sample", flush=True)
+    full, sample, gs = _full_and_sample(gix, Q, 50, 0.01, 0.005, seed=3)
+    print("case: sift_like k=50 oracle on the sample", flush=True)
+    st = check_query(oix, X, Q[sample], 50, 0.01, 0.005, gs)
+    assert st["band_queries"] <= 3
+    _full_batch_properties(full, X.shape[0], 50, 0.01, 0.005)
+    ref = oix.query(Q[:512], 50, 0.01, 0.005)
+    r_gpu, r_ref = _recall(full["ids"][:512], gt, 50), _recall(ref["ids"], gt, 50)
+    print(f"recall@50 GPU {r_gpu:.5f} oracle {r_ref:.5f}", flush=True)
+    assert abs(r_gpu - r_ref) <= 0.001
+
+
+def test_sift_like_batcher_with_model(suco, sift1m):
+    """A batcher with a network attached, fed the 10,000 queries as uneven
+    batches (1..4096): bitwise equal to suco_query_alpha on the alphas the
+    network gives, and a sample of those queries matches the oracle."""
+    X, Q, oix, gix = sift1m["X"], sift1m["Q"], sift1m["oix"], sift1m["gix"]
+    Qd = torch.from_numpy(Q).cuda()
+    net = suco.MLP(17, seed=21)
+    F = suco.query_features(gix, Qd)
+    net.set_norm(F.mean(dim=0).cpu().numpy(), F.std(dim=0).cpu().numpy())
+    amin, amax, scale = 0.0005, 0.01, 0.003
+    print("case: sift_like batcher with model, uneven stream", flush=True)
+    b = suco.Batcher(gix, 4096, 10, 0.005)
+    b.set_model(net, scale, amin, amax)
+    out_ids = torch.empty((Q.shape[0], 10), dtype=torch.int32, device="cuda")
+    out_d = torch.empty((Q.shape[0], 10), dtype=torch.float32, device="cuda")
+    start = 0
+    for sz in synth.Workload(2).batch_sizes(Q.shape[0]):
+        b.query(Qd[start:start + sz], out=(out_ids[start:start + sz], out_d[start:start + sz]))
+        start += sz
+    ids, d, au = suco.query_learned(gix, net, Qd, 10, 0.005, scale, amin, amax)
+    p_ids, p_d = gix.query_alpha(Qd, 10, au, 0.005)
+    torch.cuda.synchronize()
+    b.free()
+    assert np.array_equal(out_ids.cpu().numpy(), p_ids.cpu().numpy())
+    assert np.array_equal(out_d.cpu().numpy(), p_d.cpu().numpy())
+    assert np.array_equal(ids.cpu().numpy(), p_ids.cpu().numpy())
+    aq = au.cpu().numpy()
+    assert (aq >= amin).all() and (aq <= amax).all() and len(np.unique(aq)) > 100
+    sample = np.sort(np.random.default_rng(4).choice(Q.shape[0], 12, replace=False))
+    gs = debug(gix, Q[sample], 10, 0.0, 0.005, alpha_q=aq[sample])
+    assert np.array_equal(gs["ids"], p_ids.cpu().numpy()[sample])
+    print("case: sift_like batcher with model, oracle on the sample", flush=True)
+    st = check_query(oix, X, Q[sample], 10, aq[sample].astype(np.float64), 0.005, gs)
+    assert st["band_queries"] <= 2
 
 
 def test_byte_rows_equal_fp32_rows(suco):

@@ -500,3 +500,114 @@ def test_theorem1_higher_score_means_closer_with_probability():
         frac = (higher & closer).sum() / higher.sum()
         assert frac >= bound, (qi, frac)
         assert frac > 0.5   # better than chance: inverted or shuffled scores fail here
+
+
+def test_adam_steps_closed_form_over_three_steps():
+    # Kingma & Ba, Algorithm 1, for a gradient sequence whose moments have closed
+    # forms: g, then 0, then 0.  After step t the bias-corrected moments are
+    #   t=1: m^ = g,                           v^ = g^2
+    #   t=2: m^ = b1 (1-b1) g / (1-b1^2),      v^ = b2 (1-b2) g^2 / (1-b2^2)
+    #   t=3: m^ = b1^2 (1-b1) g / (1-b1^3),    v^ = b2^2 (1-b2) g^2 / (1-b2^3)
+    # A wrong decay, a missing or misplaced bias correction, or eps inside the
+    # root changes the steps of t = 2 and 3 (t = 1 alone cannot tell them apart).
+    from oracle.mlp import MLP64, init_params
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-3
+    net = MLP64(init_params(3, 4, seed=2))
+    start = {k: v.copy() for k, v in net.p.items()}
+    rng = np.random.default_rng(5)
+    g = {k: rng.choice([-1.0, 1.0], size=v.shape) * (0.1 + rng.random(v.shape)) for k, v in net.p.items()}
+    zero = {k: np.zeros_like(v) for k, v in net.p.items()}
+    state = {}
+    moved = {k: np.zeros_like(v) for k, v in net.p.items()}
+    for t, gt in enumerate([g, zero, zero], start=1):
+        before = {k: v.copy() for k, v in net.p.items()}
+        net.adam_step(gt, state, lr=lr, b1=b1, b2=b2, eps=eps)
+        for k in net.p:
+            a = np.abs(g[k])
+            mh = g[k] * b1 ** (t - 1) * (1 - b1) / (1 - b1 ** t)
+            vh = a * a * b2 ** (t - 1) * (1 - b2) / (1 - b2 ** t)
+            step = lr * mh / (np.sqrt(vh) + eps)
+            assert np.allclose(before[k] - net.p[k], step, rtol=1e-9, atol=0), (t, k)
+            moved[k] += step
+    for k in net.p:
+        assert np.allclose(start[k] - net.p[k], moved[k], rtol=1e-9, atol=0)
+    # constant gradient: m^ = g and v^ = g^2 at every step, so t steps move lr*t*g/(|g|+eps)
+    net2 = MLP64(init_params(3, 4, seed=2))
+    st2 = {}
+    for _ in range(4):
+        net2.adam_step(g, st2, lr=lr)
+    for k in net2.p:
+        assert np.allclose(start[k] - net2.p[k], 4 * lr * g[k] / (np.abs(g[k]) + eps), rtol=1e-9, atol=0)
+
+
+def _tiny_net_for_rounding_points():
+    """A 1 -> 3 -> 3 -> 1 network whose BF16 inference value follows by hand.
+
+    F = 1 + 2^-10 (an FP32 value; BF16 rounds it to 1).  Near 9 the BF16 spacing
+    is 2^-4 and GELU(z) = z exactly in FP64 (1 - Phi(9) is far below 2^-53).
+      unit 0: z1 = 2^-5 x + 9      -> 9 + 2^-5 at x = 1, the tie between 9 and
+              9.0625, which rounds to the even 9; the unrounded x gives 9.0625
+      unit 1: z1 = 2^-6 x + 9      -> 9.015625, rounded to 9
+      unit 2: z1 = 0               -> 0
+      layer 2 (h1 -> z2): z2 = [h1_0, h1_1 + 3*2^-7, h1_1 + 2^-7]
+              with h1 = [9, 9, 0]: [9, 9.0234375, 9.0078125], all rounded to 9;
+              an unrounded h1_1 = 9.015625 would give 9.0390625 -> 9.0625
+      output: y = (1 + 2^-9) h2_0 + 2 h2_1 + 4 h2_2 + 0.5, where BF16 rounds
+              1 + 2^-9 to 1, so y = 9 + 18 + 36 + 0.5 = 63.5.
+    Each left-out rounding gives another value: the input (63.5625), h1
+    (63.625), h2 (63.578125), the weights (63.517578125)."""
+    from oracle.mlp import MLP64
+    p = dict(W1=np.array([[2.0 ** -5], [2.0 ** -6], [0.0]]), b1=np.array([9.0, 9.0, 0.0]),
+             W2=np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 1.0, 0]]), b2=np.array([0.0, 3 * 2.0 ** -7, 2.0 ** -7]),
+             W3=np.array([[1.0 + 2.0 ** -9, 2.0, 4.0]]), b3=np.array([0.5]))
+    return MLP64(p), np.array([[1.0 + 2.0 ** -10]], np.float32)
+
+
+def test_forward_bf16_rounding_points_by_hand():
+    net, F = _tiny_net_for_rounding_points()
+    assert net.forward_bf16(F)[0] == 63.5
+    # the FP64 forward keeps every value: y = (1 + 2^-9) z0 + 2 (z1 + 3*2^-7) + 4 (z1 + 2^-7) + 0.5
+    x = 1.0 + 2.0 ** -10
+    z0, z1 = 9.0 + 2.0 ** -5 * x, 9.0 + 2.0 ** -6 * x
+    want = (1 + 2.0 ** -9) * z0 + 2 * (z1 + 3 * 2.0 ** -7) + 4 * (z1 + 2.0 ** -7) + 0.5
+    assert abs(net.forward(F)[0] - want) <= 1e-12
+
+
+def test_forward_bf16_within_rounding_bound_of_forward():
+    # Every BF16 rounding (to 8 significant bits) changes a value by at most
+    # u = 2^-8 of it, and GELU is Lipschitz with constant L = Phi(sqrt2) + sqrt2 phi(sqrt2)
+    # < 1.13.  Propagating: with x^ = x + dx, W^ = W + dW (|dW| <= u|W|):
+    #   |z^ - z| <= |W| |dx| + u |W| |x^| + u |b|
+    #   |h^ - h| <= L |z^ - z| + u |GELU(z^)|
+    # layer by layer, then |y^ - y| <= |W3| |dh2| + u |W3| |h2^| + u |b3|.
+    # The bound holds for every row; a dropped bias or layer, a transposed
+    # weight or a rounding at the wrong place exceeds it on random nets.
+    from oracle.mlp import MLP64, init_params, gelu
+    u, L = 2.0 ** -8, 1.13
+    rng = np.random.default_rng(9)
+    for seed in range(4):
+        p = init_params(7, 16, seed=seed)
+        for k in p:
+            p[k] = (p[k] + 0.2 * rng.normal(size=p[k].shape)).astype(np.float32)
+        mu = rng.normal(size=7).astype(np.float32)
+        sd = (0.5 + rng.random(7)).astype(np.float32)
+        net = MLP64(p, mu=mu, sigma=sd)
+        F = (rng.normal(size=(300, 7)) * sd + mu).astype(np.float32)
+        y = net.forward(F)
+        yb = net.forward_bf16(F)
+        P = {k: np.abs(np.asarray(v, np.float64)) for k, v in net.p.items()}
+        x = net.standardise(F)
+        dx = np.abs(x) * (u + 2.0 ** -23) + 2.0 ** -23        # FP32 standardisation, then BF16
+        xh = np.abs(x) + dx
+        dz1 = dx @ P["W1"].T + u * xh @ P["W1"].T + u * P["b1"]
+        z1 = x @ net.p["W1"].T + net.p["b1"]
+        dh1 = L * dz1 + u * (np.abs(gelu(z1)) + L * dz1) + 2.0 ** -23 * (np.abs(gelu(z1)) + L * dz1)
+        h1h = np.abs(gelu(z1)) + dh1
+        dz2 = dh1 @ P["W2"].T + u * h1h @ P["W2"].T + u * P["b2"]
+        z2 = gelu(z1) @ net.p["W2"].T + net.p["b2"]
+        dh2 = L * dz2 + u * (np.abs(gelu(z2)) + L * dz2) + 2.0 ** -23 * (np.abs(gelu(z2)) + L * dz2)
+        h2h = np.abs(gelu(z2)) + dh2
+        dy = (dh2 @ P["W3"].T + u * h2h @ P["W3"].T + u * P["b3"])[:, 0]
+        assert (np.abs(yb - y) <= dy * (1 + 1e-9)).all(), seed
+        # and the rounding is not a no-op: the two differ on most rows
+        assert (yb != y).mean() > 0.9
