@@ -175,6 +175,21 @@ SUCO_API int suco_index_load(const char *path, const suco_build_params *p, void 
 SUCO_API int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
                double beta, int32_t *ids, float *dists, void *stream);
 
+/* suco_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it): the same
+ * kernels and the same results, bitwise, with the workspace taken from a
+ * fixed 64 MiB device array inside the library (each device the library runs
+ * on holds its own copy until the process ends) instead of an allocation.
+ * The call allocates nothing and records no events.  The batch is split into
+ * passes whose workspace fits the array (about 2 bytes per point and query,
+ * 4 bytes per candidate); SUCO_E_UNSUPPORTED when even one query does not
+ * fit (n above about 30 million at beta = 0.005).  Every call on a device
+ * shares that device's array and needs no state from an earlier call: calls
+ * that overlap on one device (several streams, several host threads) race,
+ * so the caller must order them.  Arguments as in suco_query. */
+SUCO_API int suco_query_noalloc(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
+                                double beta, int32_t *ids, float *dists, void *stream);
+
 /* As suco_query with one collision ratio per query: alpha_q device [nq]
  * float32, each meant to lie in (0, 1]; query j activates
  * A_j = max(1, ceil(alpha_q[j]*n)) points per subspace (the value is widened

@@ -27,6 +27,7 @@ EXPORTED = (
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
     "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags", "suco_index_save", "suco_index_load",
+    "suco_query_noalloc",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order")
@@ -78,6 +79,7 @@ def lib():
         L.suco_index_load.argtypes = [C.c_char_p, C.POINTER(BuildParams), P, C.POINTER(P)]
         L.suco_query.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
         L.suco_query_alpha.argtypes = [P, P, i64, i32, P, dbl, P, P, P]
+        L.suco_query_noalloc.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
         L.suco_query_debug.argtypes = [P, P, i64, i32, P, dbl, dbl, P, P, P, P, P, P, P, P, P]
         L.suco_collide_select.argtypes = [P, i64, P, P, i32, dbl, P, P, P]
         L.suco_rerank.argtypes = [P, P, i64, P, i64, i32, P, P, P]
@@ -250,6 +252,16 @@ class Index:
         ids, dists = out if out is not None else self._out(nq, k)
         _check(lib().suco_query(self._h, pq, nq, k, float(alpha), float(beta), _dev(ids, torch.int32),
                                 _dev(dists, torch.float32), _stream(stream)))
+        return ids, dists
+
+    def query_noalloc(self, Q, k: int, alpha: float, beta: float, out=None, stream=None):
+        """suco_query with the library's fixed scratch as workspace (see suco_query_noalloc)."""
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        ids, dists = out if out is not None else self._out(nq, k)
+        _check(lib().suco_query_noalloc(self._h, pq, nq, k, float(alpha), float(beta), _dev(ids, torch.int32),
+                                        _dev(dists, torch.float32), _stream(stream)))
         return ids, dists
 
     def query_alpha(self, Q, k: int, alpha_q, beta: float, out=None, stream=None):

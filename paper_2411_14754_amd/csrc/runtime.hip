@@ -480,8 +480,17 @@ struct Bf16Opts {
     float *cdist = nullptr;
 };
 
+// Workspace given by the caller instead of the index's arena (the entry point
+// that allocates nothing): passes are sized to fit `bytes`, no timing events
+// are recorded and the index's arena bookkeeping is left alone.
+struct FixedWork {
+    char *base;
+    size_t bytes;
+};
+
 int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, const float *alpha_q, double alpha,
-              double beta, int32_t *ids, float *dists, const DebugOut *dbg, const Bf16Opts *bo, hipStream_t st) {
+              double beta, int32_t *ids, float *dists, const DebugOut *dbg, const Bf16Opts *bo, hipStream_t st,
+              const FixedWork *fx = nullptr) {
     int rc = check_query(cix, Q, nq, k, beta, ids, dists);
     if (rc) return rc;
     if (!alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
@@ -496,9 +505,25 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
     if ((rc = rerank_cfg(ix->d, B, &c32))) return rc;
     if (bo && (rc = rerank_bf16_cfg(ix->d, B, &c16))) return rc;
     const int parts = std::max(c32.parts, c16.parts);
-    std::lock_guard<std::mutex> lock(ix->mu);
+    std::unique_lock<std::mutex> lock(ix->mu, std::defer_lock);
+    if (!fx) lock.lock();
     DeviceGuard dg(ix->device);
-    const size_t C = (size_t)pass_size(nq, ix->chunk);
+    int64_t cap = ix->chunk;
+    if (fx) {
+        // the largest pass whose workspace fits the fixed buffer
+        auto need = [&](int64_t c) { size_t b = 0; carve(ix, nullptr, (size_t)c, B, k, parts, false, &b); return b; };
+        int64_t lo = 0, hi = std::min<int64_t>(nq, ix->chunk);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (need(mid) <= fx->bytes) lo = mid; else hi = mid - 1;
+        }
+        if (lo == 0)
+            return fail(SUCO_E_UNSUPPORTED, "one query needs " + std::to_string(need(1)) +
+                                                " bytes of workspace; the fixed scratch holds " +
+                                                std::to_string(fx->bytes));
+        cap = lo;
+    }
+    const size_t C = (size_t)pass_size(nq, cap);
     const int nh = 2 * ix->ns;
     const bool dense = dbg && dbg->scores;
     // BF16 buffers follow the common workspace
@@ -513,14 +538,20 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         nsv = cv.take<int32_t>(C);
         return cv.off;
     };
-    size_t bytes = 0;
-    carve(ix, nullptr, C, B, k, parts, dense, &bytes);
-    if (bo) bytes = extra(nullptr, bytes);
-    if ((rc = ensure_arena(ix, bytes))) return rc;
-    if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
+    char *base = fx ? fx->base : nullptr;
+    if (!fx) {
+        size_t bytes = 0;
+        carve(ix, nullptr, C, B, k, parts, dense, &bytes);
+        if (bo) bytes = extra(nullptr, bytes);
+        if ((rc = ensure_arena(ix, bytes))) return rc;
+        if (ix->pending) HIPCHECK(hipStreamWaitEvent(st, ix->done, 0));
+        base = ix->arena;
+    }
     size_t wbytes = 0;
-    Work w = carve(ix, ix->arena, C, B, k, parts, dense, &wbytes);
-    if (bo) extra(ix->arena, wbytes);
+    Work w = carve(ix, base, C, B, k, parts, dense, &wbytes);
+    if (bo) extra(base, wbytes);
+    // every launch of a pass, with timing events when profiling is on
+    auto T = [&](int stage, auto &&fn) { return fx ? fn() : timed(ix, stage, st, fn); };
     const IndexView v = ix->view();
     for (int64_t c0 = 0; c0 < nq; c0 += (int64_t)C) {
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
@@ -541,20 +572,20 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
             CentreBf16Pass cp{};
             cp.Q = qp.Q; cp.nq = cn; cp.d = ix->d; cp.sk = ix->sk; cp.nh = nh; cp.halves = ix->halves;
             cp.centb = ix->centb; cp.cnorm2 = ix->cnorm2; cp.D = D;
-            HIPCHECK(timed(ix, kCentresBf16, st, [&] { return launch(plan_centre_dists_bf16(cp), &cp, st); }));
+            HIPCHECK(T(kCentresBf16, [&] { return launch(plan_centre_dists_bf16(cp), &cp, st); }));
             qp.Dext = D;
             if (bo->cdist)
                 HIPCHECK(hipMemcpyAsync(bo->cdist + c0 * nh * ix->sk, D, sizeof(float) * cn * nh * ix->sk,
                                         hipMemcpyDeviceToDevice, st));
         }
-        HIPCHECK(timed(ix, kActivate, st, [&] { return launch_activate(qp, st); }));
+        HIPCHECK(T(kActivate, [&] { return launch_activate(qp, st); }));
         if (cn <= kOrderWide) {
             qp.order_out = w.order;
-            HIPCHECK(timed(ix, kOrder, st, [&] { return launch(plan_order(qp), &qp, st); }));
+            HIPCHECK(T(kOrder, [&] { return launch(plan_order(qp), &qp, st); }));
             qp.order = w.order;
         }
-        HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
-        HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
+        HIPCHECK(T(kCollide, [&] { return launch_collide(qp, st); }));
+        HIPCHECK(T(kSelect, [&] { return launch_select(qp, st); }));
         RerankPass rp{};
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
         rp.parts = c32.parts; rp.rows_per_part = c32.rpp; rp.G = c32.G; rp.U = c32.U;
@@ -564,13 +595,13 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
             bp.Xb = ix->Xb; bp.xerr = ix->xerr; bp.Q = qp.Q; bp.cand = w.cand; bp.B = B; bp.n = ix->n;
             bp.d = ix->d; bp.k = k; bp.nq = cn; bp.parts = c16.parts; bp.rows_per_part = c16.rpp; bp.G = c16.G;
             bp.U = c16.U; bp.part_keys = w.part_keys; bp.lo = lo; bp.surv = surv; bp.nsurv = nsv;
-            HIPCHECK(timed(ix, kRerankBf16, st, [&] { return launch(plan_rerank_bf16(bp, 0), &bp, st); }));
-            HIPCHECK(timed(ix, kSurvivors, st, [&] { return launch(plan_survivors(bp), &bp, st); }));
+            HIPCHECK(T(kRerankBf16, [&] { return launch(plan_rerank_bf16(bp, 0), &bp, st); }));
+            HIPCHECK(T(kSurvivors, [&] { return launch(plan_survivors(bp), &bp, st); }));
             // the FP32 re-rank of the survivors: one part per query
             rp.cand = surv; rp.rows_dev = nsv; rp.parts = 1; rp.rows_per_part = B;
         }
-        HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));
-        HIPCHECK(timed(ix, kMerge, st, [&] { return launch_merge(rp, st); }));
+        HIPCHECK(T(kRerank, [&] { return launch_rerank(rp, st); }));
+        HIPCHECK(T(kMerge, [&] { return launch_merge(rp, st); }));
         if (bo && bo->nsurv)
             HIPCHECK(hipMemcpyAsync(bo->nsurv + c0, nsv, sizeof(int32_t) * cn, hipMemcpyDeviceToDevice, st));
         if (bo && bo->relerr) {
@@ -599,11 +630,43 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
                                           hipMemcpyDeviceToDevice, st));
         }
     }
-    HIPCHECK(hipEventRecord(ix->done, st));
-    ix->pending = true;
+    if (!fx) {
+        HIPCHECK(hipEventRecord(ix->done, st));
+        ix->pending = true;
+    }
     return SUCO_OK;
 }
 
+}  // namespace
+
+// -------------------------------------------------------------- no-alloc --
+// Workspace of suco_query_noalloc: a fixed array in the library's device code
+// object.  Every device the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns with that device current (the array's name is a
+// host-side stand-in, not a device address).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[kScratchDevices] = {};
+
+// The scratch array's address on the current device, looked up once per device.
+int scratch_on(int dev, char **out) {
+    if (dev < 0 || dev >= kScratchDevices) return fail(SUCO_E_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SUCO_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch[dev];
+    return SUCO_OK;
+}
 }  // namespace
 
 // ================================================================== ABI ==
@@ -719,6 +782,21 @@ int suco_index_free(suco_index *ix) {
 int suco_query(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
                int32_t *ids, float *dists, void *stream) {
     return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int suco_query_noalloc(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+                       int32_t *ids, float *dists, void *stream) {
+    int rc = check_query(ix, Q, nq, k, beta, ids, dists);
+    if (rc) return rc;
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (nq == 0) return SUCO_OK;
+    char *base = nullptr;
+    {
+        DeviceGuard dg(ix->device);
+        if ((rc = scratch_on(ix->device, &base))) return rc;
+    }
+    FixedWork fx{base, kScratchBytes};
+    return run_query(ix, Q, nq, k, nullptr, alpha, beta, ids, dists, nullptr, nullptr, (hipStream_t)stream, &fx);
 }
 
 int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, int32_t k, const float *alpha_q,
