@@ -76,6 +76,10 @@ typedef struct suco_build_params {
  * per-row bound of its rounding error (4*n bytes) and BF16 centres.  Needs d
  * to be a multiple of 8. */
 #define SUCO_BUILD_BF16 2
+/* Leave out the sparse collision step and its cell-major copy of the IMI
+ * (4*n*n_s bytes): every query counts SC-scores tile by tile over the whole
+ * id range.  The results are the same either way. */
+#define SUCO_BUILD_NO_SPARSE 4
 
 SUCO_API int suco_version(void);
 SUCO_API const char *suco_last_error(void);
@@ -361,12 +365,14 @@ SUCO_API int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, f
  * microseconds per launch).  suco_profile_read waits for the recorded work
  * and returns, per step, the summed milliseconds and launch counts since the
  * last read, then resets.  Steps, in order: 0 activate (centre distances and
- * Dynamic Activation), 1 collide (SC-score counting), 2 select (top-B by
- * score), 3 rerank (candidate distances, partial top-k), 4 merge (final top-k),
- * 5 BF16 centre distances, 6 BF16 first re-rank pass, 7 survivors, 8 ordering
- * of a pass's queries by activated points (heaviest first) for step 3.
- *  ms        host double [9]
- *  launches  host int64 [9] */
+ * Dynamic Activation), 1 collide (SC-score counting over id tiles), 2 select
+ * (top-B by score), 3 rerank (candidate distances, partial top-k), 4 merge
+ * (final top-k), 5 BF16 centre distances, 6 BF16 first re-rank pass,
+ * 7 survivors, 8 ordering of a pass's queries by activated points (heaviest
+ * first), 9 sparse collide (SC-scores and top-B of the queries whose
+ * activated points are few next to n, per bucket of 4096 ids).
+ *  ms        host double [10]
+ *  launches  host int64 [10] */
 SUCO_API int suco_profile(suco_index *ix, int enable);
 SUCO_API int suco_profile_read(suco_index *ix, double *ms, int64_t *launches);
 

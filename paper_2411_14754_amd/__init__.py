@@ -30,7 +30,8 @@ EXPORTED = (
     "suco_query_noalloc",
 )
 
-STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order")
+STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order",
+          "collide_sparse")
 
 
 class SucoError(RuntimeError):
@@ -46,6 +47,7 @@ class BuildParams(C.Structure):
 
 BUILD_NO_BYTE_ROWS = 1
 BUILD_BF16 = 2
+BUILD_NO_SPARSE = 4
 BF16_S1 = 1
 INDEX_BYTE_ROWS, INDEX_BF16 = 1, 2
 

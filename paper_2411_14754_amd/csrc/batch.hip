@@ -106,7 +106,7 @@ struct suco_batcher {
     Mail *mail = nullptr;
     int *nq_dev = nullptr;
     uint16_t *cells = nullptr, *lvl = nullptr;
-    int32_t *ncells = nullptr, *aprime = nullptr, *order = nullptr;
+    int32_t *ncells = nullptr, *aprime = nullptr, *order = nullptr, *route = nullptr;
     uint32_t *hist = nullptr, *cand = nullptr;
     uint64_t *part_keys = nullptr;
     std::map<int, Bucket> buckets;
@@ -128,11 +128,12 @@ struct suco_batcher {
         Fs = nullptr;
         for (void *p : {(void *)Qs, (void *)alphas, (void *)ids_s, (void *)dists_s, (void *)mail, (void *)nq_dev,
                         (void *)cells, (void *)lvl, (void *)ncells, (void *)aprime, (void *)hist, (void *)cand,
-                        (void *)part_keys, (void *)order})
+                        (void *)part_keys, (void *)order, (void *)route})
             if (p) (void)hipFree(p);
         Qs = nullptr; alphas = nullptr; ids_s = nullptr; dists_s = nullptr; mail = nullptr; nq_dev = nullptr;
         cells = nullptr; lvl = nullptr; ncells = nullptr; aprime = nullptr; hist = nullptr; cand = nullptr;
         order = nullptr;
+        route = nullptr;
         part_keys = nullptr;
         magic = 0;
     }
@@ -241,6 +242,8 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         qp.cells = b->cells; qp.ncells = b->ncells; qp.aprime = b->aprime; qp.hist = b->hist; qp.lvl = b->lvl;
         if (C <= kOrderWide) { qp.order_out = b->order; qp.order = b->order; }
         qp.cand = b->cand;
+        qp.route = ix->sp_cap ? b->route : nullptr;
+        qp.sp_cap = ix->sp_cap;
         RerankPass &rp = bk->rps[c];
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = b->cand; rp.B = b->B; rp.n = ix->n; rp.d = ix->d; rp.k = b->k;
         rp.nq = C; rp.parts = parts; rp.nq_dev = b->nq_dev; rp.q_base = c * b->C; rp.rows_per_part = t.rpp;
@@ -255,6 +258,10 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         if (qp.order) {
             const Launch Lo = plan_order(qp);
             if ((e = add_node(bk->graph, &prev, Lo.func, Lo.grid, Lo.block, Lo.lds, aq)) != hipSuccess) return e;
+        }
+        if (qp.route) {
+            const Launch Lp = plan_collide_sparse(qp, 0);
+            if ((e = add_node(bk->graph, &prev, Lp.func, Lp.grid, Lp.block, Lp.lds, aq)) != hipSuccess) return e;
         }
         if ((e = add_node(bk->graph, &prev, Lc.func, Lc.grid, Lc.block, Lc.lds, aq)) != hipSuccess) return e;
         if ((e = add_node(bk->graph, &prev, Ls.func, Ls.grid, Ls.block, Ls.lds, aq)) != hipSuccess) return e;
@@ -337,7 +344,7 @@ int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, doub
         (rc = dev_alloc(&b->mail, 1)) || (rc = dev_alloc(&b->nq_dev, 1)) ||
         (rc = dev_alloc(&b->cells, C * ix->ns * ix->K)) || (rc = dev_alloc(&b->ncells, C * ix->ns)) ||
         (rc = dev_alloc(&b->aprime, C * ix->ns)) || (rc = dev_alloc(&b->hist, C * ix->P * (ix->ns + 2))) ||
-        (rc = dev_alloc(&b->order, C)) ||
+        (rc = dev_alloc(&b->order, C)) || (rc = dev_alloc(&b->route, C)) ||
         (rc = dev_alloc(&b->lvl, C * (size_t)ix->P * ix->TILE)) || (rc = dev_alloc(&b->cand, C * (size_t)b->B)) ||
         (rc = dev_alloc(&b->part_keys, C * (size_t)b->parts_max * k))) {
         b->release();

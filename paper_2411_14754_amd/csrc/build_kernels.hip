@@ -223,6 +223,35 @@ __global__ __launch_bounds__(64) void k_imi_build(const uint8_t *assign, int64_t
     }
 }
 
+// Cell-major copy of the IMI for the sparse collision step: the ids of cell c
+// of subspace i, ascending, at ids32[i*n + coffs[i*(K+1) + c] ...].  The
+// tile-major runs of a cell are concatenated in tile order (tiles hold
+// consecutive id ranges, each run ascending), one wave per (cell, subspace).
+__global__ __launch_bounds__(64) void k_cell_major(const uint32_t *toffs, const uint16_t *ids16,
+                                                    const uint32_t *csize, int64_t n, int K, int P, int TILE,
+                                                    uint32_t *coffs, uint32_t *ids32) {
+    const int c = blockIdx.x, i = blockIdx.y, lane = threadIdx.x;
+    // start of cell c: the sizes of the cells before it (lanes sum strided parts)
+    uint32_t part = 0;
+    for (int c2 = lane; c2 < c; c2 += kWave) part += csize[(int64_t)i * K + c2];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    uint32_t at = part;
+    if (lane == 0) {
+        coffs[(int64_t)i * (K + 1) + c] = at;
+        if (c == K - 1) coffs[(int64_t)i * (K + 1) + K] = at + csize[(int64_t)i * K + c];
+    }
+    uint32_t *dst = ids32 + (int64_t)i * n;
+    for (int p = 0; p < P; ++p) {
+        const uint32_t *to = toffs + ((int64_t)i * P + p) * (K + 1);
+        const uint32_t s = to[c], e = to[c + 1];
+        const uint16_t *src = ids16 + (int64_t)i * P * TILE;
+        const uint32_t t0 = (uint32_t)p * (uint32_t)TILE;
+        for (uint32_t m = s + lane; m < e; m += kWave) dst[at + (m - s)] = t0 + src[m];
+        at += e - s;
+    }
+}
+
 // ============================================================= launchers ==
 hipError_t launch_gather_rows(const float *X, int d, const int64_t *ids, int m, int dim0, int w,
                               float *out, hipStream_t s) {
@@ -260,6 +289,13 @@ hipError_t launch_km_update(const KmeansPass &k, hipStream_t s) {
 
 hipError_t launch_cent_to_f32(const double *c64, float *c32, int64_t m, hipStream_t s) {
     hipLaunchKernelGGL(k_cent_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, c64, c32, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_major(const uint32_t *toffs, const uint16_t *ids16, const uint32_t *csize, int64_t n,
+                             int ns, int K, int P, int TILE, uint32_t *coffs, uint32_t *ids32, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_major, dim3((unsigned)K, (unsigned)ns), dim3(kWave), 0, s, toffs, ids16, csize, n, K, P,
+                       TILE, coffs, ids32);
     return hipGetLastError();
 }
 

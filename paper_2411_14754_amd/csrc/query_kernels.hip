@@ -874,6 +874,7 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int rq = item / S, g = item - rq * S;
         const int ql = a.order ? a.order[rq] : rq;   // heaviest queries first
+        if (a.route != nullptr && a.route[ql] == 0) continue;   // counted by the sparse step
         // this thread's subspace: activated cell count and its cell of the first batch
         const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
         const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
@@ -889,6 +890,351 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
             collide_tiles_pipelined<NT>(a, L, sc, ql, g, my_nc, c_first, b);
         }
     }
+}
+
+// ======================================================== collide (sparse) ==
+// One work-group per query whose activated points are few next to n: its
+// SC-scores are counted per bucket of kSpBucket consecutive ids that holds
+// some of them, so the work follows the activated points (counting is
+// O(alpha*n*N_s) per query, Sec. 4.3) instead of visiting every tile of the
+// id range:
+//  1. the query's activated cells become runs of the cell-major id copy (one
+//     run per cell), and every id is counted in its bucket;
+//  2. buckets are grouped into rounds whose ids fit in LDS; per round the
+//     ids are read again and their low 12 bits placed bucket by bucket;
+//  3. a wave takes a bucket: 4-bit scores in the wave's window (a 32-bit LDS
+//     atomic add of 1 << 4*(low & 7): an id occurs once per subspace and
+//     N_s <= 15, so no nibble carries), the old values give the histogram
+//     G[t] = #{score >= t} as in the tiled step, and the bucket's points of
+//     non-zero score go, in ascending id, to the query's list area as
+//     (score << 12 | low) entries while the window is cleared;
+//  4. T = max{t : G[t] >= B} and R = B - G[T+1]; each bucket counts its
+//     entries above T and at T, two block scans give the level-T cut (the R
+//     lowest ids of score T, taken in bucket order) and every bucket's output
+//     offset, and the candidates are written in ascending id.
+// A query is left to the tiled steps (route 1) when N_s > 15, it has more
+// than kSpMaxRuns activated cells, more points than kSpMaxRounds rounds hold
+// or a bucket larger than one round, or when T = 0 (fewer than B points
+// collide: the score-0 points are the tiled selection's case); otherwise
+// route 0, and the tiled collision and selection kernels skip the query.
+struct SparseLds {
+    uint32_t G[kSpMaxNs + 2];
+    uint32_t red[2 * kSpWaves + 2];
+    uint32_t rb[kSpMaxRounds + 1];   // round r covers buckets [rb[r], rb[r+1])
+    int nruns, nrounds, flag;
+};
+
+// Every id of the query's activated cells, in runs: wave w takes runs w,
+// w + kSpWaves, ...; a run's ids are read by consecutive lanes, four loads in
+// flight per lane.
+template <class F>
+__device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, int nruns, F &&f) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int r = w; r < nruns; r += kSpWaves) {
+        const uint2 rd = runs[r];
+        const uint32_t *src = a.ix.ids32 + rd.x;
+        for (uint32_t m = (uint32_t)lane; m < rd.y; m += 4u * kWave) {
+            uint32_t id[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t mm = m + (uint32_t)(u * kWave);
+                id[u] = mm < rd.y ? src[mm] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (m + (uint32_t)(u * kWave) < rd.y) f(id[u]);
+        }
+    }
+}
+
+// One bucket by one wave (see step 3).  seg holds its len low ids; list is
+// the bucket's entry area (global); hc gathers the old values per level in
+// 16-bit fields.  Returns the number of entries written.
+__device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, const int b, const uint16_t *seg,
+                                              const uint32_t len, uint32_t *win, uint64_t (&hc)[4],
+                                              uint16_t *list) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (uint32_t j = (uint32_t)lane; j < len; j += kWave) {
+        const uint32_t u = seg[j];
+        const uint32_t sh = (u & 7u) << 2;
+        const uint32_t o = (atomicAdd(&win[u >> 3], 1u << sh) >> sh) & 15u;
+        const uint64_t one = 1ull << ((o & 3u) << 4);
+        if (o < 4u) hc[0] += one;
+        else if (o < 8u) hc[1] += one;
+        else if (o < 12u) hc[2] += one;
+        else hc[3] += one;
+    }
+    // lane l reads words 8l .. 8l + 7 (ids 64l .. 64l + 63 of the bucket) and clears them
+    uint4 *w4 = reinterpret_cast<uint4 *>(win) + 2 * lane;
+    uint32_t x[8];
+    {
+        const uint4 p0 = w4[0], p1 = w4[1];
+        x[0] = p0.x; x[1] = p0.y; x[2] = p0.z; x[3] = p0.w;
+        x[4] = p1.x; x[5] = p1.y; x[6] = p1.z; x[7] = p1.w;
+    }
+    uint32_t nz[8], cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        nz[k] = (x[k] | (x[k] >> 1) | (x[k] >> 2) | (x[k] >> 3)) & 0x11111111u;
+        cnt += (uint32_t)__popc(nz[k]);
+    }
+    if (cnt != 0u) {
+        w4[0] = make_uint4(0u, 0u, 0u, 0u);
+        w4[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    uint16_t *dst = list + (incl - cnt);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint32_t m = nz[k];
+        while (m != 0u) {
+            const uint32_t nib = (uint32_t)__builtin_ctz(m) >> 2;
+            *dst++ = (uint16_t)((((x[k] >> (4u * nib)) & 15u) << kSpShift) | ((uint32_t)(8 * lane + k) * 8u + nib));
+            m &= m - 1u;
+        }
+    }
+    if (a.scores != nullptr) {
+        // dense scores on request (parity tests): ids of this lane, below n
+        uint8_t *row = a.scores + (int64_t)ql * a.ix.P * a.ix.TILE;
+        const int64_t id0 = (int64_t)b * kSpBucket + 64 * lane;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            for (int nib = 0; nib < 8; ++nib) {
+                const int64_t id = id0 + 8 * k + nib;
+                if (id < a.ix.n) row[id] = (uint8_t)((x[k] >> (4 * nib)) & 15u);
+            }
+    }
+    return (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+}
+
+// Entry pairs of a bucket's list, read past the L1 cache (the list was
+// written by other waves of this work-group).
+__device__ __forceinline__ uint32_t sp_load_pair(const uint16_t *list, uint32_t j2) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(list) + j2;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
+    extern __shared__ uint4 sp_dyn[];
+    __shared__ SparseLds S;
+    const int NB = a.ix.NB, ns = a.ix.ns, K = a.ix.K;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, length)
+    const int NBp = sp_nb_padded(NB);
+    uint32_t *boff = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);      // [NB+1] bucket starts, then output offsets
+    uint32_t *bfill = boff + NBp;                                          // [NB] fill pointers, then entry counts
+    uint32_t *bx = bfill + NBp;                                            // [NB] above-T | at-T << 16, then takes
+    uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
+    uint16_t *raw = reinterpret_cast<uint16_t *>(win_all + kSpWaves * kSpWords);
+    uint32_t *win = win_all + w * kSpWords;
+    const uint32_t cap = (uint32_t)a.sp_cap;
+    const int nq = pass_nq(a.nq_dev, a.q_base, a.nq);
+    const int64_t lstride = (int64_t)a.ix.P * a.ix.TILE;
+    for (int j = tid; j < kSpWaves * kSpWords; j += kSpThreads) win_all[j] = 0u;
+    for (int rq = blockIdx.x; rq < nq; rq += gridDim.x) {
+        const int ql = a.order ? a.order[rq] : rq;
+        // ---- runs of the activated cells
+        if (tid == 0) {
+            uint32_t m = 0;
+            int nr = 0;
+            for (int i = 0; i < ns; ++i) {
+                m += (uint32_t)a.aprime[ql * ns + i];
+                nr += a.ncells[ql * ns + i];
+            }
+            S.nruns = nr;
+            S.flag = (ns > kSpMaxNs || nr > kSpMaxRuns || m > (uint32_t)kSpMaxRounds * cap) ? 1 : 0;
+        }
+        for (int t = tid; t < ns + 2; t += kSpThreads) S.G[t] = 0u;
+        for (int b = tid; b <= NB; b += kSpThreads) boff[b] = 0u;
+        __syncthreads();
+        if (S.flag) {
+            if (tid == 0) a.route[ql] = 1;
+            __syncthreads();
+            continue;
+        }
+        const int nruns = S.nruns;
+        for (int r = tid; r < nruns; r += kSpThreads) {
+            int i = 0, j = r;
+            while (j >= a.ncells[ql * ns + i]) j -= a.ncells[ql * ns + i++];
+            const int c = a.cells[((int64_t)ql * ns + i) * K + j];
+            const uint32_t *co = a.ix.coffs + (int64_t)i * (K + 1);
+            const uint32_t s = co[c];
+            runs[r] = make_uint2((uint32_t)((int64_t)i * a.ix.n) + s, co[c + 1] - s);
+        }
+        __syncthreads();
+        // ---- 1. points per bucket
+        sp_walk(a, runs, nruns, [&](uint32_t id) { atomicAdd(&boff[id >> kSpShift], 1u); });
+        __syncthreads();
+        // exclusive scan over the buckets: thread t owns a contiguous block of them
+        const int per = (NB + kSpThreads - 1) / kSpThreads;
+        const int b0t = tid * per < NB ? tid * per : NB, b1t = b0t + per < NB ? b0t + per : NB;
+        {
+            uint32_t local = 0, big = 0;
+            for (int b = b0t; b < b1t; ++b) {
+                local += boff[b];
+                big |= boff[b] > cap ? 1u : 0u;
+            }
+            uint32_t tot;
+            uint32_t run = block_excl_scan<kSpThreads>(local, S.red, &tot);
+            const uint32_t anybig = __syncthreads_or(big != 0u);
+            for (int b = b0t; b < b1t; ++b) {
+                const uint32_t v = boff[b];
+                boff[b] = run;
+                run += v;
+            }
+            if (tid == 0) {
+                boff[NB] = tot;
+                S.flag = anybig ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (S.flag) {
+            if (tid == 0) a.route[ql] = 1;
+            __syncthreads();
+            continue;
+        }
+        // rounds: the longest run of buckets from each start whose ids fit
+        if (tid == 0) {
+            int r = 0, st = 0;
+            S.rb[0] = 0;
+            while (st < NB && r < kSpMaxRounds) {
+                int lo = st + 1, hi = NB;            // largest e with boff[e] - boff[st] <= cap
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (boff[mid] - boff[st] <= cap) lo = mid; else hi = mid - 1;
+                }
+                S.rb[++r] = (uint32_t)lo;
+                st = lo;
+            }
+            S.nrounds = r;
+            S.flag = st < NB ? 1 : 0;
+        }
+        __syncthreads();
+        if (S.flag) {
+            if (tid == 0) a.route[ql] = 1;
+            __syncthreads();
+            continue;
+        }
+        // ---- 2 and 3: rounds of placement and bucket counting
+        uint16_t *qlist = a.lvl + (int64_t)ql * lstride;
+        uint64_t hc[4] = {0ull, 0ull, 0ull, 0ull};
+        for (int r = 0; r < S.nrounds; ++r) {
+            const int bb0 = (int)S.rb[r], bb1 = (int)S.rb[r + 1];
+            const uint32_t base = boff[bb0];
+            for (int b = bb0 + tid; b < bb1; b += kSpThreads) bfill[b] = boff[b] - base;
+            __syncthreads();
+            sp_walk(a, runs, nruns, [&](uint32_t id) {
+                const int b = (int)(id >> kSpShift);
+                if (b >= bb0 && b < bb1) raw[atomicAdd(&bfill[b], 1u)] = (uint16_t)(id & (kSpBucket - 1));
+            });
+            __syncthreads();
+            for (int b = bb0 + w; b < bb1; b += kSpWaves) {
+                const uint32_t st = boff[b] - base, len = boff[b + 1] - boff[b];
+                const uint32_t ne = sp_bucket(a, ql, b, raw + st, len, win, hc, qlist + (int64_t)b * kSpBucket);
+                if (lane == 0) bfill[b] = ne;
+            }
+            __syncthreads();
+        }
+        // ---- 4. threshold, level-T cut, candidates
+#pragma unroll
+        for (int t = 1; t <= kSpMaxNs; ++t) {
+            if (t > ns) break;
+            const uint32_t f = (uint32_t)(hc[(t - 1) >> 2] >> (((t - 1) & 3) * 16)) & 0xffffu;
+            const uint32_t sum = wave_sum(f);
+            if (lane == 0 && sum) atomicAdd(&S.G[t], sum);
+        }
+        __threadfence();                 // the entry lists reach L2 before other waves read them
+        __syncthreads();
+        const uint32_t B = (uint32_t)a.B;
+        int T = 0;
+        for (int t = ns; t >= 1; --t)
+            if (S.G[t] >= B) { T = t; break; }
+        if (T == 0) {
+            if (tid == 0) a.route[ql] = 1;
+            __syncthreads();
+            continue;
+        }
+        const uint32_t R = B - S.G[T + 1];
+        for (int b = w; b < NB; b += kSpWaves) {
+            const uint32_t ne = bfill[b];
+            const uint16_t *list = qlist + (int64_t)b * kSpBucket;
+            uint32_t gt = 0, eq = 0;
+            for (uint32_t j2 = (uint32_t)lane; 2 * j2 < ne; j2 += kWave) {
+                const uint32_t pr = sp_load_pair(list, j2);
+                const uint32_t s0 = (pr & 0xffffu) >> kSpShift, s1 = pr >> (16 + kSpShift);
+                gt += (s0 > (uint32_t)T) + (2 * j2 + 1 < ne && s1 > (uint32_t)T);
+                eq += (s0 == (uint32_t)T) + (2 * j2 + 1 < ne && s1 == (uint32_t)T);
+            }
+            gt = wave_sum(gt);
+            eq = wave_sum(eq);
+            if (lane == 0) bx[b] = gt | (eq << 16);
+        }
+        __syncthreads();
+        {
+            uint32_t eql = 0;
+            for (int b = b0t; b < b1t; ++b) eql += bx[b] >> 16;
+            uint32_t tot;
+            uint32_t eb = block_excl_scan<kSpThreads>(eql, S.red, &tot);
+            uint32_t outl = 0;
+            for (int b = b0t; b < b1t; ++b) {
+                const uint32_t gt = bx[b] & 0xffffu, eq = bx[b] >> 16;
+                const uint32_t take = eb >= R ? 0u : (R - eb < eq ? R - eb : eq);
+                eb += eq;
+                boff[b] = gt + take;         // this bucket's candidates
+                bx[b] = take;
+                outl += gt + take;
+            }
+            uint32_t ob = block_excl_scan<kSpThreads>(outl, S.red, &tot);
+            for (int b = b0t; b < b1t; ++b) {
+                const uint32_t v = boff[b];
+                boff[b] = ob;
+                ob += v;
+            }
+        }
+        __syncthreads();
+        uint32_t *cq = a.cand + (int64_t)ql * a.B;
+        const uint64_t below = (1ull << lane) - 1ull;
+        for (int b = w; b < NB; b += kSpWaves) {
+            const uint32_t ne = bfill[b], take = bx[b];
+            const uint16_t *list = qlist + (int64_t)b * kSpBucket;
+            uint32_t pos = boff[b], eqseen = 0;
+            const uint32_t id0 = (uint32_t)b << kSpShift;
+            for (uint32_t c0 = 0; c0 < ne; c0 += 2 * kWave) {
+                const uint32_t j2 = c0 / 2 + (uint32_t)lane;
+                const bool v0 = 2 * j2 < ne, v1 = 2 * j2 + 1 < ne;
+                const uint32_t pr = v0 ? sp_load_pair(list, j2) : 0u;
+                const uint32_t e0 = pr & 0xffffu, e1 = pr >> 16;
+                const uint32_t s0 = e0 >> kSpShift, s1 = e1 >> kSpShift;
+                const bool q0 = v0 && s0 == (uint32_t)T, q1 = v1 && s1 == (uint32_t)T;
+                // level-T rank of the lane's first entry inside the bucket
+                const uint64_t m0 = __ballot(q0), m1 = __ballot(q1);
+                const uint32_t r0 = eqseen + (uint32_t)__popcll(m0 & below) + (uint32_t)__popcll(m1 & below);
+                const bool t0 = (v0 && s0 > (uint32_t)T) || (q0 && r0 < take);
+                const bool t1 = (v1 && s1 > (uint32_t)T) || (q1 && r0 + (q0 ? 1u : 0u) < take);
+                const uint64_t k0 = __ballot(t0), k1 = __ballot(t1);
+                uint32_t at = pos + (uint32_t)__popcll(k0 & below) + (uint32_t)__popcll(k1 & below);
+                if (t0 && at < B) cq[at] = id0 | (e0 & (kSpBucket - 1));
+                at += t0 ? 1u : 0u;
+                if (t1 && at < B) cq[at] = id0 | (e1 & (kSpBucket - 1));
+                pos += (uint32_t)(__popcll(k0) + __popcll(k1));
+                eqseen += (uint32_t)(__popcll(m0) + __popcll(m1));
+            }
+        }
+        if (tid == 0) a.route[ql] = 0;
+        __syncthreads();
+    }
+}
+
+// Points in the activated cells of every (query, subspace): one wave each.
+__global__ __launch_bounds__(kWave) void k_cell_points(SizesPass a) {
+    const int item = blockIdx.x, q = item / a.ix.ns, i = item - q * a.ix.ns;
+    if (q >= a.nq) return;
+    const int nc = a.ncells[item];
+    const uint16_t *cl = a.cells + (int64_t)item * a.ix.K;
+    uint32_t s = 0;
+    for (int j = threadIdx.x; j < nc; j += kWave) s += a.ix.csize[(int64_t)i * a.ix.K + cl[j]];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) a.aprime[item] = (int32_t)s;
 }
 
 // ================================================================= order ==
@@ -1158,6 +1504,7 @@ __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
     for (int w = threadIdx.x; w < (NT / kWave) * 64; w += NT) sum[w] = 0u;
     __syncthreads();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        if (a.route != nullptr && a.route[item] == 0) continue;   // selected by the sparse step
         select_item<NT>(a, item, bm, sum);
         __syncthreads();
     }
@@ -1508,6 +1855,23 @@ Launch plan_collide(const QueryPass &p, int cap) {
     return L;
 }
 
+Launch plan_collide_sparse(const QueryPass &p, int cap) {
+    Launch L;
+    L.lds = sp_lds_bytes(p.ix.NB, p.sp_cap);
+    L.grid = dim3(grid_for(p.nq, cap));
+    L.block = dim3(kSpThreads);
+    L.func = reinterpret_cast<const void *>(&k_collide_sparse);
+    return L;
+}
+
+Launch plan_cell_points(const SizesPass &p) {
+    Launch L;
+    L.grid = dim3((unsigned)std::max(1, p.nq * p.ix.ns));
+    L.block = dim3(kWave);
+    L.func = reinterpret_cast<const void *>(&k_cell_points);
+    return L;
+}
+
 Launch plan_order(const QueryPass &p) {
     Launch L;
     L.func = p.nq <= kOrderMax ? reinterpret_cast<const void *>(&k_order)
@@ -1558,6 +1922,12 @@ Launch plan_merge(const RerankPass &r, int cap) {
 hipError_t launch(const Launch &L, void *arg, hipStream_t s) {
     void *args[] = {arg};
     return hipLaunchKernel(L.func, L.grid, L.block, args, L.lds, s);
+}
+
+int sparse_static_lds() {
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_collide_sparse)) != hipSuccess) return -1;
+    return (int)at.sharedSizeBytes;
 }
 
 int collide_static_lds() {

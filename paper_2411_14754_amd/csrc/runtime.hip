@@ -62,9 +62,20 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->device = dev;
     ix->n = n; ix->d = d; ix->ns = ns; ix->sk = sk; ix->K = sk * sk;
     ix->no_byte_rows = p && (p->flags & SUCO_BUILD_NO_BYTE_ROWS);
+    ix->no_sparse = p && (p->flags & SUCO_BUILD_NO_SPARSE);
     ix->want_bf16 = p && (p->flags & SUCO_BUILD_BF16);
     ix->tile_req = p ? p->tile_max : 0;
     ix->chunk_req = p ? std::max(0, p->query_chunk) : 0;
+    // The sparse collision step: two work-groups per CU (160 KB of LDS per CU on
+    // gfx950), each with its tables, windows and as many ids per round as fit.
+    ix->NB = (int)((n + kSpBucket - 1) / kSpBucket);
+    if (!ix->no_sparse && ns <= kSpMaxNs && ix->NB <= kSpMaxBuckets) {
+        const int sps = sparse_static_lds();
+        if (sps < 0) { delete ix; return fail(SUCO_E_HIP, "cannot query the sparse collision kernel's attributes"); }
+        const int64_t budget = std::min<int64_t>(max_lds, 160 * 1024 / 2) - sps;
+        const int64_t cap = (budget - (int64_t)sp_lds_bytes(ix->NB, 0)) / 2 / 8 * 8;
+        ix->sp_cap = cap >= 4096 ? (int)std::min<int64_t>(cap, 1 << 20) : 0;
+    }
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
     const int64_t per = (n + P0 - 1) / P0;
     ix->TILE = (int)((per + 255) / 256 * 256);
@@ -82,7 +93,9 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
         (rc = dev_alloc(&ix->halves, (size_t)2 * ns)) ||
         (rc = dev_alloc(&ix->toffs, (size_t)ns * ix->P * (ix->K + 1))) ||
         (rc = dev_alloc(&ix->ids16, (size_t)ns * span)) || (rc = dev_alloc(&ix->csize, (size_t)ns * ix->K)) ||
-        (rc = dev_alloc(&ix->assign, (size_t)2 * ns * n))) {
+        (rc = dev_alloc(&ix->assign, (size_t)2 * ns * n)) ||
+        (ix->sp_cap && ((rc = dev_alloc(&ix->coffs, (size_t)ns * (ix->K + 1))) ||
+                        (rc = dev_alloc(&ix->ids32, (size_t)ns * n))))) {
         ix->release();
         delete ix;
         return rc;
@@ -109,6 +122,9 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
 int finish_index(suco_index *ix, hipStream_t st) {
     HIPCHECK(launch_imi_build(ix->assign, ix->n, ix->ns, ix->sk, ix->P, ix->TILE, ix->toffs, ix->ids16,
                               ix->csize, st));
+    if (ix->sp_cap)
+        HIPCHECK(launch_cell_major(ix->toffs, ix->ids16, ix->csize, ix->n, ix->ns, ix->K, ix->P, ix->TILE, ix->coffs,
+                                   ix->ids32, st));
     int *bad = nullptr;
     int rc = dev_alloc(&bad, 1);
     if (rc) return rc;
@@ -303,7 +319,8 @@ int save_index(const suco_index *ix, const char *path) {
     std::memcpy(h.magic, kFileMagic, 8);
     h.version = 1; h.header_bytes = sizeof(FileHeader);
     h.n = ix->n; h.d = ix->d; h.ns = ix->ns; h.sk = ix->sk;
-    h.flags = (ix->no_byte_rows ? SUCO_BUILD_NO_BYTE_ROWS : 0) | (ix->want_bf16 ? SUCO_BUILD_BF16 : 0);
+    h.flags = (ix->no_byte_rows ? SUCO_BUILD_NO_BYTE_ROWS : 0) | (ix->want_bf16 ? SUCO_BUILD_BF16 : 0) |
+              (ix->no_sparse ? SUCO_BUILD_NO_SPARSE : 0);
     h.tile_max = ix->tile_req; h.query_chunk = ix->chunk_req;
     if (std::fwrite(&h, sizeof h, 1, out.f) != 1) return fail(SUCO_E_INVAL, "write failed: " + tmp);
     WordHash hs;
@@ -422,7 +439,7 @@ struct Carve {
 
 struct Work {
     uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint16_t *lvl; uint8_t *scores;
-    uint32_t *cand; uint64_t *part_keys; int32_t *order;
+    uint32_t *cand; uint64_t *part_keys; int32_t *order, *route;
 };
 
 // dense: also room for the dense SC-scores (exported on request only)
@@ -438,6 +455,7 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.scores = dense ? c.take<uint8_t>(C * (size_t)ix->P * ix->TILE) : nullptr;
     w.cand = c.take<uint32_t>(C * (size_t)B);
     w.order = c.take<int32_t>(C);
+    w.route = c.take<int32_t>(C);
     w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
     if (bytes) *bytes = c.off;
     return w;
@@ -568,6 +586,8 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         qp.cells = w.cells; qp.ncells = w.ncells; qp.aprime = w.aprime;
         qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
         qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores; qp.cand = w.cand;
+        qp.route = ix->sp_cap ? w.route : nullptr;
+        qp.sp_cap = ix->sp_cap;
         if (bo && (bo->flags & SUCO_BF16_S1)) {
             CentreBf16Pass cp{};
             cp.Q = qp.Q; cp.nq = cn; cp.d = ix->d; cp.sk = ix->sk; cp.nh = nh; cp.halves = ix->halves;
@@ -584,6 +604,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
             HIPCHECK(T(kOrder, [&] { return launch(plan_order(qp), &qp, st); }));
             qp.order = w.order;
         }
+        if (qp.route) HIPCHECK(T(kCollideSparse, [&] { return launch(plan_collide_sparse(qp, 0), &qp, st); }));
         HIPCHECK(T(kCollide, [&] { return launch_collide(qp, st); }));
         HIPCHECK(T(kSelect, [&] { return launch_select(qp, st); }));
         RerankPass rp{};
@@ -866,6 +887,15 @@ int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells
         qp.ncells = const_cast<int32_t *>(ncells) + c0 * ix->ns;
         qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores;
         qp.cand = reinterpret_cast<uint32_t *>(cand) + c0 * B;
+        qp.aprime = w.aprime;
+        qp.route = ix->sp_cap ? w.route : nullptr;
+        qp.sp_cap = ix->sp_cap;
+        if (qp.route) {
+            // the sparse step reads the activated points per subspace
+            SizesPass sp{qp.ix, qp.cells, qp.ncells, cn, w.aprime};
+            HIPCHECK(launch(plan_cell_points(sp), &sp, st));
+            HIPCHECK(timed(ix, kCollideSparse, st, [&] { return launch(plan_collide_sparse(qp, 0), &qp, st); }));
+        }
         HIPCHECK(timed(ix, kCollide, st, [&] { return launch_collide(qp, st); }));
         HIPCHECK(timed(ix, kSelect, st, [&] { return launch_select(qp, st); }));
         if (scores)

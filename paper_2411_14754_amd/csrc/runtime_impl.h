@@ -103,6 +103,11 @@ struct suco_index {
     uint32_t *csize = nullptr;
     uint8_t *assign = nullptr;
     uint8_t *X8 = nullptr;          // byte copy of X when every coordinate is an integer in 0..255
+    uint32_t *coffs = nullptr;      // cell-major copy of the IMI for the sparse collision step
+    uint32_t *ids32 = nullptr;
+    int NB = 0;                     // buckets of the sparse step
+    int sp_cap = 0;                 // its ids per round; 0: the step is off
+    bool no_sparse = false;
     bool no_byte_rows = false;
     bool want_bf16 = false;
     int tile_req = 0;               // tile_max and query_chunk as the caller gave them (0 = automatic),
@@ -135,7 +140,8 @@ struct suco_index {
     IndexView view() const {
         IndexView v;
         v.X = X; v.cent = cent; v.halves = halves; v.toffs = toffs; v.ids16 = ids16; v.csize = csize;
-        v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE;
+        v.coffs = coffs; v.ids32 = ids32;
+        v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE; v.NB = NB;
         return v;
     }
 
@@ -154,8 +160,9 @@ struct suco_index {
         prof_used = 0;
         for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
                         (void *)assign, (void *)arena, (void *)X8, (void *)Xb, (void *)xerr, (void *)centb,
-                        (void *)cnorm2})
+                        (void *)cnorm2, (void *)coffs, (void *)ids32})
             if (p) (void)hipFree(p);
+        coffs = nullptr; ids32 = nullptr;
         X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
         assign = nullptr; arena = nullptr; arena_bytes = 0; X8 = nullptr;
         Xb = nullptr; xerr = nullptr; centb = nullptr; cnorm2 = nullptr;
@@ -168,7 +175,10 @@ namespace suco {
 
 inline bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
 
-enum Stage { kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kOrder, kStages };
+enum Stage {
+    kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kOrder, kCollideSparse,
+    kStages
+};
 
 // Launch through `fn`, bracketed by a pair of timing events when profiling is on.
 template <class F>

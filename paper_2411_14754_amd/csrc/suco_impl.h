@@ -26,9 +26,32 @@ struct IndexView {
     const uint32_t *toffs;   // [ns][P][K+1] start of cell c's ids inside tile p
     const uint16_t *ids16;   // [ns][P*TILE] tile-local ids, tile-major, cell-major, ascending
     const uint32_t *csize;   // [ns][K] points per cell
+    const uint32_t *coffs;   // [ns][K+1] start of cell c in ids32, or null (no sparse collision step)
+    const uint32_t *ids32;   // [ns][n] point ids, cell-major, ascending within a cell
     int64_t n;
     int d, ns, sk, K, P, TILE;
+    int NB;                  // buckets of kSpBucket consecutive ids (sparse collision step)
 };
+
+// Sparse collision step (query_kernels.hip): ids are grouped in buckets of
+// 4096 consecutive ids, one 2 KB window of 4-bit scores per wave.
+constexpr int kSpShift = 12;
+constexpr int kSpBucket = 1 << kSpShift;
+constexpr int kSpThreads = 512;
+constexpr int kSpWaves = kSpThreads / kWave;
+constexpr int kSpWords = kSpBucket / 8;
+constexpr int kSpMaxNs = 15;        // a 4-bit score
+constexpr int kSpMaxBuckets = 4096; // n <= 2^24
+constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
+constexpr int kSpMaxRounds = 4;     // LDS fillings per query
+// Dynamic LDS of the sparse step for NB buckets and `cap` ids per round: the
+// run table, three per-bucket arrays of NB + 1 words padded to 16 bytes, the
+// waves' score windows and the round's low ids.
+__host__ __device__ inline int sp_nb_padded(int NB) { return (NB + 4) & ~3; }
+__host__ __device__ inline size_t sp_lds_bytes(int NB, int cap) {
+    return 8 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
+           2 * (size_t)((cap + 7) & ~7);
+}
 
 // One pass of the query path over a chunk of queries.
 struct QueryPass {
@@ -57,6 +80,9 @@ struct QueryPass {
     const float *Dext;        // [nq][2ns][sqrt_k] centre distances computed elsewhere, or null
     const int32_t *order;     // [nq] order in which the collision step takes the queries, or null
     int32_t *order_out;       // [nq] written by the ordering kernel
+    int32_t *route;           // [nq] 0: scored and selected by the sparse step; 1: by the tiled
+                              //   steps; null: no sparse step (every query takes the tiled steps)
+    int sp_cap;               // sparse step: ids per round (LDS)
 };
 
 struct RerankPass {
@@ -81,6 +107,7 @@ struct RerankPass {
 
 // Launchers (query_kernels.hip)
 int collide_static_lds();   // bytes of LDS the collision kernel declares statically
+int sparse_static_lds();    // the same for the sparse collision kernel
 
 // A kernel with its launch shape: the same plan serves a direct launch and a graph node.
 struct Launch {
@@ -93,6 +120,17 @@ struct Launch {
 constexpr int kActivateGrid = 8192;
 Launch plan_activate(const QueryPass &p, int cap);
 Launch plan_collide(const QueryPass &p, int cap);
+Launch plan_collide_sparse(const QueryPass &p, int cap);
+// Points in the given activated cells per (query, subspace), for the sparse
+// step when the cells come from the caller.
+struct SizesPass {
+    IndexView ix;
+    const uint16_t *cells;    // [nq][ns][K]
+    const int32_t *ncells;    // [nq][ns]
+    int nq;
+    int32_t *aprime;          // [nq][ns]
+};
+Launch plan_cell_points(const SizesPass &p);
 constexpr int kOrderMax = 1024;   // largest pass the ordering kernel sorts
 constexpr int kOrderWide = 16384; // largest pass the bucketed ordering kernel takes
 Launch plan_order(const QueryPass &p);
@@ -196,5 +234,7 @@ hipError_t launch_km_update(const KmeansPass &k, hipStream_t s);
 hipError_t launch_cent_to_f32(const double *c64, float *c32, int64_t m, hipStream_t s);
 hipError_t launch_imi_build(const uint8_t *assign, int64_t n, int ns, int sk, int P, int TILE,
                             uint32_t *toffs, uint16_t *ids16, uint32_t *csize, hipStream_t s);
+hipError_t launch_cell_major(const uint32_t *toffs, const uint16_t *ids16, const uint32_t *csize, int64_t n,
+                             int ns, int K, int P, int TILE, uint32_t *coffs, uint32_t *ids32, hipStream_t s);
 
 }  // namespace suco

@@ -186,6 +186,51 @@ def test_k_extremes(suco, k):
     gix.free()
 
 
+@pytest.mark.parametrize("alpha", [0.01, 0.05])
+def test_sqrt_k_above_64(suco, alpha):
+    """sqrtK = 100 (the activation step's 128-thread form): activated cells,
+    scores, candidates and top-k against the oracle, at a small and a large budget."""
+    W = synth.Workload(1)
+    X, Q = W.data(30_000), W.queries(20)
+    print(f"case: sqrtK=100 n=30000 alpha={alpha}", flush=True)
+    oix, gix = make(X, 4, 100, iters=4)
+    g = debug(gix, Q, 10, alpha, 0.01)
+    assert g["ncells"].sum() > g["ncells"].size        # several cells somewhere
+    st = check_query(oix, X, Q, 10, alpha, 0.01, g)
+    assert st["band_queries"] <= 2
+    gix.free()
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.0005, 0.005), (0.003, 0.005), (0.01, 0.005), (0.05, 0.002),
+                                        (0.3, 0.01), (0.0001, 0.2)])
+def test_sparse_step_equals_tiled_step(suco, alpha, beta):
+    """The sparse collision step (SC-scores per bucket of 4096 ids, one or
+    several LDS rounds) against the tiled step on the same index: candidates,
+    SC-scores and top-k bitwise.  The budgets span one round, several rounds,
+    queries left to the tiled step (too many points) and T = 0 (fewer than B
+    colliding points), all in one batch with per-query alphas around alpha."""
+    W = synth.Workload(2)
+    X = W.data(200_000)
+    Q = W.queries(300)
+    _, c32, asg, _ = oracle.build_index(X, 8, 32, iters=3, seed=2)
+    Xd = torch.from_numpy(X).cuda()
+    sp = suco.Index.from_index(Xd, 8, 32, c32, asg)
+    td = suco.Index.from_index(Xd, 8, 32, c32, asg, flags=suco.BUILD_NO_SPARSE)
+    aq = (alpha * np.exp(np.random.default_rng(1).uniform(-1.0, 1.0, Q.shape[0]))).astype(np.float32)
+    aq = np.minimum(aq, 1.0).astype(np.float32)
+    print(f"case: sparse vs tiled alpha~{alpha} beta={beta}", flush=True)
+    a = debug(sp, Q, 10, 0.0, beta, alpha_q=aq)
+    b = debug(td, Q, 10, 0.0, beta, alpha_q=aq)
+    for key in ("ids", "dists", "cand", "scores", "ncells", "aprime"):
+        assert np.array_equal(a[key], b[key]), key
+    sp.profile(True)
+    sp.query_alpha(torch.from_numpy(Q).cuda(), 10, torch.from_numpy(aq).cuda(), beta)
+    prof = sp.profile_read()
+    print("profile", {k: v for k, v in prof.items() if v[1]}, flush=True)
+    sp.free()
+    td.free()
+
+
 def test_per_query_alpha(suco):
     W = synth.Workload(1)
     X, Q = W.data(8000), W.queries(25)
