@@ -88,6 +88,55 @@ def recall_at(ids, gt):
     return float(hit.float().mean() / k)
 
 
+def exact_dists(Xd, Qd, ids):
+    """Euclidean distances (FP64) of the points `ids` [nq][k] to the queries."""
+    rows = Xd[ids.long()].double()
+    return ((rows - Qd.double()[:, None, :]) ** 2).sum(dim=2).sqrt()
+
+
+def mean_relative_error(dists, gt_d):
+    """Sec. 5.1's MRE: the mean over queries and ranks of (d_i - d*_i) / d*_i, zero d*_i skipped."""
+    g = gt_d.double()
+    m = g > 0
+    r = (dists.double() - g) / g.clamp_min(1e-300)
+    return float(r[m].mean()) if bool(m.any()) else 0.0
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """GB/s of a device-to-device copy of `mib` MiB (bytes read plus bytes written per copy)."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
+def timed_steps(fn, steps, warmup):
+    """(total ms, per-step ms list) of `steps` calls after `warmup`, HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for j in range(steps):
+        fn()
+        ev[j + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[j].elapsed_time(ev[j + 1]) for j in range(steps)]
+    return ev[0].elapsed_time(ev[steps]), per
+
+
 KERNEL_SOURCES = ("query_kernels.hip", "bf16.hip", "wave.h", "suco_impl.h")
 
 
@@ -111,21 +160,57 @@ def counter_traffic(kernel, workload):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def host_cpu():
+    """(threads the oracle may use, nproc, CPU model): the GPU machine gives one GPU's share of its
+    cores (16) to a job whatever nproc shows."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return max(1, min(16, avail)), os.cpu_count() or 1, model
+
+
+def oracle_rate(oix, Q, k, alpha, beta, threads, budget_s, cap):
+    """Queries per second of the oracle on a prefix of Q sized to take about budget_s."""
+    probe = min(cap, max(threads, 32))
+    t0 = time.time()
+    oix.query(Q[:probe], k, alpha, beta, nthreads=threads)
+    dt = time.time() - t0
+    m = int(min(cap, max(probe, probe * budget_s / max(dt, 1e-6))))
+    if m > probe:
+        t0 = time.time()
+        oix.query(Q[:m], k, alpha, beta, nthreads=threads)
+        dt = time.time() - t0
+    else:
+        m = probe
+    return m / dt, m, dt
+
+
 def cpu_baseline(X, Q, alpha, beta, k, sample, log):
-    """The FP64 oracle (its own index, built from the same data) timed on the host."""
+    """The FP64 oracle (its own index, built from the same data) timed on the host: the host's
+    share of cores and one thread, each on a prefix of the queries sized to about 10 s."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, nproc, model = host_cpu()
     t0 = time.time()
     _, c32, asg, _ = oracle.build_index(X, 8, 50, iters=25, seed=1, nthreads=threads)
     oix = oracle.Index(X, 8, 50, c32, asg)
     log(f"oracle index built in {time.time() - t0:.1f}s on {threads} threads")
-    Qs = Q[:sample]
-    t0 = time.time()
-    oix.query(Qs, k, alpha, beta, nthreads=threads)
-    dt = time.time() - t0
-    return {"value": round(sample / dt, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of the 10,000 queries at alpha={alpha}, beta={beta}, k={k}; "
-                      f"FP64 C oracle, OpenMP over queries; {dt:.1f}s"}
+    qps, m, dt = oracle_rate(oix, Q, k, alpha, beta, threads, 10.0, min(sample, Q.shape[0]))
+    qps1, m1, dt1 = oracle_rate(oix, Q, k, alpha, beta, 1, 5.0, min(sample, Q.shape[0]))
+    log(f"oracle: {qps:.1f} QPS on {threads} threads ({m} queries), {qps1:.1f} QPS on 1 thread ({m1} queries)")
+    return {"value": round(qps, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": round(qps1, 3), "nproc": nproc, "cpu_model": model,
+            "sample": f"first {m} of the 10,000 queries on {threads} threads ({dt:.1f}s) and first {m1} on one "
+                      f"thread ({dt1:.1f}s), each sized to ~10 s / ~5 s of work; alpha={alpha}, beta={beta}, "
+                      f"k={k}; FP64 C oracle, OpenMP over queries"}
 
 
 def bench_bf16(args, log):
@@ -254,18 +339,8 @@ def bench_bf16(args, log):
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "gist_like")}
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
         log("timing the CPU oracle")
-        _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=2, seed=1, nthreads=threads)
-        oix = oracle.Index(X, ns, sk, c32, asg)
-        sample = min(args.cpu_sample, 64)
-        t0 = time.time()
-        oix.query(Q[:sample], k, alpha, beta, nthreads=threads)
-        dt = time.time() - t0
-        cpu = {"value": round(sample / dt, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {sample} of the 1,000 queries at alpha={alpha}, beta={beta}, k={k}; FP64 C "
-                         f"oracle on its own 2-iteration index, OpenMP over queries; {dt:.1f}s"}
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "1,000 queries")
     line = {
         "metric": "QPS at recall@10=0.95, GIST-like n=1M d=960: BF16 split-precision SuCo on 1 GPU",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -324,17 +399,19 @@ def stage_profile(ix, fn, steps, step_bytes, nq):
 
 
 def oracle_baseline(X, Q, ns, sk, alpha, beta, k, sample, what):
-    """The FP64 oracle on its own 2-iteration index, timed on `sample` queries on the host."""
+    """The FP64 oracle on its own 2-iteration index, timed on the host's share of cores and on one
+    thread, each on a prefix of the queries sized to about 10 s (at most `sample` queries)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, nproc, model = host_cpu()
     _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=2, seed=1, nthreads=threads)
     oix = oracle.Index(X, ns, sk, c32, asg)
-    t0 = time.time()
-    oix.query(Q[:sample], k, alpha, beta, nthreads=threads)
-    dt = time.time() - t0
-    return {"value": round(sample / dt, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of the {what} at alpha={alpha}, beta={beta}, k={k}; FP64 C oracle on its "
-                      f"own 2-iteration index, OpenMP over queries; {dt:.1f}s"}
+    qps, m, dt = oracle_rate(oix, Q, k, alpha, beta, threads, 10.0, sample)
+    qps1, m1, dt1 = oracle_rate(oix, Q, k, alpha, beta, 1, 5.0, sample)
+    return {"value": round(qps, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": round(qps1, 3), "nproc": nproc, "cpu_model": model,
+            "sample": f"first {m} of the {what} on {threads} threads ({dt:.1f}s) and first {m1} on one thread "
+                      f"({dt1:.1f}s); alpha={alpha}, beta={beta}, k={k}; FP64 C oracle on its own 2-iteration "
+                      f"index, OpenMP over queries"}
 
 
 def step_bytes_for(ix, suco, Qs, k, alpha, beta, n, d):
@@ -427,7 +504,7 @@ def bench_batched_deep(args, log):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "100,000 queries")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "100,000 queries")
     line = {
         "metric": "QPS of a stream of uneven batches, Deep-like n=10M d=96: batched persistent SuCo on 1 GPU",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -459,7 +536,7 @@ def bench_deep_plain(args, log, ix, suco, Qd, X, Q, sp, alpha, ms_plain, rec_pla
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "100,000 queries")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "100,000 queries")
     line = {
         "metric": "QPS of 100,000 queries in one call, Deep-like n=10M d=96: plain SuCo on 1 GPU",
         "value": round(nq * args.steps / (ms_plain / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
@@ -556,7 +633,7 @@ def bench_learned_lifted(args, log):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 16, "10,000 queries")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "10,000 queries")
     line = {
         "metric": "QPS at recall@10=0.95, lifted n=10M d=256: learned+batched vs plain SuCo on 1 GPU",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -586,7 +663,7 @@ def main():
                          "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=10_000, help="most queries the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--tile-max", type=int, default=0, help="largest collision tile (0: library default)")
@@ -693,29 +770,29 @@ def main():
     T = srt[:, B - 1:B]
     ge_T = float((sc >= T).sum(dim=1).double().mean())
     del o, sc, srt
+    rows_b = 1.0 if ix.flags() & suco.INDEX_BYTE_ROWS else 4.0
+    # algorithmic bytes per query of each step in the index's own layout: the
+    # sparse step reads the activated cells' 32-bit ids once (the survey's S3
+    # term 4*A'*N_s) and writes B candidate ids, everything else in LDS; the
+    # tiled step reads the 16-bit tile-local ids and writes the non-zero-score
+    # ids by level, the selection reads the levels at or above the threshold;
+    # the re-rank reads the candidates' rows as stored (one byte per coordinate
+    # when the index keeps the byte copy) and their ids
     step_bytes = {
-        "collide": 2.0 * aprime + 2.0 * U,           # u16 ids of activated cells read, non-zero-score ids written
-        "select": 2.0 * ge_T + 4.0 * B,              # ids at or above the threshold read, candidates written
-        # candidate rows (bytes when the index keeps a byte copy of X) + candidate ids
-        "rerank": (1.0 if ix.flags() & suco.INDEX_BYTE_ROWS else 4.0) * B * d + 4.0 * B,
+        "collide_sparse": 4.0 * aprime + 4.0 * B,
+        "collide": 2.0 * aprime + 2.0 * U,
+        "select": 2.0 * ge_T + 4.0 * B,
+        "rerank": rows_b * B * d + 4.0 * B,
     }
+    # the survey's per-query figures for the same steps (S3: 4*A'*N_s, S5: 4*B*d FP32 rows)
+    survey_bytes = {"collide_sparse": 4.0 * aprime, "collide": 4.0 * aprime, "rerank": 4.0 * B * d + 4.0 * B}
 
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(steps):
-            fn()
-        t1.record(stream)
-        torch.cuda.synchronize()
-        return t0.elapsed_time(t1)
-
-    ms_plain = timed(lambda: run(alpha), args.steps, args.warmup)
+    ms_plain, per_step = timed_steps(lambda: run(alpha), args.steps, args.warmup)
     plain_value = nq * args.steps / (ms_plain / 1e3)
     plain_rec = recall_at(ids, gt)
-    log(f"plain timed: {ms_plain / args.steps:.3f} ms/step, {plain_value:.0f} QPS, recall@10={plain_rec:.4f}")
+    plain_mre = mean_relative_error(dists, exact_dists(Xd, Qd, gt))
+    log(f"plain timed: {ms_plain / args.steps:.3f} ms/step (median {sorted(per_step)[len(per_step) // 2]:.3f}), "
+        f"{plain_value:.0f} QPS, recall@10={plain_rec:.4f}, MRE={plain_mre:.2e}")
 
     # same steps again with every launch bracketed by HIP events on the query stream
     ix.profile(True)
@@ -726,23 +803,33 @@ def main():
     ix.profile(False)
     launches = stage["collide"][1] // args.steps
     per_kernel = {}
-    for s, (tms, cnt) in stage.items():
+    for sname, (tms, cnt) in stage.items():
         if cnt == 0:
             continue
         avg_ms = tms / cnt
         ent = {"avg_ms": round(avg_ms, 5), "launches": cnt,
                "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
-        if s in step_bytes:
+        if sname in step_bytes:
             # launches cover `chunk` queries except a ragged last one: use the per-step total
-            bytes_launch = step_bytes[s] * nq / max(1, cnt // args.steps)
+            bytes_launch = step_bytes[sname] * nq / max(1, cnt // args.steps)
             ent["alg_bytes_per_launch"] = bytes_launch
             ent["gbs"] = round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1)
-        per_kernel[s] = ent
-    dom = max(step_bytes, key=lambda s: stage[s][0])
-    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+            if sname in survey_bytes:
+                sb_launch = survey_bytes[sname] * nq / max(1, cnt // args.steps)
+                ent["survey_bytes_per_launch"] = sb_launch
+                ent["survey_gbs"] = round(sb_launch / (avg_ms * 1e-3) / 1e9, 1)
+        per_kernel[sname] = ent
+    dom = max((t for t in step_bytes if stage[t][1]), key=lambda t: stage[t][0])
+    kern_name = {"collide_sparse": "k_collide_sparse", "collide": "k_collide", "select": "k_select",
+                 "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
+    copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "sift_like")}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "sift_like"),
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                "survey_bytes": {t: {"gbs": per_kernel[t].get("survey_gbs"),
+                                     "frac": round(per_kernel[t]["survey_gbs"] / HBM_PEAK_GBS, 4)}
+                                 for t in survey_bytes if t in per_kernel and "survey_gbs" in per_kernel[t]}}
 
     # learned + batched: labels from plain sweeps on training queries, FP32
     # training, scale calibrated on held-out queries, then the evaluation queries
@@ -773,7 +860,7 @@ def main():
                 b.query(Qd[s0:s0 + sz], alpha=alpha, out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
                 s0 += sz
 
-        ms_pb = timed(plain_stream, args.steps, max(1, args.warmup))
+        ms_pb, _ = timed_steps(plain_stream, args.steps, max(1, args.warmup))
         log(f"plain batched stream: {ms_pb / args.steps:.3f} ms/step, {nq * args.steps / (ms_pb / 1e3):.0f} QPS")
         b.set_model(net, scale, amin, amax)
 
@@ -783,11 +870,12 @@ def main():
                 b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
                 s0 += sz
 
-        ms_l = timed(stream_pass, args.steps, max(1, args.warmup))
+        ms_l, per_step = timed_steps(stream_pass, args.steps, max(1, args.warmup))
         value = nq * args.steps / (ms_l / 1e3)
         rec = recall_at(ids, gt)
-        ms_l1 = timed(lambda: suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax, out=(ids, dists)),
-                      args.steps, max(1, args.warmup))
+        learned_mre = mean_relative_error(dists, exact_dists(Xd, Qd, gt))
+        ms_l1, _ = timed_steps(lambda: suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax,
+                                                          out=(ids, dists)), args.steps, max(1, args.warmup))
         log(f"learned, one call: {ms_l1 / args.steps:.3f} ms/step, {nq * args.steps / (ms_l1 / 1e3):.0f} QPS")
         _, _, au = suco.query_learned(ix, net, Qd, k, beta, scale, amin, amax)
         mean_alpha = float(au.double().mean())
@@ -805,6 +893,7 @@ def main():
                         "train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
                         "scale": round(scale, 5), "mean_alpha": round(mean_alpha, 6), "train_s": round(train_s, 2),
                         "batch_sizes": sizes, "plain_qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1),
+                        "mre": learned_mre,
                         "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)]}
         b.free()
         net.free()
@@ -824,6 +913,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(sorted(per_step)[len(per_step) // 2], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -833,6 +923,7 @@ def main():
                                f"beta={beta}",
                    "form": form, "recall_at_10": round(rec, 5),
                    "plain": {"alpha": alpha, "qps": round(plain_value, 1), "recall_at_10": round(plain_rec, 5),
+                             "mre": plain_mre,
                              "qps_at_recall_0.95_interp": None if qps_interp is None else round(qps_interp, 1)},
                    "learned": learned_info,
                    "launches_per_step": launches, "index_build_s": round(build_s, 3), "sweep": sweep},

@@ -207,7 +207,8 @@ SUCO_API int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, 
  * query), also exporting the intermediate results of every step; each extra
  * output is device memory and may be NULL:
  *  scores  uint8 [nq][n]      SC-scores after step 3
- *  cand    int32 [nq][B]      step-4 candidates in ascending id order
+ *  cand    int32 [nq][B]      step-4 candidates (the set is defined; its order
+ *                             within a row is not, compare rows as sets)
  *  ncells  int32 [nq][n_s]    number of cells activated per subspace
  *  aprime  int32 [nq][n_s]    points in those cells (>= A)
  *  cells   uint16 [nq][n_s][sqrt_k^2]  activated cell ids (a1*sqrt_k + a2),

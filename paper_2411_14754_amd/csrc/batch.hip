@@ -345,7 +345,7 @@ int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, doub
         (rc = dev_alloc(&b->cells, C * ix->ns * ix->K)) || (rc = dev_alloc(&b->ncells, C * ix->ns)) ||
         (rc = dev_alloc(&b->aprime, C * ix->ns)) || (rc = dev_alloc(&b->hist, C * ix->P * (ix->ns + 2))) ||
         (rc = dev_alloc(&b->order, C)) || (rc = dev_alloc(&b->route, C)) ||
-        (rc = dev_alloc(&b->lvl, C * (size_t)ix->P * ix->TILE)) || (rc = dev_alloc(&b->cand, C * (size_t)b->B)) ||
+        (rc = dev_alloc(&b->lvl, C * (size_t)ix->P * ix->TILE + 2 * kSpBucket)) || (rc = dev_alloc(&b->cand, C * (size_t)b->B)) ||
         (rc = dev_alloc(&b->part_keys, C * (size_t)b->parts_max * k))) {
         b->release();
         delete b;

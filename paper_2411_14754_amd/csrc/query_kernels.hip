@@ -22,67 +22,6 @@
 
 namespace suco {
 
-// Sum over the block; every thread gets the total.  Like the scans below, it
-// is called by every thread of the block.
-template <int NT>
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red) {
-    v = wave_sum(v);
-    if constexpr (NT == kWave) {
-        return v;
-    } else {
-        __syncthreads();
-        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
-        __syncthreads();
-        uint32_t s = 0;
-#pragma unroll
-        for (int j = 0; j < NT / kWave; ++j) s += red[j];
-        return s;
-    }
-}
-
-// Exclusive prefix over threads in index order; *total gets the block sum.
-template <int NT>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const uint32_t x = wave_incl_scan(v);
-    __syncthreads();
-    if (lane == kWave - 1) red[w] = x;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-#pragma unroll
-    for (int j = 0; j < NT / kWave; ++j) {
-        uint32_t r = red[j];
-        base += (j < w) ? r : 0u;
-        tot += r;
-    }
-    *total = tot;
-    return base + x - v;
-}
-
-// Two exclusive prefixes at once (one pass of barriers); *ta, *tb get the sums.
-template <int NT>
-__device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint32_t *red2, uint32_t *ea,
-                                                 uint32_t *eb, uint32_t *ta, uint32_t *tb) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const uint32_t xa = wave_incl_scan(va), xb = wave_incl_scan(vb);
-    __syncthreads();
-    if (lane == kWave - 1) { red2[2 * w] = xa; red2[2 * w + 1] = xb; }
-    __syncthreads();
-    uint32_t ba = 0, bb = 0, sa = 0, sb = 0;
-#pragma unroll
-    for (int j = 0; j < NT / kWave; ++j) {
-        const uint32_t ra = red2[2 * j], rb = red2[2 * j + 1];
-        ba += (j < w) ? ra : 0u;
-        bb += (j < w) ? rb : 0u;
-        sa += ra;
-        sb += rb;
-    }
-    *ea = ba + xa - va;
-    *eb = bb + xb - vb;
-    *ta = sa;
-    *tb = sb;
-}
-
 // A = max(1, ceil(alpha*n - 1e-9)), capped at n, in FP64 without contraction.
 // A per-query alpha is not validated on the host: above 1, +inf and NaN
 // activate every point, and alpha <= 0 activates one.
@@ -574,7 +513,7 @@ template <int NT>
 __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, const uint32_t (&lid)[kCollideUnroll],
                                               const uint32_t vm, const int b, const bool inc, uint64_t (&hc)[2]) {
     const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    const uint64_t below_mask = (1ull << lane) - 1ull;
     uint32_t old[kCollideUnroll];
 #pragma unroll
     for (int u = 0; u < kCollideUnroll; ++u) {
@@ -604,7 +543,7 @@ __device__ __forceinline__ void collide_count(CollideLds<NT> &L, uint32_t *sc, c
 #pragma unroll
         for (int u = 0; u < kCollideUnroll; ++u) {
             if (old[u] == 0u) {
-                const uint32_t pos = base + (uint32_t)__popcll(m[u] & lanes_below);
+                const uint32_t pos = base + (uint32_t)__popcll(m[u] & below_mask);
                 if (pos < (uint32_t)kTouchCap) L.touched[pos] = (uint16_t)(lid[u] >> 2);
             }
             base += (uint32_t)__popcll(m[u]);
@@ -897,121 +836,198 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 // SC-scores are counted per bucket of kSpBucket consecutive ids that holds
 // some of them, so the work follows the activated points (counting is
 // O(alpha*n*N_s) per query, Sec. 4.3) instead of visiting every tile of the
-// id range:
+// id range, and everything after the id reads stays in LDS:
 //  1. the query's activated cells become runs of the cell-major id copy (one
-//     run per cell), and every id is counted in its bucket;
-//  2. buckets are grouped into rounds whose ids fit in LDS; per round the
-//     ids are read again and their low 12 bits placed bucket by bucket;
-//  3. a wave takes a bucket: 4-bit scores in the wave's window (a 32-bit LDS
-//     atomic add of 1 << 4*(low & 7): an id occurs once per subspace and
-//     N_s <= 15, so no nibble carries), the old values give the histogram
-//     G[t] = #{score >= t} as in the tiled step, and the bucket's points of
-//     non-zero score go, in ascending id, to the query's list area as
-//     (score << 12 | low) entries while the window is cleared;
-//  4. T = max{t : G[t] >= B} and R = B - G[T+1]; each bucket counts its
-//     entries above T and at T, two block scans give the level-T cut (the R
-//     lowest ids of score T, taken in bucket order) and every bucket's output
-//     offset, and the candidates are written in ascending id.
+//     run per cell); one walk over their ids places the low 12 bits of each
+//     into cb slots of its bucket;
+//  2. a wave takes a bucket: 4-bit scores are counted in the wave's 2 KB
+//     window (a 32-bit LDS atomic add of 1 << 4*(low & 7): an id occurs once
+//     per subspace and N_s <= 15, so no nibble carries), then every id claims
+//     its nibble with an atomic AND that clears it: the first claimant of a
+//     point gets its score, later ones get 0, and the window ends clear.  The
+//     bucket's points of score 1 replace its slots' front (the slots already
+//     read), those of score s >= 2 go to one list of the work-group as
+//     (id << 4 | s) and add one to H[s] (the histogram G[t] = #{score >= t});
+//  3. T = max{t : G[t] >= B} and R = B - G[T+1]: every listed point above T is
+//     a candidate, and of the points at T the R lowest ids.  Per bucket, its
+//     points at T (the front count when T = 1, else counted over the list); a
+//     block scan in bucket order gives each bucket's share of the R; buckets
+//     with all or none of theirs copy them, and the one bucket cut inside
+//     finds its cut id by marking its level-T ids in a 4096-bit map and
+//     counting.  Candidates are appended in no particular order.
 // A query is left to the tiled steps (route 1) when N_s > 15, it has more
-// than kSpMaxRuns activated cells, more points than kSpMaxRounds rounds hold
-// or a bucket larger than one round, or when T = 0 (fewer than B points
-// collide: the score-0 points are the tiled selection's case); otherwise
-// route 0, and the tiled collision and selection kernels skip the query.
+// than kSpMaxRuns activated cells, a bucket receives more than cb ids, more
+// than kSpHCap points score 2 or more, or T = 0 (fewer than B points collide:
+// the score-0 points are the tiled selection's case); otherwise route 0, and
+// the tiled collision and selection kernels skip the query.
 struct SparseLds {
-    uint32_t G[kSpMaxNs + 2];
+    uint32_t H[kSpMaxNs + 2];        // H[s]: points of score s >= 2
+    uint32_t sink[kWave];            // targets of the atomics of empty slots, one word per lane
     uint32_t red[2 * kSpWaves + 2];
-    uint32_t rb[kSpMaxRounds + 1];   // round r covers buckets [rb[r], rb[r+1])
-    int nruns, nrounds, flag;
+    uint32_t cpre[kSpMaxNs + 1];     // activated cells of the subspaces before i
+    uint32_t nh;                     // points in the list of scores >= 2 (may pass kSpHCap)
+    uint32_t out;                    // candidates written
+    int nruns, flag, cutb;
+    uint32_t cut;
 };
 
 // Every id of the query's activated cells, in runs: wave w takes runs w,
-// w + kSpWaves, ...; a run's ids are read by consecutive lanes, four loads in
-// flight per lane.
+// w + kSpWaves, ... two at a time, a run's ids read by consecutive lanes,
+// sixteen loads in flight per lane; f gets the sixteen ids, a bit mask of the
+// valid ones and a mask of the slots with a valid id in some lane (the same
+// in every lane, so f skips the others without divergence).  The loads are
+// unconditional (a slot past its run's end reads the run's first id, an empty
+// run's start is 0), so every id handed to f is a point id and none of the
+// loads waits for another.
+constexpr int kSpU = 8;
 template <class F>
 __device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, int nruns, F &&f) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    for (int r = w; r < nruns; r += kSpWaves) {
-        const uint2 rd = runs[r];
-        const uint32_t *src = a.ix.ids32 + rd.x;
-        for (uint32_t m = (uint32_t)lane; m < rd.y; m += 4u * kWave) {
-            uint32_t id[4];
+    for (int r = w; r < nruns; r += 2 * kSpWaves) {
+        const uint2 r0 = runs[r];
+        const uint2 r1 = r + kSpWaves < nruns ? runs[r + kSpWaves] : make_uint2(0u, 0u);
+        const uint32_t *s0 = a.ix.ids32 + r0.x, *s1 = a.ix.ids32 + r1.x;
+        const uint32_t len = r0.y > r1.y ? r0.y : r1.y;
+        for (uint32_t m0 = 0; m0 < len; m0 += (uint32_t)(kSpU * kWave)) {
+            const uint32_t m = m0 + (uint32_t)lane;
+            uint32_t id[2 * kSpU], vm = 0u, um = 0u;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t mm = m + (uint32_t)(u * kWave);
-                id[u] = mm < rd.y ? src[mm] : 0u;
+            for (int u = 0; u < kSpU; ++u) {
+                const uint32_t mm = m + (uint32_t)(u * kWave), mb = m0 + (uint32_t)(u * kWave);
+                id[u] = s0[mm < r0.y ? mm : 0u];
+                id[kSpU + u] = s1[mm < r1.y ? mm : 0u];
+                vm |= (mm < r0.y ? 1u : 0u) << u;
+                vm |= (mm < r1.y ? 1u : 0u) << (kSpU + u);
+                um |= (mb < r0.y ? 1u : 0u) << u;
+                um |= (mb < r1.y ? 1u : 0u) << (kSpU + u);
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (m + (uint32_t)(u * kWave) < rd.y) f(id[u]);
+            f(id, vm, um);
         }
     }
 }
 
-// One bucket by one wave (see step 3).  seg holds its len low ids; list is
-// the bucket's entry area (global); hc gathers the old values per level in
-// 16-bit fields.  Returns the number of entries written.
-__device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, const int b, const uint16_t *seg,
-                                              const uint32_t len, uint32_t *win, uint64_t (&hc)[4],
-                                              uint16_t *list) {
+// One bucket by one wave (step 2).  seg holds its len low ids and receives
+// its points of score 1 at the front; those of higher score go to the list
+// hl (capacity kSpHCap, count *hn); sink takes the atomics of empty slots.
+// Returns the number of points of score 1.
+__device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, const int b, uint16_t *seg,
+                                              const uint32_t len, uint32_t *win, uint32_t *hl, uint32_t *hn,
+                                              uint32_t *H, uint32_t *sink) {
     const int lane = threadIdx.x & (kWave - 1);
-    for (uint32_t j = (uint32_t)lane; j < len; j += kWave) {
-        const uint32_t u = seg[j];
-        const uint32_t sh = (u & 7u) << 2;
-        const uint32_t o = (atomicAdd(&win[u >> 3], 1u << sh) >> sh) & 15u;
-        const uint64_t one = 1ull << ((o & 3u) << 4);
-        if (o < 4u) hc[0] += one;
-        else if (o < 8u) hc[1] += one;
-        else if (o < 12u) hc[2] += one;
-        else hc[3] += one;
-    }
-    // lane l reads words 8l .. 8l + 7 (ids 64l .. 64l + 63 of the bucket) and clears them
-    uint4 *w4 = reinterpret_cast<uint4 *>(win) + 2 * lane;
-    uint32_t x[8];
-    {
-        const uint4 p0 = w4[0], p1 = w4[1];
-        x[0] = p0.x; x[1] = p0.y; x[2] = p0.z; x[3] = p0.w;
-        x[4] = p1.x; x[5] = p1.y; x[6] = p1.z; x[7] = p1.w;
-    }
-    uint32_t nz[8], cnt = 0;
+    constexpr int UQ = 4;
+    for (uint32_t j0 = 0; j0 < len; j0 += (uint32_t)(UQ * kWave)) {
+        uint32_t u[UQ];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        nz[k] = (x[k] | (x[k] >> 1) | (x[k] >> 2) | (x[k] >> 3)) & 0x11111111u;
-        cnt += (uint32_t)__popc(nz[k]);
-    }
-    if (cnt != 0u) {
-        w4[0] = make_uint4(0u, 0u, 0u, 0u);
-        w4[1] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    const uint32_t incl = wave_incl_scan(cnt);
-    uint16_t *dst = list + (incl - cnt);
+        for (int q = 0; q < UQ; ++q) {
+            const uint32_t j = j0 + (uint32_t)(q * kWave + lane);
+            u[q] = seg[j < len ? j : 0u];
+        }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        uint32_t m = nz[k];
-        while (m != 0u) {
-            const uint32_t nib = (uint32_t)__builtin_ctz(m) >> 2;
-            *dst++ = (uint16_t)((((x[k] >> (4u * nib)) & 15u) << kSpShift) | ((uint32_t)(8 * lane + k) * 8u + nib));
-            m &= m - 1u;
+        for (int q = 0; q < UQ; ++q) {
+            if (j0 + (uint32_t)(q * kWave) >= len) break;             // the same in every lane
+            const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
+            atomicAdd(v ? &win[u[q] >> 3] : &sink[lane], v ? 1u << ((u[q] & 7u) << 2) : 0u);
         }
     }
     if (a.scores != nullptr) {
-        // dense scores on request (parity tests): ids of this lane, below n
+        // dense scores on request (parity tests): lane l writes ids 64l .. 64l + 63 below n
         uint8_t *row = a.scores + (int64_t)ql * a.ix.P * a.ix.TILE;
         const int64_t id0 = (int64_t)b * kSpBucket + 64 * lane;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t x = win[8 * lane + k];
             for (int nib = 0; nib < 8; ++nib) {
                 const int64_t id = id0 + 8 * k + nib;
-                if (id < a.ix.n) row[id] = (uint8_t)((x[k] >> (4 * nib)) & 15u);
+                if (id < a.ix.n) row[id] = (uint8_t)((x >> (4 * nib)) & 15u);
             }
+        }
     }
-    return (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    // claims; the front entries written in a step lie below the step's end,
+    // whose slots were all read at the start of the step
+    uint32_t n1 = 0;
+    const uint32_t id0 = (uint32_t)b << kSpShift;
+    for (uint32_t j0 = 0; j0 < len; j0 += (uint32_t)(UQ * kWave)) {
+        uint32_t u[UQ], sv[UQ];
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const uint32_t j = j0 + (uint32_t)(q * kWave + lane);
+            u[q] = seg[j < len ? j : 0u];
+        }
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            sv[q] = 0u;
+            if (j0 + (uint32_t)(q * kWave) >= len) continue;          // the same in every lane
+            const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
+            const uint32_t sh = (u[q] & 7u) << 2;
+            const uint32_t old = atomicAnd(v ? &win[u[q] >> 3] : &sink[lane], v ? ~(15u << sh) : ~0u);
+            sv[q] = v ? (old >> sh) & 15u : 0u;
+        }
+        uint64_t mh[UQ];
+        uint32_t nh = 0;
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const uint64_t m1 = __ballot(sv[q] == 1u);
+            mh[q] = __ballot(sv[q] >= 2u);
+            nh += (uint32_t)__popcll(mh[q]);
+            if (sv[q] == 1u) seg[n1 + lanes_below(m1)] = (uint16_t)u[q];
+            n1 += (uint32_t)__popcll(m1);
+        }
+        if (nh) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(hn, nh);
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+#pragma unroll
+            for (int q = 0; q < UQ; ++q) {
+                if (sv[q] >= 2u) {
+                    const uint32_t at = base + lanes_below(mh[q]);
+                    if (at < (uint32_t)kSpHCap) hl[at] = ((id0 | u[q]) << 4) | sv[q];
+                    atomicAdd(&H[sv[q]], 1u);
+                }
+                base += (uint32_t)__popcll(mh[q]);
+            }
+        }
+    }
+    return n1;
 }
 
-// Entry pairs of a bucket's list, read past the L1 cache (the list was
-// written by other waves of this work-group).
-__device__ __forceinline__ uint32_t sp_load_pair(const uint16_t *list, uint32_t j2) {
-    const uint32_t *p = reinterpret_cast<const uint32_t *>(list) + j2;
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The id below which a set's `take` lowest ids lie (its take-th lowest + 1),
+// for ids inside one bucket: one wave marks their low bits in a 4096-bit map
+// (its clear window), counts set bits in id order and clears the map.
+// mark(j) returns the low id of element j, or kSpBucket to skip it.
+template <class M>
+__device__ __forceinline__ uint32_t sp_cut(uint32_t cnt, uint32_t take, uint32_t *bm, M &&mark) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (uint32_t j = (uint32_t)lane; j < cnt; j += kWave) {
+        const uint32_t lo = mark(j);
+        if (lo < (uint32_t)kSpBucket) atomicOr(&bm[lo >> 5], 1u << (lo & 31u));
+    }
+    const uint32_t w0 = bm[2 * lane], w1 = bm[2 * lane + 1];        // ids 64l .. 64l + 63
+    const uint32_t c = (uint32_t)(__popc(w0) + __popc(w1));
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t k = take - 1u;                                  // 0-based rank of the last taken
+    const uint64_t hit = __ballot(incl > k && incl - c <= k);
+    const int src = __builtin_ctzll(hit);
+    uint32_t cut = 0;
+    if (lane == src) {
+        uint64_t m = ((uint64_t)w1 << 32) | w0;
+        for (uint32_t r = k - (incl - c); r > 0; --r) m &= m - 1ull;
+        cut = (uint32_t)(64 * lane) + (uint32_t)__builtin_ctzll(m) + 1u;
+    }
+    bm[2 * lane] = 0u;
+    bm[2 * lane + 1] = 0u;
+    return (uint32_t)__builtin_amdgcn_readlane((int)cut, src);
+}
+
+// Append the selected ones of a wave's 64 candidates (one per lane) to the
+// query's list: one atomic per wave for the positions.
+__device__ __forceinline__ void sp_emit(bool t, uint32_t id, uint32_t *cq, uint32_t B, uint32_t *out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t m = __ballot(t);
+    if (m == 0ull) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(out, (uint32_t)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    const uint32_t at = base + lanes_below(m);
+    if (t && at < B) cq[at] = id;
 }
 
 __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
@@ -1019,205 +1035,183 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
     __shared__ SparseLds S;
     const int NB = a.ix.NB, ns = a.ix.ns, K = a.ix.K;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, length)
     const int NBp = sp_nb_padded(NB);
-    uint32_t *boff = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);      // [NB+1] bucket starts, then output offsets
-    uint32_t *bfill = boff + NBp;                                          // [NB] fill pointers, then entry counts
-    uint32_t *bx = bfill + NBp;                                            // [NB] above-T | at-T << 16, then takes
+    uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, length)
+    uint32_t *bfill = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);     // [NB] ids per bucket
+    uint32_t *bx = bfill + NBp;                                            // [NB] points of score 1, then level-T points
     uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
-    uint16_t *raw = reinterpret_cast<uint16_t *>(win_all + kSpWaves * kSpWords);
+    uint32_t *hl = win_all + kSpWaves * kSpWords;                          // [kSpHCap] (id << 4 | score), score >= 2
+    uint16_t *raw = reinterpret_cast<uint16_t *>(hl + kSpHCap);            // [NB][cb] low ids, then score-1 points
     uint32_t *win = win_all + w * kSpWords;
-    const uint32_t cap = (uint32_t)a.sp_cap;
+    const uint32_t cb = ((uint32_t)a.sp_cap / (uint32_t)NB) & ~1u;         // slots per bucket
     const int nq = pass_nq(a.nq_dev, a.q_base, a.nq);
-    const int64_t lstride = (int64_t)a.ix.P * a.ix.TILE;
+    const int per = (NB + kSpThreads - 1) / kSpThreads;
+    const int b0t = tid * per < NB ? tid * per : NB, b1t = b0t + per < NB ? b0t + per : NB;
     for (int j = tid; j < kSpWaves * kSpWords; j += kSpThreads) win_all[j] = 0u;
+    for (int j = tid; j < kWave; j += kSpThreads) S.sink[j] = 0u;
     for (int rq = blockIdx.x; rq < nq; rq += gridDim.x) {
         const int ql = a.order ? a.order[rq] : rq;
-        // ---- runs of the activated cells
-        if (tid == 0) {
-            uint32_t m = 0;
-            int nr = 0;
-            for (int i = 0; i < ns; ++i) {
-                m += (uint32_t)a.aprime[ql * ns + i];
-                nr += a.ncells[ql * ns + i];
+        // ---- the query's size: activated cells (wave 0, a lane per subspace)
+        if (w == 0) {
+            const bool on = lane < ns && ns <= kSpMaxNs;
+            const uint32_t c = on ? (uint32_t)a.ncells[ql * ns + lane] : 0u;
+            const uint32_t ci = wave_incl_scan(c);
+            if (lane <= kSpMaxNs) S.cpre[lane] = ci - c;
+            const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
+            if (lane == 0) {
+                S.nruns = (int)nr;
+                S.flag = (ns > kSpMaxNs || nr > (uint32_t)kSpMaxRuns || cb == 0u) ? 1 : 0;
+                S.nh = 0u;
+                S.out = 0u;
             }
-            S.nruns = nr;
-            S.flag = (ns > kSpMaxNs || nr > kSpMaxRuns || m > (uint32_t)kSpMaxRounds * cap) ? 1 : 0;
         }
-        for (int t = tid; t < ns + 2; t += kSpThreads) S.G[t] = 0u;
-        for (int b = tid; b <= NB; b += kSpThreads) boff[b] = 0u;
+        for (int t = tid; t < kSpMaxNs + 2; t += kSpThreads) S.H[t] = 0u;
+        for (int b = tid; b < NB; b += kSpThreads) bfill[b] = 0u;
         __syncthreads();
         if (S.flag) {
             if (tid == 0) a.route[ql] = 1;
             __syncthreads();
             continue;
         }
+        // ---- runs of the activated cells
         const int nruns = S.nruns;
         for (int r = tid; r < nruns; r += kSpThreads) {
-            int i = 0, j = r;
-            while (j >= a.ncells[ql * ns + i]) j -= a.ncells[ql * ns + i++];
+            int i = 0;
+            while (i + 1 < ns && S.cpre[i + 1] <= (uint32_t)r) ++i;
+            const int j = r - (int)S.cpre[i];
             const int c = a.cells[((int64_t)ql * ns + i) * K + j];
             const uint32_t *co = a.ix.coffs + (int64_t)i * (K + 1);
-            const uint32_t s = co[c];
-            runs[r] = make_uint2((uint32_t)((int64_t)i * a.ix.n) + s, co[c + 1] - s);
+            const uint32_t st = co[c], len = co[c + 1] - st;
+            runs[r] = make_uint2(len ? (uint32_t)((int64_t)i * a.ix.n) + st : 0u, len);
         }
         __syncthreads();
-        // ---- 1. points per bucket
-        sp_walk(a, runs, nruns, [&](uint32_t id) { atomicAdd(&boff[id >> kSpShift], 1u); });
-        __syncthreads();
-        // exclusive scan over the buckets: thread t owns a contiguous block of them
-        const int per = (NB + kSpThreads - 1) / kSpThreads;
-        const int b0t = tid * per < NB ? tid * per : NB, b1t = b0t + per < NB ? b0t + per : NB;
-        {
-            uint32_t local = 0, big = 0;
-            for (int b = b0t; b < b1t; ++b) {
-                local += boff[b];
-                big |= boff[b] > cap ? 1u : 0u;
-            }
-            uint32_t tot;
-            uint32_t run = block_excl_scan<kSpThreads>(local, S.red, &tot);
-            const uint32_t anybig = __syncthreads_or(big != 0u);
-            for (int b = b0t; b < b1t; ++b) {
-                const uint32_t v = boff[b];
-                boff[b] = run;
-                run += v;
-            }
-            if (tid == 0) {
-                boff[NB] = tot;
-                S.flag = anybig ? 1 : 0;
-            }
-        }
-        __syncthreads();
-        if (S.flag) {
-            if (tid == 0) a.route[ql] = 1;
-            __syncthreads();
-            continue;
-        }
-        // rounds: the longest run of buckets from each start whose ids fit
-        if (tid == 0) {
-            int r = 0, st = 0;
-            S.rb[0] = 0;
-            while (st < NB && r < kSpMaxRounds) {
-                int lo = st + 1, hi = NB;            // largest e with boff[e] - boff[st] <= cap
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (boff[mid] - boff[st] <= cap) lo = mid; else hi = mid - 1;
-                }
-                S.rb[++r] = (uint32_t)lo;
-                st = lo;
-            }
-            S.nrounds = r;
-            S.flag = st < NB ? 1 : 0;
-        }
-        __syncthreads();
-        if (S.flag) {
-            if (tid == 0) a.route[ql] = 1;
-            __syncthreads();
-            continue;
-        }
-        // ---- 2 and 3: rounds of placement and bucket counting
-        uint16_t *qlist = a.lvl + (int64_t)ql * lstride;
-        uint64_t hc[4] = {0ull, 0ull, 0ull, 0ull};
-        for (int r = 0; r < S.nrounds; ++r) {
-            const int bb0 = (int)S.rb[r], bb1 = (int)S.rb[r + 1];
-            const uint32_t base = boff[bb0];
-            for (int b = bb0 + tid; b < bb1; b += kSpThreads) bfill[b] = boff[b] - base;
-            __syncthreads();
-            sp_walk(a, runs, nruns, [&](uint32_t id) {
-                const int b = (int)(id >> kSpShift);
-                if (b >= bb0 && b < bb1) raw[atomicAdd(&bfill[b], 1u)] = (uint16_t)(id & (kSpBucket - 1));
-            });
-            __syncthreads();
-            for (int b = bb0 + w; b < bb1; b += kSpWaves) {
-                const uint32_t st = boff[b] - base, len = boff[b + 1] - boff[b];
-                const uint32_t ne = sp_bucket(a, ql, b, raw + st, len, win, hc, qlist + (int64_t)b * kSpBucket);
-                if (lane == 0) bfill[b] = ne;
-            }
-            __syncthreads();
-        }
-        // ---- 4. threshold, level-T cut, candidates
+        // ---- 1. one walk into cb slots per bucket (every id is counted; the
+        // query is left to the tiled steps if a bucket overflows); all sixteen
+        // atomics of a step are issued before the stores they place
+        sp_walk(a, runs, nruns, [&](const uint32_t (&id)[2 * kSpU], uint32_t vm, uint32_t um) {
+            uint32_t pos[2 * kSpU];
 #pragma unroll
-        for (int t = 1; t <= kSpMaxNs; ++t) {
-            if (t > ns) break;
-            const uint32_t f = (uint32_t)(hc[(t - 1) >> 2] >> (((t - 1) & 3) * 16)) & 0xffffu;
-            const uint32_t sum = wave_sum(f);
-            if (lane == 0 && sum) atomicAdd(&S.G[t], sum);
-        }
-        __threadfence();                 // the entry lists reach L2 before other waves read them
+            for (int u = 0; u < 2 * kSpU; ++u) {
+                const bool v = (vm >> u) & 1u;
+                pos[u] = 0u;
+                if ((um >> u) & 1u) pos[u] = atomicAdd(v ? &bfill[id[u] >> kSpShift] : &S.sink[lane], v ? 1u : 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 2 * kSpU; ++u)
+                if (((vm >> u) & 1u) && pos[u] < cb)
+                    raw[(id[u] >> kSpShift) * cb + pos[u]] = (uint16_t)(id[u] & (kSpBucket - 1));
+        });
         __syncthreads();
+        bool over = false;
+        for (int b = b0t; b < b1t; ++b) over |= bfill[b] > cb;
+        if (__syncthreads_or(over)) {
+            if (tid == 0) a.route[ql] = 1;
+            __syncthreads();
+            continue;
+        }
+        // ---- 2. every bucket
+        for (int b = w; b < NB; b += kSpWaves) {
+            const uint32_t n1 = sp_bucket(a, ql, b, raw + b * cb, bfill[b], win, hl, &S.nh, S.H, S.sink);
+            if (lane == 0) bx[b] = n1;
+        }
+        __syncthreads();
+        // ---- 3. threshold: G[t] = sum of H[s] for s >= t >= 2; G[1] adds the score-1 points
         const uint32_t B = (uint32_t)a.B;
         int T = 0;
-        for (int t = ns; t >= 1; --t)
-            if (S.G[t] >= B) { T = t; break; }
-        if (T == 0) {
+        uint32_t GT1 = 0;                    // G[T + 1]
+        {
+            uint32_t g = 0;
+            for (int t = ns; t >= 2; --t) {
+                if (g + S.H[t] >= B) { T = t; GT1 = g; break; }
+                g += S.H[t];
+            }
+            if (T == 0) {
+                uint32_t e = 0;
+                for (int b = b0t; b < b1t; ++b) e += bx[b];
+                e = block_sum<kSpThreads>(e, S.red);
+                if (g + e >= B) { T = 1; GT1 = g; }
+            }
+        }
+        const uint32_t nhl = S.nh;
+        if (T == 0 || nhl > (uint32_t)kSpHCap) {
             if (tid == 0) a.route[ql] = 1;
             __syncthreads();
             continue;
         }
-        const uint32_t R = B - S.G[T + 1];
-        for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t ne = bfill[b];
-            const uint16_t *list = qlist + (int64_t)b * kSpBucket;
-            uint32_t gt = 0, eq = 0;
-            for (uint32_t j2 = (uint32_t)lane; 2 * j2 < ne; j2 += kWave) {
-                const uint32_t pr = sp_load_pair(list, j2);
-                const uint32_t s0 = (pr & 0xffffu) >> kSpShift, s1 = pr >> (16 + kSpShift);
-                gt += (s0 > (uint32_t)T) + (2 * j2 + 1 < ne && s1 > (uint32_t)T);
-                eq += (s0 == (uint32_t)T) + (2 * j2 + 1 < ne && s1 == (uint32_t)T);
-            }
-            gt = wave_sum(gt);
-            eq = wave_sum(eq);
-            if (lane == 0) bx[b] = gt | (eq << 16);
+        const uint32_t R = B - GT1;
+        // level-T points per bucket: the score-1 counts, or counted over the list
+        if (T > 1) {
+            for (int b = b0t; b < b1t; ++b) bx[b] = 0u;
+            __syncthreads();
+            for (uint32_t j = (uint32_t)tid; j < nhl; j += kSpThreads)
+                if ((hl[j] & 15u) == (uint32_t)T) atomicAdd(&bx[hl[j] >> (4 + kSpShift)], 1u);
+            __syncthreads();
         }
-        __syncthreads();
+        // each bucket's share of the R lowest level-T ids (bfill: take), and the cut bucket
         {
             uint32_t eql = 0;
-            for (int b = b0t; b < b1t; ++b) eql += bx[b] >> 16;
+            for (int b = b0t; b < b1t; ++b) eql += bx[b];
             uint32_t tot;
             uint32_t eb = block_excl_scan<kSpThreads>(eql, S.red, &tot);
-            uint32_t outl = 0;
             for (int b = b0t; b < b1t; ++b) {
-                const uint32_t gt = bx[b] & 0xffffu, eq = bx[b] >> 16;
+                const uint32_t eq = bx[b];
                 const uint32_t take = eb >= R ? 0u : (R - eb < eq ? R - eb : eq);
                 eb += eq;
-                boff[b] = gt + take;         // this bucket's candidates
-                bx[b] = take;
-                outl += gt + take;
+                bfill[b] = take;
             }
-            uint32_t ob = block_excl_scan<kSpThreads>(outl, S.red, &tot);
-            for (int b = b0t; b < b1t; ++b) {
-                const uint32_t v = boff[b];
-                boff[b] = ob;
-                ob += v;
-            }
+            if (tid == 0) S.cutb = -1;
         }
         __syncthreads();
+        // the cut bucket: the one (at most) that takes some but not all of its level-T points
+        for (int b = b0t; b < b1t; ++b)
+            if (bfill[b] != 0u && bfill[b] != bx[b]) S.cutb = b;
+        __syncthreads();
+        const int cutb = S.cutb;
+        if (w == 0) {
+            uint32_t cut = 0;
+            if (cutb >= 0) {
+                const uint32_t take = bfill[cutb];
+                if (T == 1) {
+                    const uint16_t *f = raw + cutb * cb;
+                    cut = sp_cut(bx[cutb], take, win, [&](uint32_t j) { return (uint32_t)f[j]; });
+                } else {
+                    cut = sp_cut(nhl, take, win, [&](uint32_t j) {
+                        const uint32_t e = hl[j];
+                        return ((e & 15u) == (uint32_t)T && (int)(e >> (4 + kSpShift)) == cutb)
+                                   ? (e >> 4) & (kSpBucket - 1) : (uint32_t)kSpBucket;
+                    });
+                }
+            }
+            if (lane == 0) S.cut = cut;
+        }
+        __syncthreads();
+        const uint32_t cut = S.cut;
+        // ---- candidates: the listed points above T, and the level-T points of
+        // buckets before the cut bucket and below the cut inside it
         uint32_t *cq = a.cand + (int64_t)ql * a.B;
-        const uint64_t below = (1ull << lane) - 1ull;
-        for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t ne = bfill[b], take = bx[b];
-            const uint16_t *list = qlist + (int64_t)b * kSpBucket;
-            uint32_t pos = boff[b], eqseen = 0;
-            const uint32_t id0 = (uint32_t)b << kSpShift;
-            for (uint32_t c0 = 0; c0 < ne; c0 += 2 * kWave) {
-                const uint32_t j2 = c0 / 2 + (uint32_t)lane;
-                const bool v0 = 2 * j2 < ne, v1 = 2 * j2 + 1 < ne;
-                const uint32_t pr = v0 ? sp_load_pair(list, j2) : 0u;
-                const uint32_t e0 = pr & 0xffffu, e1 = pr >> 16;
-                const uint32_t s0 = e0 >> kSpShift, s1 = e1 >> kSpShift;
-                const bool q0 = v0 && s0 == (uint32_t)T, q1 = v1 && s1 == (uint32_t)T;
-                // level-T rank of the lane's first entry inside the bucket
-                const uint64_t m0 = __ballot(q0), m1 = __ballot(q1);
-                const uint32_t r0 = eqseen + (uint32_t)__popcll(m0 & below) + (uint32_t)__popcll(m1 & below);
-                const bool t0 = (v0 && s0 > (uint32_t)T) || (q0 && r0 < take);
-                const bool t1 = (v1 && s1 > (uint32_t)T) || (q1 && r0 + (q0 ? 1u : 0u) < take);
-                const uint64_t k0 = __ballot(t0), k1 = __ballot(t1);
-                uint32_t at = pos + (uint32_t)__popcll(k0 & below) + (uint32_t)__popcll(k1 & below);
-                if (t0 && at < B) cq[at] = id0 | (e0 & (kSpBucket - 1));
-                at += t0 ? 1u : 0u;
-                if (t1 && at < B) cq[at] = id0 | (e1 & (kSpBucket - 1));
-                pos += (uint32_t)(__popcll(k0) + __popcll(k1));
-                eqseen += (uint32_t)(__popcll(m0) + __popcll(m1));
+        auto take_t = [&](uint32_t id) {
+            const int b = (int)(id >> kSpShift);
+            return bfill[b] == bx[b] ? bfill[b] != 0u : (b == cutb && (id & (kSpBucket - 1)) < cut);
+        };
+        for (uint32_t j0 = (uint32_t)(w * kWave); j0 < nhl; j0 += (uint32_t)kSpThreads) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            const uint32_t e = hl[j < nhl ? j : 0u];
+            const uint32_t sv = e & 15u, id = e >> 4;
+            const bool t = j < nhl && (sv > (uint32_t)T || (sv == (uint32_t)T && take_t(id)));
+            sp_emit(t, id, cq, B, &S.out);
+        }
+        if (T == 1) {
+            for (int b = w; b < NB; b += kSpWaves) {
+                const uint32_t take = bfill[b], n1 = bx[b];
+                if (take == 0u) continue;
+                const uint16_t *f = raw + b * cb;
+                const uint32_t id0 = (uint32_t)b << kSpShift;
+                const uint32_t lim = take == n1 ? (uint32_t)kSpBucket : cut;
+                for (uint32_t j0 = 0; j0 < n1; j0 += kWave) {
+                    const uint32_t j = j0 + (uint32_t)lane;
+                    const uint32_t lo = f[j < n1 ? j : 0u];
+                    sp_emit(j < n1 && lo < lim, id0 | lo, cq, B, &S.out);
+                }
             }
         }
         if (tid == 0) a.route[ql] = 0;

@@ -66,13 +66,13 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->want_bf16 = p && (p->flags & SUCO_BUILD_BF16);
     ix->tile_req = p ? p->tile_max : 0;
     ix->chunk_req = p ? std::max(0, p->query_chunk) : 0;
-    // The sparse collision step: two work-groups per CU (160 KB of LDS per CU on
-    // gfx950), each with its tables, windows and as many ids per round as fit.
+    // The sparse collision step: one work-group per CU (160 KB of LDS per CU on
+    // gfx950) with its tables, windows and as many ids as fit.
     ix->NB = (int)((n + kSpBucket - 1) / kSpBucket);
     if (!ix->no_sparse && ns <= kSpMaxNs && ix->NB <= kSpMaxBuckets) {
         const int sps = sparse_static_lds();
         if (sps < 0) { delete ix; return fail(SUCO_E_HIP, "cannot query the sparse collision kernel's attributes"); }
-        const int64_t budget = std::min<int64_t>(max_lds, 160 * 1024 / 2) - sps;
+        const int64_t budget = std::min<int64_t>(max_lds, 160 * 1024) - sps;
         const int64_t cap = (budget - (int64_t)sp_lds_bytes(ix->NB, 0)) / 2 / 8 * 8;
         ix->sp_cap = cap >= 4096 ? (int)std::min<int64_t>(cap, 1 << 20) : 0;
     }
@@ -425,18 +425,6 @@ int load_index(const char *path, const suco_build_params *pin, hipStream_t st, s
 }
 
 // ------------------------------------------------------------ workspace --
-struct Carve {
-    char *base;
-    size_t off = 0;
-    template <class T>
-    T *take(size_t count) {
-        off = (off + 255) & ~size_t(255);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += sizeof(T) * std::max<size_t>(count, 1);
-        return p;
-    }
-};
-
 struct Work {
     uint16_t *cells; int32_t *ncells, *aprime; float *feat; uint32_t *hist; uint16_t *lvl; uint8_t *scores;
     uint32_t *cand; uint64_t *part_keys; int32_t *order, *route;
@@ -451,7 +439,8 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.aprime = c.take<int32_t>(C * ix->ns);
     w.feat = c.take<float>(C * 2 * ix->ns);
     w.hist = c.take<uint32_t>(C * ix->P * (ix->ns + 2));
-    w.lvl = c.take<uint16_t>(C * (size_t)ix->P * ix->TILE);
+    // (the sparse step's unconditional loads may read up to one bucket past a row's end)
+    w.lvl = c.take<uint16_t>(C * (size_t)ix->P * ix->TILE + 2 * kSpBucket);
     w.scores = dense ? c.take<uint8_t>(C * (size_t)ix->P * ix->TILE) : nullptr;
     w.cand = c.take<uint32_t>(C * (size_t)B);
     w.order = c.take<int32_t>(C);
@@ -459,18 +448,6 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
     if (bytes) *bytes = c.off;
     return w;
-}
-
-int ensure_arena(suco_index *ix, size_t bytes) {
-    if (bytes <= ix->arena_bytes) return SUCO_OK;
-    if (ix->pending) HIPCHECK(hipEventSynchronize(ix->done));
-    if (ix->arena) (void)hipFree(ix->arena);
-    ix->arena = nullptr;
-    ix->arena_bytes = 0;
-    int rc = dev_alloc(&ix->arena, bytes);
-    if (rc) return rc;
-    ix->arena_bytes = bytes;
-    return SUCO_OK;
 }
 
 struct DebugOut {

@@ -200,6 +200,33 @@ hipError_t timed(suco_index *ix, int stage, hipStream_t st, F &&fn) {
 }
 
 
+// Consecutive 256-byte-aligned buffers carved out of one allocation (base ==
+// null: only the total size is computed, in off).
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * std::max<size_t>(count, 1);
+        return p;
+    }
+};
+
+// Grow the index's query workspace to `bytes` (waiting for the queries that use it).
+inline int ensure_arena(suco_index *ix, size_t bytes) {
+    if (bytes <= ix->arena_bytes) return SUCO_OK;
+    if (ix->pending) HIPCHECK(hipEventSynchronize(ix->done));
+    if (ix->arena) (void)hipFree(ix->arena);
+    ix->arena = nullptr;
+    ix->arena_bytes = 0;
+    int rc = dev_alloc(&ix->arena, bytes);
+    if (rc) return rc;
+    ix->arena_bytes = bytes;
+    return SUCO_OK;
+}
+
 // the collision kernel (512 threads) takes this many runs of every subspace per batch
 inline int runs_per_sub(int ns) {
     int r = 1;

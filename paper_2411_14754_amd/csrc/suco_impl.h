@@ -34,23 +34,24 @@ struct IndexView {
 };
 
 // Sparse collision step (query_kernels.hip): ids are grouped in buckets of
-// 4096 consecutive ids, one 2 KB window of 4-bit scores per wave.
+// 4096 consecutive ids, one 2 KB window of 4-bit scores per wave, one
+// work-group of 1024 threads per CU with all of its LDS.
 constexpr int kSpShift = 12;
 constexpr int kSpBucket = 1 << kSpShift;
-constexpr int kSpThreads = 512;
+constexpr int kSpThreads = 1024;
 constexpr int kSpWaves = kSpThreads / kWave;
 constexpr int kSpWords = kSpBucket / 8;
 constexpr int kSpMaxNs = 15;        // a 4-bit score
 constexpr int kSpMaxBuckets = 4096; // n <= 2^24
 constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
-constexpr int kSpMaxRounds = 4;     // LDS fillings per query
-// Dynamic LDS of the sparse step for NB buckets and `cap` ids per round: the
-// run table, three per-bucket arrays of NB + 1 words padded to 16 bytes, the
-// waves' score windows and the round's low ids.
+constexpr int kSpHCap = 4096;       // points of score >= 2 a query may list
+// Dynamic LDS of the sparse step for NB buckets and `cap` slots: the run
+// table, two per-bucket arrays padded to 16 bytes, the waves' score windows,
+// the list of points of score >= 2 and the slots.
 __host__ __device__ inline int sp_nb_padded(int NB) { return (NB + 4) & ~3; }
 __host__ __device__ inline size_t sp_lds_bytes(int NB, int cap) {
-    return 8 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
-           2 * (size_t)((cap + 7) & ~7);
+    return 8 * (size_t)kSpMaxRuns + 8 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
+           4 * (size_t)kSpHCap + 2 * (size_t)((cap + 7) & ~7);
 }
 
 // One pass of the query path over a chunk of queries.

@@ -33,6 +33,11 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
 }
 
+// Set bits of a 64-bit wave mask in the lanes below this one (v_mbcnt).
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Sum over the 64 lanes, the same in every lane (all lanes active).
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), kWave - 1);
@@ -73,6 +78,67 @@ __device__ __forceinline__ void topk_insert(uint64_t &best, uint64_t kk, int k, 
             else if (lane > pos) best = up;
         }
     }
+}
+
+// Sum over the block; every thread gets the total.  Like the scans below, it
+// is called by every thread of the block.
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red) {
+    v = wave_sum(v);
+    if constexpr (NT == kWave) {
+        return v;
+    } else {
+        __syncthreads();
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+        __syncthreads();
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < NT / kWave; ++j) s += red[j];
+        return s;
+    }
+}
+
+// Exclusive prefix over threads in index order; *total gets the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t x = wave_incl_scan(v);
+    __syncthreads();
+    if (lane == kWave - 1) red[w] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < NT / kWave; ++j) {
+        uint32_t r = red[j];
+        base += (j < w) ? r : 0u;
+        tot += r;
+    }
+    *total = tot;
+    return base + x - v;
+}
+
+// Two exclusive prefixes at once (one pass of barriers); *ta, *tb get the sums.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint32_t *red2, uint32_t *ea,
+                                                 uint32_t *eb, uint32_t *ta, uint32_t *tb) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t xa = wave_incl_scan(va), xb = wave_incl_scan(vb);
+    __syncthreads();
+    if (lane == kWave - 1) { red2[2 * w] = xa; red2[2 * w + 1] = xb; }
+    __syncthreads();
+    uint32_t ba = 0, bb = 0, sa = 0, sb = 0;
+#pragma unroll
+    for (int j = 0; j < NT / kWave; ++j) {
+        const uint32_t ra = red2[2 * j], rb = red2[2 * j + 1];
+        ba += (j < w) ? ra : 0u;
+        bb += (j < w) ? rb : 0u;
+        sa += ra;
+        sb += rb;
+    }
+    *ea = ba + xa - va;
+    *eb = bb + xb - vb;
+    *ta = sa;
+    *tb = sb;
 }
 
 }  // namespace suco
