@@ -50,6 +50,8 @@ def lib():
         L.so_layout.argtypes = [i32, i32, P, P]
         L.so_init_ids.argtypes = [P, i64, i32, i32, i32, i32, C.c_uint64, i32, P]
         L.so_kmeans.argtypes = [P, i64, i32, i32, i32, i32, i32, P, P, P, P, i32]
+        L.so_kmedians.argtypes = [P, i64, i32, i32, i32, i32, i32, P, P, P, P, i32]
+        L.so_build_metric.argtypes = [P, i64, i32, i32, i32, i32, C.c_uint64, i32, P, P, P, P, i32]
         L.so_build.argtypes = [P, i64, i32, i32, i32, i32, C.c_uint64, P, P, P, P, i32]
         L.so_index_create.restype = P
         L.so_index_create.argtypes = [P, i64, i32, i32, i32, P, P]
@@ -66,15 +68,18 @@ def lib():
         L.so_da_trace.argtypes = [P, i32, P, P, P, P, i64, P, P, P]
         L.so_select.argtypes = [P, i64, i64, P]
         L.so_rerank.argtypes = [P, i32, P, P, i64, i32, P, P]
+        L.so_rerank_metric.argtypes = [P, i32, P, P, i64, i32, i32, P, P]
         L.so_query.argtypes = [P, P, i64, i32, P, C.c_double, i32, P, P, P, P, P, P, i32]
         L.so_query_cells.restype = i64
         L.so_query_cells.argtypes = [P, P, i32, C.c_double, i32, P, P, P, P, P, P]
-        L.so_sclinear.argtypes = [P, i64, i32, i32, P, i64, i32, C.c_double, C.c_double, P, P, P, i32]
+        L.so_sclinear_metric.argtypes = [P, i64, i32, i32, P, i64, i32, C.c_double, C.c_double, i32, P, P, P, i32]
         L.so_bruteforce.argtypes = [P, i64, i32, P, i64, i32, P, P, i32]
+        L.so_bruteforce_metric.argtypes = [P, i64, i32, P, i64, i32, i32, P, P, i32]
         L.so_bf16.restype = C.c_double
         L.so_bf16.argtypes = [C.c_float]
         L.so_bf16_round.argtypes = [P, i64, P]
         L.so_index_set_s1_bf16.argtypes = [P, i32]
+        L.so_index_set_metric.argtypes = [P, i32]
         _lib = L
     return _lib
 
@@ -111,29 +116,32 @@ def init_ids(X: np.ndarray, ns: int, sk: int, seed: int, g: int) -> np.ndarray:
     return out
 
 
-def kmeans(X, dim0, w, sk, iters, init, nthreads=None):
+def kmeans(X, dim0, w, sk, iters, init, nthreads=None, metric=0):
+    """Lloyd's k-means on one half (metric 0), or k-medians under L1 (metric 1, SuCo-L1)."""
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     cent = np.zeros((sk, w), np.float64)
     assign = np.zeros(n, np.int32)
     obj = np.zeros(iters + 1, np.float64)
     init = np.ascontiguousarray(init, np.int64)
-    rc = lib().so_kmeans(_p(X), n, d, dim0, w, sk, iters, _p(init), _p(cent), _p(assign), _p(obj),
-                         nthreads or default_threads())
+    fn = lib().so_kmedians if metric else lib().so_kmeans
+    rc = fn(_p(X), n, d, dim0, w, sk, iters, _p(init), _p(cent), _p(assign), _p(obj),
+            nthreads or default_threads())
     assert rc == 0
     return cent, assign, obj
 
 
-def build_index(X: np.ndarray, ns: int, sk: int, iters: int = 25, seed: int = 1, nthreads=None):
-    """Alg. 2: returns (cent64 [sk*d], cent32 [sk*d], assign int32 [2ns][n], obj [2ns][iters+1])."""
+def build_index(X: np.ndarray, ns: int, sk: int, iters: int = 25, seed: int = 1, nthreads=None, metric=0):
+    """Alg. 2: returns (cent64 [sk*d], cent32 [sk*d], assign int32 [2ns][n], obj [2ns][iters+1]).
+    metric 1 (SuCo-L1) clusters with k-medians under L1."""
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     c64 = np.zeros(sk * d, np.float64)
     c32 = np.zeros(sk * d, np.float32)
     asg = np.zeros((2 * ns, n), np.int32)
     obj = np.zeros((2 * ns, iters + 1), np.float64)
-    rc = lib().so_build(_p(X), n, d, ns, sk, iters, C.c_uint64(seed), _p(c64), _p(c32), _p(asg),
-                        _p(obj), nthreads or default_threads())
+    rc = lib().so_build_metric(_p(X), n, d, ns, sk, iters, C.c_uint64(seed), int(metric), _p(c64), _p(c32),
+                               _p(asg), _p(obj), nthreads or default_threads())
     assert rc == 0
     return c64, c32, asg, obj
 
@@ -141,7 +149,8 @@ def build_index(X: np.ndarray, ns: int, sk: int, iters: int = 25, seed: int = 1,
 class Index:
     """The oracle's index over X with given FP32 centres and assignments."""
 
-    def __init__(self, X, ns, sk, cent32, assign):
+    def __init__(self, X, ns, sk, cent32, assign, metric=0):
+        self.metric = int(metric)
         self.X = np.ascontiguousarray(X, np.float32)
         self.n, self.d = self.X.shape
         self.ns, self.sk, self.K = ns, sk, sk * sk
@@ -150,6 +159,7 @@ class Index:
         self.h = lib().so_index_create(_p(self.X), self.n, self.d, ns, sk, _p(self.cent32), _p(self.assign))
         if not self.h:
             raise MemoryError("oracle index")
+        lib().so_index_set_metric(self.h, self.metric)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -236,17 +246,17 @@ def select(scores: np.ndarray, B: int) -> np.ndarray:
     return out
 
 
-def rerank(X, q, cand, k):
+def rerank(X, q, cand, k, metric=0):
     X = np.ascontiguousarray(X, np.float32)
     q = np.ascontiguousarray(q, np.float32)
     cand = np.ascontiguousarray(cand, np.int32)
     ids = np.zeros(k, np.int32)
     dist = np.zeros(k, np.float64)
-    lib().so_rerank(_p(X), X.shape[1], _p(q), _p(cand), cand.shape[0], k, _p(ids), _p(dist))
+    lib().so_rerank_metric(_p(X), X.shape[1], _p(q), _p(cand), cand.shape[0], k, int(metric), _p(ids), _p(dist))
     return ids, dist
 
 
-def sclinear(X, ns, Q, k, alpha, beta, want_scores=False, nthreads=None):
+def sclinear(X, ns, Q, k, alpha, beta, want_scores=False, nthreads=None, metric=0):
     X = np.ascontiguousarray(X, np.float32)
     Q = np.ascontiguousarray(Q, np.float32).reshape(-1, X.shape[1])
     n, d = X.shape
@@ -254,18 +264,19 @@ def sclinear(X, ns, Q, k, alpha, beta, want_scores=False, nthreads=None):
     ids = np.zeros((nq, k), np.int32)
     dist = np.zeros((nq, k), np.float64)
     sc = np.zeros((nq, n), np.uint8) if want_scores else None
-    lib().so_sclinear(_p(X), n, d, ns, _p(Q), nq, k, float(alpha), float(beta), _p(ids), _p(dist),
-                      _p(sc) if sc is not None else None, nthreads or default_threads())
+    lib().so_sclinear_metric(_p(X), n, d, ns, _p(Q), nq, k, float(alpha), float(beta), int(metric), _p(ids),
+                             _p(dist), _p(sc) if sc is not None else None, nthreads or default_threads())
     return (ids, dist, sc) if want_scores else (ids, dist)
 
 
-def bruteforce(X, Q, k, nthreads=None):
+def bruteforce(X, Q, k, nthreads=None, metric=0):
+    """Exact k-NN by (distance, id): Euclidean (metric 0) or Manhattan (metric 1)."""
     X = np.ascontiguousarray(X, np.float32)
     Q = np.ascontiguousarray(Q, np.float32).reshape(-1, X.shape[1])
     ids = np.zeros((Q.shape[0], k), np.int32)
     dist = np.zeros((Q.shape[0], k), np.float64)
-    lib().so_bruteforce(_p(X), X.shape[0], X.shape[1], _p(Q), Q.shape[0], k, _p(ids), _p(dist),
-                        nthreads or default_threads())
+    lib().so_bruteforce_metric(_p(X), X.shape[0], X.shape[1], _p(Q), Q.shape[0], k, int(metric), _p(ids),
+                               _p(dist), nthreads or default_threads())
     return ids, dist
 
 

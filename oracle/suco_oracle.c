@@ -100,23 +100,24 @@ EXPORT void so_init_ids(const float *X, int64_t n, int d, int dim0, int w, int s
     }
 }
 
-/* Squared Euclidean distance of row p's half (dims dim0..dim0+w) to centre c,
- * summed in dimension order. */
-static double half_dist2(const float *X, int d, int64_t p, int dim0, int w, const double *c) {
+/* Distance of row p's half (dims dim0..dim0+w) to centre c, summed in
+ * dimension order: the squared Euclidean distance (metric 0) or the
+ * Manhattan distance (metric 1, SuCo-L1 of Sec. 5.3). */
+static double half_dist(const float *X, int d, int64_t p, int dim0, int w, const double *c, int metric) {
     double s = 0.0;
     for (int j = 0; j < w; ++j) {
         double t = (double)X[p * d + dim0 + j] - c[j];
-        s += t * t;
+        s += metric ? fabs(t) : t * t;
     }
     return s;
 }
 
 static int nearest_centre(const float *X, int d, int64_t p, int dim0, int w,
-                          const double *cent, int sk, double *best_out) {
+                          const double *cent, int sk, int metric, double *best_out) {
     int best = 0;
-    double bd = half_dist2(X, d, p, dim0, w, cent);
+    double bd = half_dist(X, d, p, dim0, w, cent, metric);
     for (int c = 1; c < sk; ++c) {
-        double t = half_dist2(X, d, p, dim0, w, cent + (int64_t)c * w);
+        double t = half_dist(X, d, p, dim0, w, cent + (int64_t)c * w, metric);
         if (t < bd) { bd = t; best = c; }   /* ties keep the lowest centre id */
     }
     *best_out = bd;
@@ -145,7 +146,7 @@ EXPORT int so_kmeans(const float *X, int64_t n, int d, int dim0, int w, int sk, 
     for (int it = 0; it <= iters; ++it) {
         /* assignment step: each point independently (order-free) */
 #pragma omp parallel for num_threads(nthreads) schedule(static)
-        for (int64_t p = 0; p < n; ++p) assign[p] = nearest_centre(X, d, p, dim0, w, cent, sk, &md[p]);
+        for (int64_t p = 0; p < n; ++p) assign[p] = nearest_centre(X, d, p, dim0, w, cent, sk, 0, &md[p]);
         double o = 0.0;
         for (int64_t p = 0; p < n; ++p) o += md[p];
         if (obj) obj[it] = o;
@@ -168,15 +169,72 @@ EXPORT int so_kmeans(const float *X, int64_t n, int d, int dim0, int w, int sk, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* The clustering of SuCo-L1 (Sec. 5.3 only says the distance measure        */
+/* changes).  READING: k-medians, Lloyd's iteration under the Manhattan      */
+/* distance: the same initial centres and t iterations of {assign to the    */
+/* nearest centre by L1 (ties -> lowest id), replace each coordinate of a    */
+/* centre by the lower median of its members' values (the ceil(m/2)-th       */
+/* smallest of m, which minimises the sum of absolute deviations); an empty  */
+/* cluster keeps its centre}, then one final assignment.  obj[it] = the sum  */
+/* of L1 distances at the it-th assignment (non-increasing).                 */
+/* ------------------------------------------------------------------------ */
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+EXPORT int so_kmedians(const float *X, int64_t n, int d, int dim0, int w, int sk, int iters,
+                       const int64_t *init_ids, double *cent, int32_t *assign, double *obj, int nthreads) {
+    for (int c = 0; c < sk; ++c)
+        for (int j = 0; j < w; ++j)
+            cent[(int64_t)c * w + j] = (double)X[init_ids[c] * d + dim0 + j];
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(sk + 1));
+    int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    double *md = (double *)malloc(sizeof(double) * (size_t)n);
+    double *vals = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!cnt || !mem || !md || !vals) { free(cnt); free(mem); free(md); free(vals); return -2; }
+    if (nthreads < 1) nthreads = 1;
+    for (int it = 0; it <= iters; ++it) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int64_t p = 0; p < n; ++p) assign[p] = nearest_centre(X, d, p, dim0, w, cent, sk, 1, &md[p]);
+        double o = 0.0;
+        for (int64_t p = 0; p < n; ++p) o += md[p];
+        if (obj) obj[it] = o;
+        if (it == iters) break;
+        /* members of every cluster, grouped by cluster */
+        memset(cnt, 0, sizeof(int64_t) * (size_t)(sk + 1));
+        for (int64_t p = 0; p < n; ++p) cnt[assign[p] + 1] += 1;
+        for (int c = 0; c < sk; ++c) cnt[c + 1] += cnt[c];
+        {
+            int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)sk);
+            memcpy(fill, cnt, sizeof(int64_t) * (size_t)sk);
+            for (int64_t p = 0; p < n; ++p) mem[fill[assign[p]]++] = p;
+            free(fill);
+        }
+        for (int c = 0; c < sk; ++c) {
+            int64_t m = cnt[c + 1] - cnt[c];
+            if (m == 0) continue;
+            for (int j = 0; j < w; ++j) {
+                for (int64_t t = 0; t < m; ++t) vals[t] = (double)X[mem[cnt[c] + t] * d + dim0 + j];
+                qsort(vals, (size_t)m, sizeof(double), cmp_double);
+                cent[(int64_t)c * w + j] = vals[(m - 1) / 2];
+            }
+        }
+    }
+    free(cnt); free(mem); free(md); free(vals);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Create Index (Alg. 2): for every subspace, k-means on both halves.        */
 /* Outputs the FP64 centres, their single rounding to FP32 (the canonical    */
 /* index the queries read) and the assignments [2*ns][n].                    */
 /* Centres are packed half after half: half g occupies sk*width[g] values    */
 /* starting at sk*dim0[g].                                                   */
 /* ------------------------------------------------------------------------ */
-EXPORT int so_build(const float *X, int64_t n, int d, int ns, int sk, int iters, uint64_t seed,
-                    double *cent64, float *cent32, int32_t *assign, double *obj /*[2ns][iters+1]*/,
-                    int nthreads) {
+EXPORT int so_build_metric(const float *X, int64_t n, int d, int ns, int sk, int iters, uint64_t seed,
+                           int metric, double *cent64, float *cent32, int32_t *assign,
+                           double *obj /*[2ns][iters+1]*/, int nthreads) {
     int *dim0 = (int *)malloc(sizeof(int) * 2 * ns), *wd = (int *)malloc(sizeof(int) * 2 * ns);
     int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * sk);
     if (!dim0 || !wd || !ids) return -2;
@@ -185,12 +243,21 @@ EXPORT int so_build(const float *X, int64_t n, int d, int ns, int sk, int iters,
     for (int g = 0; g < 2 * ns && rc == 0; ++g) {
         so_init_ids(X, n, d, dim0[g], wd[g], sk, seed, g, ids);
         double *cg = cent64 + (int64_t)sk * dim0[g];
-        rc = so_kmeans(X, n, d, dim0[g], wd[g], sk, iters, ids, cg, assign + (int64_t)g * n,
-                       obj ? obj + (int64_t)g * (iters + 1) : NULL, nthreads);
+        if (metric)
+            rc = so_kmedians(X, n, d, dim0[g], wd[g], sk, iters, ids, cg, assign + (int64_t)g * n,
+                             obj ? obj + (int64_t)g * (iters + 1) : NULL, nthreads);
+        else
+            rc = so_kmeans(X, n, d, dim0[g], wd[g], sk, iters, ids, cg, assign + (int64_t)g * n,
+                           obj ? obj + (int64_t)g * (iters + 1) : NULL, nthreads);
         for (int64_t t = 0; t < (int64_t)sk * wd[g]; ++t) cent32[(int64_t)sk * dim0[g] + t] = (float)cg[t];
     }
     free(dim0); free(wd); free(ids);
     return rc;
+}
+
+EXPORT int so_build(const float *X, int64_t n, int d, int ns, int sk, int iters, uint64_t seed,
+                    double *cent64, float *cent32, int32_t *assign, double *obj, int nthreads) {
+    return so_build_metric(X, n, d, ns, sk, iters, seed, 0, cent64, cent32, assign, obj, nthreads);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -231,6 +298,7 @@ typedef struct {
     int64_t *offs;     /* [ns][K+1] */
     int32_t *ids;      /* [ns][n]   */
     int s1_bf16;       /* centre distances from BF16-rounded values (model) */
+    int metric;        /* 0: squared Euclidean keys, Euclidean result; 1: Manhattan (SuCo-L1) */
 } so_index;
 
 EXPORT so_index *so_index_create(const float *X, int64_t n, int d, int ns, int sk,
@@ -283,11 +351,16 @@ EXPORT void so_centroid_dists(const so_index *ix, const float *q, int g, double 
             double a = (double)q[d0 + j], b = (double)cg[(int64_t)c * w + j];
             if (ix->s1_bf16) { a = so_bf16(q[d0 + j]); b = so_bf16(cg[(int64_t)c * w + j]); }
             double t = a - b;
-            s += t * t;
+            s += ix->metric ? fabs(t) : t * t;
         }
         dist[c] = s;
     }
 }
+
+/* SuCo-L1 (Sec. 5.3): centre distances, keys and the re-rank by the
+ * Manhattan distance.  With it, dists1 + dists2 is the L1 distance to the
+ * cell's product centre (L1 is a sum over dimensions, like squared L2). */
+EXPORT void so_index_set_metric(so_index *ix, int metric) { ix->metric = metric != 0; }
 
 /* Model of the split-precision step 1 (not in the paper): the same squared
  * distances, from the query half and centres first rounded to BF16. */
@@ -489,21 +562,30 @@ static int cmp_distid(const void *a, const void *b) {
     if (x->d2 > y->d2) return 1;
     return (x->id > y->id) - (x->id < y->id);
 }
-static double full_dist2(const float *X, int d, int64_t p, const float *q) {
+/* Squared Euclidean (metric 0) or Manhattan (metric 1) distance of row p to
+ * q; the returned distance is the Euclidean one (square root) or the
+ * Manhattan one. */
+static double full_dist(const float *X, int d, int64_t p, const float *q, int metric) {
     double s = 0.0;
     for (int j = 0; j < d; ++j) {
         double t = (double)X[p * d + j] - (double)q[j];
-        s += t * t;
+        s += metric ? fabs(t) : t * t;
     }
     return s;
 }
+static double returned_dist(double v, int metric) { return metric ? v : sqrt(v); }
+
+EXPORT void so_rerank_metric(const float *X, int d, const float *q, const int32_t *cand, int64_t B, int k,
+                             int metric, int32_t *ids, double *dists) {
+    distid *e = (distid *)malloc(sizeof(distid) * (size_t)B);
+    for (int64_t t = 0; t < B; ++t) { e[t].id = cand[t]; e[t].d2 = full_dist(X, d, cand[t], q, metric); }
+    qsort(e, (size_t)B, sizeof(distid), cmp_distid);
+    for (int t = 0; t < k; ++t) { ids[t] = e[t].id; dists[t] = returned_dist(e[t].d2, metric); }
+    free(e);
+}
 EXPORT void so_rerank(const float *X, int d, const float *q, const int32_t *cand, int64_t B, int k,
                       int32_t *ids, double *dists) {
-    distid *e = (distid *)malloc(sizeof(distid) * (size_t)B);
-    for (int64_t t = 0; t < B; ++t) { e[t].id = cand[t]; e[t].d2 = full_dist2(X, d, cand[t], q); }
-    qsort(e, (size_t)B, sizeof(distid), cmp_distid);
-    for (int t = 0; t < k; ++t) { ids[t] = e[t].id; dists[t] = sqrt(e[t].d2); }
-    free(e);
+    so_rerank_metric(X, d, q, cand, B, k, 0, ids, dists);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -544,7 +626,7 @@ EXPORT int so_query(const so_index *ix, const float *Q, int64_t nq, int k, const
             if (aprime_out) aprime_out[qi * ns + i] = ap;
         }
         so_select(sc, n, B, cand);
-        so_rerank(ix->X, d, q, cand, B, k, ids + qi * k, dists + qi * k);
+        so_rerank_metric(ix->X, d, q, cand, B, k, ix->metric, ids + qi * k, dists + qi * k);
         if (scores_out) memcpy(scores_out + qi * n, sc, (size_t)n);
         if (cand_out) memcpy(cand_out + qi * B, cand, sizeof(int32_t) * (size_t)B);
         free(sc); free(d1); free(d2); free(i1); free(i2); free(cells); free(cand);
@@ -576,9 +658,9 @@ EXPORT int64_t so_query_cells(const so_index *ix, const float *q, int i, double 
 /* points, the A nearest collide (READING: order by (distance, id)); then   */
 /* the same selection and re-rank.                                           */
 /* ------------------------------------------------------------------------ */
-EXPORT int so_sclinear(const float *X, int64_t n, int d, int ns, const float *Q, int64_t nq, int k,
-                       double alpha, double beta, int32_t *ids, double *dists, uint8_t *scores_out,
-                       int nthreads) {
+EXPORT int so_sclinear_metric(const float *X, int64_t n, int d, int ns, const float *Q, int64_t nq, int k,
+                              double alpha, double beta, int metric, int32_t *ids, double *dists,
+                              uint8_t *scores_out, int nthreads) {
     int *dim0 = (int *)malloc(sizeof(int) * 2 * ns), *wd = (int *)malloc(sizeof(int) * 2 * ns);
     so_layout(d, ns, dim0, wd);
     int64_t A = so_count_A(alpha, n), B = so_count_B(beta, n, k);
@@ -595,7 +677,7 @@ EXPORT int so_sclinear(const float *X, int64_t n, int d, int ns, const float *Q,
                 double s = 0.0;
                 for (int j = 0; j < sw; ++j) {
                     double t = (double)X[p * d + s0 + j] - (double)q[s0 + j];
-                    s += t * t;
+                    s += metric ? fabs(t) : t * t;
                 }
                 e[p].d2 = s; e[p].id = (int32_t)p;
             }
@@ -603,7 +685,7 @@ EXPORT int so_sclinear(const float *X, int64_t n, int d, int ns, const float *Q,
             for (int64_t z = 0; z < A; ++z) sc[e[z].id] += 1;
         }
         so_select(sc, n, B, cand);
-        so_rerank(X, d, q, cand, B, k, ids + qi * k, dists + qi * k);
+        so_rerank_metric(X, d, q, cand, B, k, metric, ids + qi * k, dists + qi * k);
         if (scores_out) memcpy(scores_out + qi * n, sc, (size_t)n);
         free(sc); free(e); free(cand);
     }
@@ -614,16 +696,20 @@ EXPORT int so_sclinear(const float *X, int64_t n, int d, int ns, const float *Q,
 /* ------------------------------------------------------------------------ */
 /* Exact k-NN by (squared distance, id) -- the problem statement (Sec. 1).   */
 /* ------------------------------------------------------------------------ */
-EXPORT int so_bruteforce(const float *X, int64_t n, int d, const float *Q, int64_t nq, int k,
-                         int32_t *ids, double *dists, int nthreads) {
+EXPORT int so_bruteforce_metric(const float *X, int64_t n, int d, const float *Q, int64_t nq, int k,
+                                int metric, int32_t *ids, double *dists, int nthreads) {
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int64_t qi = 0; qi < nq; ++qi) {
         distid *e = (distid *)malloc(sizeof(distid) * (size_t)n);
-        for (int64_t p = 0; p < n; ++p) { e[p].id = (int32_t)p; e[p].d2 = full_dist2(X, d, p, Q + qi * d); }
+        for (int64_t p = 0; p < n; ++p) { e[p].id = (int32_t)p; e[p].d2 = full_dist(X, d, p, Q + qi * d, metric); }
         qsort(e, (size_t)n, sizeof(distid), cmp_distid);
-        for (int t = 0; t < k; ++t) { ids[qi * k + t] = e[t].id; dists[qi * k + t] = sqrt(e[t].d2); }
+        for (int t = 0; t < k; ++t) { ids[qi * k + t] = e[t].id; dists[qi * k + t] = returned_dist(e[t].d2, metric); }
         free(e);
     }
     return 0;
+}
+EXPORT int so_bruteforce(const float *X, int64_t n, int d, const float *Q, int64_t nq, int k,
+                         int32_t *ids, double *dists, int nthreads) {
+    return so_bruteforce_metric(X, n, d, Q, nq, k, 0, ids, dists, nthreads);
 }

@@ -65,14 +65,20 @@ def check_cells(ref, gpu_cells, gpu_ncells, q, i, extra=0.0):
     return False
 
 
-def check_topk(X, Q, ids, dists, ref_ids, ref_dists, k):
+def true_dists(X64, ids, q, metric=0):
+    """FP64 distances of rows `ids` to q: Euclidean, or Manhattan (metric 1)."""
+    diff = X64[ids] - q.astype(np.float64)
+    return np.abs(diff).sum(axis=1) if metric else np.sqrt((diff ** 2).sum(axis=1))
+
+
+def check_topk(X, Q, ids, dists, ref_ids, ref_dists, k, metric=0):
     """Top-k identical, or a valid top-k under distance ties within REL."""
     X64 = X.astype(np.float64)
     for q in range(Q.shape[0]):
         if np.array_equal(ids[q], ref_ids[q]):
             assert np.allclose(dists[q], ref_dists[q], rtol=REL, atol=1e-6), f"query {q}: distances"
             continue
-        true = np.sqrt(((X64[ids[q]] - Q[q].astype(np.float64)) ** 2).sum(axis=1))
+        true = true_dists(X64, ids[q], Q[q], metric)
         assert len(set(ids[q].tolist())) == k, f"query {q}: repeated ids"
         assert np.allclose(np.sort(true), np.sort(ref_dists[q]), rtol=REL, atol=1e-6), \
             f"query {q}: ids {ids[q]} vs {ref_ids[q]} not a tie"
@@ -113,7 +119,7 @@ def check_query(oix, X, Q, k, alpha, beta, gpu, key_tol=None):
             assert np.array_equal(g_sc[q], ref["scores"][q]), f"query {q}: SC-scores differ"
             assert np.array_equal(np.sort(gpu["cand"][q]), np.sort(ref["cand"][q])), f"query {q}: candidates"
             check_topk(X, Q[q:q + 1], gpu["ids"][q:q + 1], gpu["dists"][q:q + 1], ref["ids"][q:q + 1],
-                       ref["dists"][q:q + 1], k)
+                       ref["dists"][q:q + 1], k, oix.metric)
         else:
             n_band += 1
             # the GPU's scores are the counts over its own cells, A' their sizes
@@ -123,7 +129,8 @@ def check_query(oix, X, Q, k, alpha, beta, gpu, key_tol=None):
             # conditional parity: the oracle's selection and re-rank on the GPU's scores
             c = oracle.select(g_sc[q], B)
             assert np.array_equal(np.sort(gpu["cand"][q]), np.sort(c)), f"query {q}: conditional candidates"
-            r_ids, r_d = oracle.rerank(X, Q[q], c, k)
-            check_topk(X, Q[q:q + 1], gpu["ids"][q:q + 1], gpu["dists"][q:q + 1], r_ids[None], r_d[None], k)
+            r_ids, r_d = oracle.rerank(X, Q[q], c, k, oix.metric)
+            check_topk(X, Q[q:q + 1], gpu["ids"][q:q + 1], gpu["dists"][q:q + 1], r_ids[None], r_d[None], k,
+                       oix.metric)
     rec_gpu = oracle.recall(gpu["ids"], ref["ids"])
     return dict(band_queries=n_band, ref=ref, agree=rec_gpu)
