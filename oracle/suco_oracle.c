@@ -32,6 +32,8 @@
 /* guard against representation error (0.03*1e6 is 30000.000000000004),     */
 /* A >= 1, and B raised to k so that a top-k of the candidates exists.       */
 /* ------------------------------------------------------------------------ */
+#define SO_SUM_GROUP 256   /* members per group of the k-means update's sums */
+
 EXPORT int64_t so_count_A(double alpha, int64_t n) {
     int64_t a = (int64_t)ceil(alpha * (double)n - 1e-9);
     if (a < 1) a = 1;
@@ -127,10 +129,13 @@ static int nearest_centre(const float *X, int d, int64_t p, int dim0, int w,
 /* ------------------------------------------------------------------------ */
 /* Lloyd's k-means on one half (Alg. 2, the two Kmeans calls).              */
 /* READING: t fixed iterations of {assign to nearest centre (ties -> lowest  */
-/* id), recompute each centre as the FP64 mean of its members (sum in row    */
-/* order); an empty cluster keeps its centre}, then one final assignment     */
-/* against the final centres.  obj[it] = sum of squared distances at the     */
-/* it-th assignment (it = 0..iters, the last one being the final pass).      */
+/* id), recompute each centre as the FP64 mean of its members; an empty      */
+/* cluster keeps its centre}, then one final assignment against the final   */
+/* centres.  obj[it] = sum of squared distances at the it-th assignment      */
+/* (it = 0..iters, the last one being the final pass).  READING (summation   */
+/* order, which Alg. 2 leaves open): a cluster's members in ascending id     */
+/* are taken in groups of SO_SUM_GROUP; each group is summed in order from   */
+/* zero, and the group sums are added in order.                              */
 /* ------------------------------------------------------------------------ */
 EXPORT int so_kmeans(const float *X, int64_t n, int d, int dim0, int w, int sk, int iters,
                      const int64_t *init_ids, double *cent, int32_t *assign, double *obj,
@@ -139,9 +144,10 @@ EXPORT int so_kmeans(const float *X, int64_t n, int d, int dim0, int w, int sk, 
         for (int j = 0; j < w; ++j)
             cent[(int64_t)c * w + j] = (double)X[init_ids[c] * d + dim0 + j];
     double *sum = (double *)malloc(sizeof(double) * (size_t)sk * w);
+    double *gsum = (double *)malloc(sizeof(double) * (size_t)sk * w);
     int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)sk);
     double *md = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!sum || !cnt || !md) { free(sum); free(cnt); free(md); return -2; }
+    if (!sum || !gsum || !cnt || !md) { free(sum); free(gsum); free(cnt); free(md); return -2; }
     if (nthreads < 1) nthreads = 1;
     for (int it = 0; it <= iters; ++it) {
         /* assignment step: each point independently (order-free) */
@@ -151,20 +157,28 @@ EXPORT int so_kmeans(const float *X, int64_t n, int d, int dim0, int w, int sk, 
         for (int64_t p = 0; p < n; ++p) o += md[p];
         if (obj) obj[it] = o;
         if (it == iters) break;
-        /* update step: means in row order */
+        /* update step: members in id order, summed group by group */
         memset(sum, 0, sizeof(double) * (size_t)sk * w);
+        memset(gsum, 0, sizeof(double) * (size_t)sk * w);
         memset(cnt, 0, sizeof(int64_t) * (size_t)sk);
         for (int64_t p = 0; p < n; ++p) {
             int a = assign[p];
+            for (int j = 0; j < w; ++j) gsum[(int64_t)a * w + j] += (double)X[p * d + dim0 + j];
             cnt[a] += 1;
-            for (int j = 0; j < w; ++j) sum[(int64_t)a * w + j] += (double)X[p * d + dim0 + j];
+            if (cnt[a] % SO_SUM_GROUP == 0)                    /* a group is complete */
+                for (int j = 0; j < w; ++j) {
+                    sum[(int64_t)a * w + j] += gsum[(int64_t)a * w + j];
+                    gsum[(int64_t)a * w + j] = 0.0;
+                }
         }
         for (int c = 0; c < sk; ++c)
             if (cnt[c] > 0)
-                for (int j = 0; j < w; ++j)
+                for (int j = 0; j < w; ++j) {
+                    if (cnt[c] % SO_SUM_GROUP) sum[(int64_t)c * w + j] += gsum[(int64_t)c * w + j];
                     cent[(int64_t)c * w + j] = sum[(int64_t)c * w + j] / (double)cnt[c];
+                }
     }
-    free(sum); free(cnt); free(md);
+    free(sum); free(gsum); free(cnt); free(md);
     return 0;
 }
 

@@ -320,6 +320,25 @@ def test_kmeans_invariants():
                 assert np.allclose(cent[c], H[m].mean(axis=0), rtol=1e-12, atol=1e-12)
 
 
+def test_kmeans_update_exact_means_across_sum_groups():
+    """Integer data, clusters of several hundred members (more than one
+    summation group, a ragged last group): every FP64 partial sum is an exact
+    integer, so after one update each centre is exactly the exact mean rounded
+    once (sum / m), whatever the grouping; a dropped or doubled group fails."""
+    rng = np.random.default_rng(12)
+    lab = rng.integers(0, 3, 2000)
+    X = (np.array([[0, 0], [100, 0], [0, 100]])[lab] + rng.integers(-20, 21, (2000, 2))).astype(np.float32)
+    init = np.array([np.flatnonzero(lab == c)[0] for c in range(3)], np.int64)
+    cent, asg, _ = oracle.kmeans(X, 0, 2, 3, 1, init)
+    H = X.astype(np.float64)
+    a0 = np.argmin(((H[:, None, :] - H[init][None, :, :]) ** 2).sum(axis=2), axis=1)
+    for c in range(3):
+        m = int((a0 == c).sum())
+        assert m > 256 and m % 256
+        tot = [sum(int(v) for v in X[a0 == c, j]) for j in range(2)]
+        assert np.array_equal(cent[c], np.array(tot, np.float64) / m)
+
+
 def test_kmeans_separates_obvious_clusters():
     rng = np.random.default_rng(0)
     centres = np.array([[-10.0, 0.0], [0.0, 10.0], [10.0, 0.0]])
