@@ -655,12 +655,154 @@ def bench_learned_lifted(args, log):
     ix.free()
 
 
+def bench_build(args, log):
+    """Create Index (Alg. 2) on the GPU for the SIFT-like (n=1M, d=128, N_s=8,
+    sqrtK=50), Deep-like (n=10M, d=96, N_s=8, sqrtK=64) and lifted (n=10M,
+    d=256, N_s=16, sqrtK=64) workloads, 25 k-means iterations: wall time with
+    the data already in HBM, the device memory the index holds, and the
+    k-means assignment's FP64 rate (its flops: every point's distance to every
+    centre of every half, three FP64 operations per dimension)."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+    rows = []
+    which = (2, 4, 5) if args.build_all else (2,)
+    for c in which:
+        W = synth.Workload(c)
+        sp = W.spec
+        n, d, ns, sk = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"]
+        log(f"{sp['name']}: generating data")
+        Xd = torch.from_numpy(W.data()).cuda()
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        t0 = time.time()
+        ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+        torch.cuda.synchronize()
+        build_s = time.time() - t0
+        free1, _ = torch.cuda.mem_get_info()
+        flops_assign = 3.0 * n * d * sk          # per assignment pass, all halves
+        rows.append({"workload": sp["name"], "n": n, "d": d, "n_s": ns, "sqrt_k": sk, "iters": 25,
+                     "build_s": round(build_s, 4), "index_bytes": int(free0 - free1),
+                     "data_bytes": 4 * n * d, "assign_flops_per_pass": flops_assign})
+        log(f"{sp['name']}: built in {build_s:.3f} s, index holds {(free0 - free1) / 2**30:.2f} GiB "
+            f"(data {4 * n * d / 2**30:.2f} GiB)")
+        ix.free()
+        del Xd
+        torch.cuda.empty_cache()
+    rec = {"metric": "GPU index build time (Create Index, 25 k-means iterations)", "value": rows[0]["build_s"],
+           "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": rows[0]["workload"], "rows": rows}}
+    print(json.dumps(rec))
+
+
+def bench_activation(args, log):
+    """Dynamic Activation against Multi-sequence (Sec. 4.2, Sec. 5.2) on the
+    SIFT-like index: the activation step's time and the whole query's, per
+    alpha, with each rule; both activate the same cells, so recall is equal."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+    W = synth.Workload(2)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    out = (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
+           torch.empty((nq, k), dtype=torch.float32, device="cuda"))
+    rows = []
+    for alpha in (0.0005, 0.003, 0.01, 0.03, 0.05):
+        row = {"alpha": alpha}
+        ref = None
+        for name, form in (("dynamic_activation", suco.ACT_DYNAMIC), ("multi_sequence", suco.ACT_MULTISEQ)):
+            ix.set_activation(form)
+            fn = lambda: ix.query(Qd, k, alpha, beta, out=out)
+            ms, _ = timed_steps(fn, args.steps, args.warmup)
+            got = out[0].clone()
+            if ref is None:
+                ref = got
+            row[name + "_same_ids"] = bool(torch.equal(ref, got))
+            ix.profile(True)
+            ix.profile_read()
+            for _ in range(args.steps):
+                fn()
+            st = ix.profile_read()
+            ix.profile(False)
+            row[name] = {"query_ms": round(ms / args.steps, 4), "activate_ms": round(st["activate"][0] / args.steps, 4)}
+        ix.set_activation(suco.ACT_DYNAMIC)
+        da, mseq = row["dynamic_activation"], row["multi_sequence"]
+        row["activate_speedup"] = round(mseq["activate_ms"] / max(1e-9, da["activate_ms"]), 3)
+        log(f"alpha={alpha}: activation DA {da['activate_ms']:.3f} ms, Multi-sequence {mseq['activate_ms']:.3f} ms; "
+            f"query {da['query_ms']:.3f} vs {mseq['query_ms']:.3f} ms")
+        rows.append(row)
+    rec = {"metric": "activation step time, Dynamic Activation vs Multi-sequence, n=1M d=128, 10,000 queries",
+           "value": rows[1]["activate_speedup"], "unit": "x (Multi-sequence time / Dynamic Activation time) at alpha=0.003",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"sift_like n={n} d={d} int 0..255, N_s={ns}, sqrtK={sk}, nq={nq}, k={k}, beta={beta}",
+                      "rows": rows}}
+    print(json.dumps(rec))
+    ix.free()
+
+
+def bench_sclinear(args, log):
+    """SuCo against SC-Linear (Alg. 1, no index) on the SIFT-like data with the
+    comparison table's parameters (alpha=0.03, beta=0.003, k=50): per-query
+    time, speed-up, recall@50, and the bytes SC-Linear moves per query (its
+    distance array written once and read by the threshold passes and the
+    scoring pass; the rows themselves are read once per pass of queries)."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+    W = synth.Workload(2)
+    sp = W.spec
+    n, d, ns, sk = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"]
+    alpha, beta, k = 0.03, 0.003, 50
+    nq_lin = 512
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    Ql = Qd[:nq_lin].contiguous()
+    gt = exact_topk(Xd, Ql, k)
+    out_s = (torch.empty((nq_lin, k), dtype=torch.int32, device="cuda"),
+             torch.empty((nq_lin, k), dtype=torch.float32, device="cuda"))
+    out_l = (torch.empty((nq_lin, k), dtype=torch.int32, device="cuda"),
+             torch.empty((nq_lin, k), dtype=torch.float32, device="cuda"))
+    ms_suco, _ = timed_steps(lambda: ix.query(Ql, k, alpha, beta, out=out_s), args.steps, args.warmup)
+    ms_lin, per_lin = timed_steps(lambda: ix.query_sclinear(Ql, k, alpha, beta, out=out_l), max(1, args.steps // 2), 1)
+    steps_lin = max(1, args.steps // 2)
+    q_suco = ms_suco / args.steps / nq_lin
+    q_lin = ms_lin / steps_lin / nq_lin
+    r_suco, r_lin = recall_at(out_s[0], gt), recall_at(out_l[0], gt)
+    # per query: n*ns FP32 distances written once, read by four radix passes, the
+    # tie count and the scoring pass; n score bytes written and read twice
+    lin_bytes = n * ns * 4 * (1 + 4 + 1 + 1) + 3 * n + n * d / 256.0
+    gbs = lin_bytes * nq_lin / (ms_lin / steps_lin / 1e3) / 1e9
+    log(f"SC-Linear: {q_lin * 1e3:.1f} us/query, recall@50={r_lin:.4f}; SuCo: {q_suco * 1e3:.2f} us/query, "
+        f"recall@50={r_suco:.4f}; speed-up {q_lin / q_suco:.0f}x")
+    rec = {"metric": "SuCo vs SC-Linear per-query time, n=1M d=128 (alpha=0.03, beta=0.003, k=50)",
+           "value": round(q_lin / q_suco, 1), "unit": "x speed-up of SuCo over SC-Linear", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"sift_like n={n} d={d} int 0..255, N_s={ns}, sqrtK={sk}, nq={nq_lin}, k={k}, "
+                                  f"alpha={alpha}, beta={beta}",
+                      "suco": {"ms_per_query": round(q_suco, 6), "recall_at_50": round(r_suco, 5)},
+                      "sclinear": {"ms_per_query": round(q_lin, 5), "recall_at_50": round(r_lin, 5),
+                                   "step_ms": [round(x, 3) for x in per_lin],
+                                   "bytes_per_query": lin_bytes, "gbs": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4)}}}
+    print(json.dumps(rec))
+    ix.free()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("sift_like", "gist_like", "deep_like", "lifted256"), default="sift_like",
+    ap.add_argument("--workload", choices=("sift_like", "gist_like", "deep_like", "lifted256", "sclinear", "activation", "build"), default="sift_like",
                     help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split "
-                         "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M")
+                         "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M; "
+                         "sclinear: SuCo against SC-Linear on the SIFT-like data; activation: Dynamic Activation "
+                         "against Multi-sequence; build: index build time and memory")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=10_000, help="most queries the CPU oracle is timed on")
@@ -676,6 +818,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=25)
     ap.add_argument("--lifted-train", type=int, default=200_000, help="training queries of the lifted256 mode")
     ap.add_argument("--target-recall", type=float, default=0.951)
+    ap.add_argument("--build-all", action="store_true", help="build: also the 10M-point Deep-like and lifted indexes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "
                          "scale HBM byte counters) and exit")
@@ -706,6 +849,15 @@ def main():
         return
     if args.workload == "lifted256":
         bench_learned_lifted(args, log)
+        return
+    if args.workload == "sclinear":
+        bench_sclinear(args, log)
+        return
+    if args.workload == "activation":
+        bench_activation(args, log)
+        return
+    if args.workload == "build":
+        bench_build(args, log)
         return
 
     import torch

@@ -80,6 +80,18 @@ typedef struct suco_build_params {
  * (4*n*n_s bytes): every query counts SC-scores tile by tile over the whole
  * id range.  The results are the same either way. */
 #define SUCO_BUILD_NO_SPARSE 4
+/* SuCo-L1 (Sec. 5.3, Table 5): the Manhattan distance instead of the
+ * Euclidean one throughout.  suco_build clusters each half with k-medians
+ * (nearest centre by L1 in FP64, ties to the lower centre id; each centre
+ * coordinate the lower median, the ceil(m/2)-th smallest of its m members'
+ * values; an empty cluster keeps its centre; the same initial centres and
+ * final assignment pass as the k-means).  Queries rank centres and cells by
+ * L1 distance (a cell's key is the L1 distance to its product centre), count
+ * and select as usual, re-rank by L1 (FP32, dimension order) and return L1
+ * distances.  Not with SUCO_BUILD_BF16 (SUCO_E_UNSUPPORTED); the Multi-
+ * sequence rule, SC-Linear and the batched and no-alloc forms follow the
+ * index's metric. */
+#define SUCO_BUILD_L1 8
 
 SUCO_API int suco_version(void);
 SUCO_API const char *suco_last_error(void);
@@ -134,7 +146,27 @@ SUCO_API int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32
  * with SUCO_BUILD_BF16.  flags: host int32. */
 #define SUCO_INDEX_BYTE_ROWS 1
 #define SUCO_INDEX_BF16 2
+#define SUCO_INDEX_L1 4       /* built with SUCO_BUILD_L1: the Manhattan distance throughout */
 SUCO_API int suco_index_flags(const suco_index *ix, int32_t *flags);
+
+/* Activation rule of step 2 for the queries that follow on this index (each
+ * query call reads it when it starts; a batcher reads it when it builds a
+ * bucket's graph, so set it before creating one).
+ *  SUCO_ACT_DYNAMIC   Dynamic Activation (Alg. 3), the default.
+ *  SUCO_ACT_MULTISEQ  Multi-sequence, the inverted multi-index traversal that
+ *                     Sec. 4.2 compares it with: a priority queue of cells by
+ *                     ascending key, seeded with the cell of both nearest
+ *                     centres, where taking a cell queues its two neighbours
+ *                     in the rank grid.  It activates the same cells (ties in
+ *                     the key by the first rank, then the second); it exists
+ *                     to measure the two rules against each other (Sec. 5.2).
+ *                     Cells are exported in retrieval order, where Dynamic
+ *                     Activation exports them row by row.
+ *  errors  SUCO_E_INVAL for another value; SUCO_E_UNSUPPORTED for
+ *          SUCO_ACT_MULTISEQ on an index with sqrt_k > 64. */
+#define SUCO_ACT_DYNAMIC 0
+#define SUCO_ACT_MULTISEQ 1
+SUCO_API int suco_index_set_activation(suco_index *ix, int32_t form);
 
 /* Release an index (NULL is accepted).  Waits for its pending queries. */
 SUCO_API int suco_index_free(suco_index *ix);
@@ -151,7 +183,8 @@ SUCO_API int suco_index_free(suco_index *ix);
  * before any device work, rebuilds the index from the stored centres and
  * assignments (as suco_build_from_index), and fails with SUCO_E_INVAL if the
  * checksum does not match.  p overrides the stored build parameters (NULL:
- * those recorded in the file).  A loaded index answers every query bitwise
+ * those recorded in the file) except SUCO_BUILD_L1, which is always the
+ * file's (the centres belong to that metric).  A loaded index answers every query bitwise
  * as the saved one did.
  *  path  host NUL-terminated file name. */
 SUCO_API int suco_index_save(const suco_index *ix, const char *path);
@@ -214,7 +247,8 @@ SUCO_API int suco_query_alpha(const suco_index *ix, const float *Q, int64_t nq, 
  *  cells   uint16 [nq][n_s][sqrt_k^2]  activated cell ids (a1*sqrt_k + a2),
  *                             the first ncells entries of each row are valid
  *  feat    float32 [nq][2*n_s] distance from each query half to its nearest
- *                             centre (sqrt of the smallest step-1 value)
+ *                             centre (sqrt of the smallest step-1 value; on a
+ *                             SUCO_BUILD_L1 index the smallest L1 distance)
  */
 SUCO_API int suco_query_debug(const suco_index *ix, const float *Q, int64_t nq, int32_t k,
                      const float *alpha_q, double alpha, double beta, int32_t *ids, float *dists,
@@ -258,6 +292,21 @@ SUCO_API int suco_query_bf16_debug(const suco_index *ix, const float *Q, int64_t
                                    double beta, int32_t flags, int32_t *ids, float *dists, int32_t *nsurv,
                                    double *relerr, float *cdist, uint8_t *scores, int32_t *cand,
                                    int32_t *ncells, int32_t *aprime, uint16_t *cells, void *stream);
+
+/* ------------------------------------------------------------ SC-Linear --
+ * The subspace collision framework without an index (Alg. 1): for each query
+ * and subspace i (the division of the index, Sec. 3.2), the A = max(1,
+ * ceil(alpha*n)) points nearest to the query in that subspace collide (Def. 2,
+ * squared distances in FP32 summed in dimension order, ties by lower id); a
+ * point's SC-score is the number of subspaces where it collides (Def. 4); the
+ * B = max(k, floor(beta*n)) points of highest score (ties by lower id) are
+ * re-ranked as in suco_query.  Reads all of D per pass of queries; the index
+ * supplies D, the subspace division and the re-rank's rows only.
+ *  Q, ids, dists, k, alpha, beta   as in suco_query.
+ *  scores  device uint8 [nq][n] SC-scores, or NULL.
+ *  limits  subspaces of at most 64 dimensions (SUCO_E_UNSUPPORTED beyond). */
+SUCO_API int suco_query_sclinear(const suco_index *ix, const float *Q, int64_t nq, int32_t k, double alpha,
+                                 double beta, int32_t *ids, float *dists, uint8_t *scores, void *stream);
 
 /* ------------------------------------------------------- single steps --
  * The steps of the query path on their own, fed by the caller; they let each
@@ -346,7 +395,9 @@ SUCO_API int suco_mlp_train_epoch(suco_mlp *m, const float *F, const float *t, i
 SUCO_API int suco_mlp_predict(suco_mlp *m, const float *F, int64_t rows, float scale, float alpha_min,
                               float alpha_max, float *y, float *alpha, void *stream);
 SUCO_API int suco_mlp_free(suco_mlp *m);
-/* Query features F device [nq][2*n_s + 1]. */
+/* Query features F device [nq][2*n_s + 1].  The learned budget (features,
+ * suco_query_learned, suco_batcher_set_model) is Euclidean: on a
+ * SUCO_BUILD_L1 index these calls return SUCO_E_UNSUPPORTED. */
 SUCO_API int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float *F, void *stream);
 /* k-ANN query with the network's per-query alpha: features, BF16 inference,
  * then exactly suco_query_alpha with those alphas; alpha_used (device [nq],

@@ -27,7 +27,7 @@ EXPORTED = (
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
     "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags", "suco_index_save", "suco_index_load",
-    "suco_query_noalloc",
+    "suco_query_noalloc", "suco_query_sclinear", "suco_index_set_activation",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order",
@@ -48,8 +48,10 @@ class BuildParams(C.Structure):
 BUILD_NO_BYTE_ROWS = 1
 BUILD_BF16 = 2
 BUILD_NO_SPARSE = 4
+BUILD_L1 = 8
 BF16_S1 = 1
-INDEX_BYTE_ROWS, INDEX_BF16 = 1, 2
+INDEX_BYTE_ROWS, INDEX_BF16, INDEX_L1 = 1, 2, 4
+ACT_DYNAMIC, ACT_MULTISEQ = 0, 1
 
 
 _lib = None
@@ -77,11 +79,13 @@ def lib():
         L.suco_index_info.argtypes = [P, P, P, P, P]
         L.suco_index_free.argtypes = [P]
         L.suco_index_flags.argtypes = [P, P]
+        L.suco_index_set_activation.argtypes = [P, i32]
         L.suco_index_save.argtypes = [P, C.c_char_p]
         L.suco_index_load.argtypes = [C.c_char_p, C.POINTER(BuildParams), P, C.POINTER(P)]
         L.suco_query.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
         L.suco_query_alpha.argtypes = [P, P, i64, i32, P, dbl, P, P, P]
         L.suco_query_noalloc.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P]
+        L.suco_query_sclinear.argtypes = [P, P, i64, i32, dbl, dbl, P, P, P, P]
         L.suco_query_debug.argtypes = [P, P, i64, i32, P, dbl, dbl, P, P, P, P, P, P, P, P, P]
         L.suco_collide_select.argtypes = [P, i64, P, P, i32, dbl, P, P, P]
         L.suco_rerank.argtypes = [P, P, i64, P, i64, i32, P, P, P]
@@ -235,6 +239,10 @@ class Index:
         _check(lib().suco_index_flags(self._h, C.byref(f)))
         return int(f.value)
 
+    def set_activation(self, form: int):
+        """ACT_DYNAMIC (Alg. 3) or ACT_MULTISEQ for the queries that follow (see suco_index_set_activation)."""
+        _check(lib().suco_index_set_activation(self._h, int(form)))
+
     def export(self):
         cent = np.zeros(self.sqrt_k * self.d, np.float32)
         asg = np.zeros((2 * self.ns, self.n), np.int32)
@@ -265,6 +273,17 @@ class Index:
         _check(lib().suco_query_noalloc(self._h, pq, nq, k, float(alpha), float(beta), _dev(ids, torch.int32),
                                         _dev(dists, torch.float32), _stream(stream)))
         return ids, dists
+
+    def query_sclinear(self, Q, k: int, alpha: float, beta: float, scores=False, out=None, stream=None):
+        """SC-Linear (Alg. 1, see suco_query_sclinear): (ids, dists, scores uint8 [nq,n] or None)."""
+        torch = _torch()
+        nq = Q.shape[0]
+        pq = _dev(Q, torch.float32, (nq, self.d), "Q")
+        ids, dists = out if out is not None else self._out(nq, k)
+        sc = torch.empty((nq, self.n), dtype=torch.uint8, device="cuda") if scores else None
+        _check(lib().suco_query_sclinear(self._h, pq, nq, k, float(alpha), float(beta), _dev(ids, torch.int32),
+                                         _dev(dists, torch.float32), _opt(sc), _stream(stream)))
+        return ids, dists, sc
 
     def query_alpha(self, Q, k: int, alpha_q, beta: float, out=None, stream=None):
         torch = _torch()

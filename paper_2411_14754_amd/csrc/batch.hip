@@ -243,9 +243,12 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         if (C <= kOrderWide) { qp.order_out = b->order; qp.order = b->order; }
         qp.cand = b->cand;
         qp.route = ix->sp_cap ? b->route : nullptr;
+        qp.tlist = qp.route ? b->route + b->C : nullptr;
+        qp.ntl = qp.route ? b->route + 2 * b->C : nullptr;
         qp.sp_cap = ix->sp_cap;
         RerankPass &rp = bk->rps[c];
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = b->cand; rp.B = b->B; rp.n = ix->n; rp.d = ix->d; rp.k = b->k;
+        rp.metric = ix->metric;
         rp.nq = C; rp.parts = parts; rp.nq_dev = b->nq_dev; rp.q_base = c * b->C; rp.rows_per_part = t.rpp;
         rp.G = b->rcfg.G; rp.U = b->rcfg.U; rp.part_keys = b->part_keys;
         rp.ids = b->ids_s + (int64_t)c * b->C * b->k;
@@ -344,7 +347,7 @@ int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, doub
         (rc = dev_alloc(&b->mail, 1)) || (rc = dev_alloc(&b->nq_dev, 1)) ||
         (rc = dev_alloc(&b->cells, C * ix->ns * ix->K)) || (rc = dev_alloc(&b->ncells, C * ix->ns)) ||
         (rc = dev_alloc(&b->aprime, C * ix->ns)) || (rc = dev_alloc(&b->hist, C * ix->P * (ix->ns + 2))) ||
-        (rc = dev_alloc(&b->order, C)) || (rc = dev_alloc(&b->route, C)) ||
+        (rc = dev_alloc(&b->order, C)) || (rc = dev_alloc(&b->route, 2 * C + 1)) ||
         (rc = dev_alloc(&b->lvl, C * (size_t)ix->P * ix->TILE + 2 * kSpBucket)) || (rc = dev_alloc(&b->cand, C * (size_t)b->B)) ||
         (rc = dev_alloc(&b->part_keys, C * (size_t)b->parts_max * k))) {
         b->release();
@@ -413,6 +416,8 @@ int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, float alph
     if (!batcher_ok(b)) return fail(SUCO_E_STATE, "invalid or freed batcher handle");
     if (m && !mlp_valid(m)) return fail(SUCO_E_STATE, "invalid or freed model handle");
     if (m && mlp_n_in(m) != 2 * b->ix->ns + 1) return fail(SUCO_E_INVAL, "the model's n_in must be 2*n_s + 1");
+    if (m && b->ix->metric)
+        return fail(SUCO_E_UNSUPPORTED, "the learned budget's features are Euclidean (not SUCO_BUILD_L1)");
     if (m && !(scale > 0.f)) return fail(SUCO_E_INVAL, "scale must be positive");
     if (m && !(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))
         return fail(SUCO_E_INVAL, "need 0 < alpha_min <= alpha_max <= 1");

@@ -5,18 +5,24 @@
 // k-means iteration, all 2*ns halves in one launch each (grid.y = half):
 //   assign   nearest centre per point in FP64 (ties -> lowest centre id) and
 //            a per-block histogram of the labels
-//   scan     per label, exclusive prefix of the block histograms over blocks;
-//            label starts over labels
+//   scan     per (label, half) block, exclusive prefix of the block
+//            histograms over blocks; then label starts over labels
 //   scatter  stable placement of every point id into its label's range, so
 //            each label's members are listed in ascending id
-//   update   one thread per (centre, dimension) sums its members' values in
-//            ascending id order in FP64 and divides by the count; an empty
-//            label keeps its centre
-// Summing each centre's members one after another in id order, with no
-// contraction into FMA, is the same arithmetic as a sequential CPU loop.
+//   update   one block per (centre, half) sums its members' values in FP64,
+//            ascending id in groups of 256 (each group in order, then the
+//            group sums in order), and divides by the count; an empty label
+//            keeps its centre
+//   median   (k-medians, SuCo-L1) one block per (centre, half) replaces each
+//            coordinate by the lower median of its members' values
+// With SuCo-L1 the assignment takes the nearest centre by L1 instead.
+// Summing each group of a centre's members one after another in id order,
+// with no contraction into FMA, then the group sums in order, is the same
+// arithmetic as the sequential CPU loop that keeps a running group sum.
 #include <hip/hip_runtime.h>
 
 #include "suco_impl.h"
+#include "wave.h"
 
 namespace suco {
 
@@ -58,7 +64,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmeansPass k, int with_hist) 
                 for (int j = 0; j < WMAX; ++j) {
                     if (j < w) {
                         const double dd = x[j] - cs[c * w + j];
-                        s = s + dd * dd;
+                        s = s + (k.metric ? fabs(dd) : dd * dd);
                     }
                 }
                 if (c == 0 || s < bd) { bd = s; best = c; }
@@ -68,7 +74,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmeansPass k, int with_hist) 
                 double s = 0.0;
                 for (int j = 0; j < w; ++j) {
                     const double dd = (double)xp[j] - cg[c * w + j];
-                    s = s + dd * dd;
+                    s = s + (k.metric ? fabs(dd) : dd * dd);
                 }
                 if (c == 0 || s < bd) { bd = s; best = c; }
             }
@@ -83,29 +89,34 @@ __global__ __launch_bounds__(256) void k_km_assign(KmeansPass k, int with_hist) 
     }
 }
 
-// grid = 2*ns, block = 128 (>= sk)
-__global__ __launch_bounds__(128) void k_km_scan(KmeansPass k) {
-    __shared__ uint32_t tot[kMaxSqrtK];
-    const int g = blockIdx.x, c = threadIdx.x, sk = k.sk;
-    if (c < sk) {
-        uint32_t run = 0;
-        uint32_t *bh = k.bh + (int64_t)g * k.nb * sk + c;
-        for (int b = 0; b < k.nb; ++b) {
-            const uint32_t v = bh[(int64_t)b * sk];
-            bh[(int64_t)b * sk] = run;
-            run += v;
-        }
-        tot[c] = run;
+// One block per (label, half): the label's block counts become exclusive
+// offsets over the blocks (a block-wide scan per 256 blocks), and the
+// label's total goes to cbase[label + 1].
+__global__ __launch_bounds__(256) void k_km_scan(KmeansPass k) {
+    __shared__ uint32_t red[256 / kWave + 1];
+    const int c = blockIdx.x, g = blockIdx.y, t = threadIdx.x, sk = k.sk;
+    uint32_t *bh = k.bh + (int64_t)g * k.nb * sk + c;
+    uint32_t run = 0;
+    for (int b0 = 0; b0 < k.nb; b0 += 256) {
+        const int b = b0 + t;
+        const uint32_t v = b < k.nb ? bh[(int64_t)b * sk] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<256>(v, red, &tot);
+        if (b < k.nb) bh[(int64_t)b * sk] = run + ex;
+        run += tot;
     }
-    __syncthreads();
-    if (c == 0) {
-        uint32_t *cb = k.cbase + (int64_t)g * (sk + 1);
-        uint32_t run = 0;
-        for (int j = 0; j < sk; ++j) {
-            cb[j] = run;
-            run += tot[j];
-        }
-        cb[sk] = run;
+    if (t == 0) k.cbase[(int64_t)g * (sk + 1) + c + 1] = run;
+}
+
+// One thread per half: label totals into label starts.
+__global__ void k_km_bases(KmeansPass k) {
+    const int g = blockIdx.x;
+    uint32_t *cb = k.cbase + (int64_t)g * (k.sk + 1);
+    uint32_t run = 0;
+    cb[0] = 0u;
+    for (int j = 0; j < k.sk; ++j) {
+        run += cb[j + 1];
+        cb[j + 1] = run;
     }
 }
 
@@ -138,28 +149,120 @@ __global__ __launch_bounds__(256) void k_km_scatter(KmeansPass k) {
     }
 }
 
+// One block per (centre, half): the centre becomes the FP64 mean of its
+// members (ascending id), summed group by group: thread t sums the groups t,
+// t + 256, ... of kSumGroup consecutive members, each in order from zero, for
+// up to 8 dimensions at a time, and the group sums are then added in group
+// order; an empty label keeps its centre.
+constexpr int kSumGroup = 256;
 __global__ __launch_bounds__(256) void k_km_update(KmeansPass k) {
 #pragma clang fp contract(off)
-    const int g = blockIdx.y;
+    __shared__ double part[256][8];
+    const int c = blockIdx.x, g = blockIdx.y, t = threadIdx.x;
     const HalfDims hd = k.halves[g];
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= k.sk * hd.w) return;
-    const int c = t / hd.w, j = t - c * hd.w;
     const uint32_t *cb = k.cbase + (int64_t)g * (k.sk + 1);
     const uint32_t s0 = cb[c], s1 = cb[c + 1];
     if (s1 == s0) return;
-    const uint32_t *ord = k.order + (int64_t)g * k.n;
-    const float *xc = k.X + hd.dim0 + j;
-    double s = 0.0;
-#pragma unroll 8
-    for (uint32_t m = s0; m < s1; ++m) s = s + (double)xc[(int64_t)ord[m] * k.d];
-    k.cent64[(int64_t)k.sk * hd.dim0 + t] = s / (double)(s1 - s0);
+    const uint32_t m = s1 - s0, ngroups = (m + kSumGroup - 1) / kSumGroup;
+    const uint32_t *ord = k.order + (int64_t)g * k.n + s0;
+    double *cent = k.cent64 + (int64_t)k.sk * hd.dim0 + (int64_t)c * hd.w;
+    for (int j0 = 0; j0 < hd.w; j0 += 8) {
+        const int nj = hd.w - j0 < 8 ? hd.w - j0 : 8;
+        double tot = 0.0;                                   // dimension j0 + t, threads t < nj
+        for (uint32_t g0 = 0; g0 < ngroups; g0 += 256) {
+            const uint32_t gi = g0 + (uint32_t)t;
+            double acc[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+            if (gi < ngroups) {
+                const uint32_t r0 = gi * kSumGroup, r1 = r0 + kSumGroup < m ? r0 + kSumGroup : m;
+#pragma unroll 4
+                for (uint32_t r = r0; r < r1; ++r) {
+                    const float *xr = k.X + (int64_t)ord[r] * k.d + hd.dim0 + j0;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (j < nj) acc[j] = acc[j] + (double)xr[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) part[t][j] = acc[j];
+            __syncthreads();
+            if (t < nj) {
+                const uint32_t ng = ngroups - g0 < 256u ? ngroups - g0 : 256u;
+                for (uint32_t u = 0; u < ng; ++u) tot = tot + part[u][t];
+            }
+            __syncthreads();
+        }
+        if (t < nj) cent[j0 + t] = tot / (double)m;
+    }
 }
 
 __global__ void k_cent_to_f32(const double *c64, float *c32, int64_t m) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < m) c32[t] = (float)c64[t];
 }
+
+// Order-preserving bit patterns of floats: unsigned comparison of the keys
+// is the comparison of the values (-0 below +0).
+__device__ __forceinline__ uint32_t float_key(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// One block per (centre, half).  Each coordinate of the centre becomes the
+// lower median of its m members' values, the ceil(m/2)-th smallest, found by
+// a radix select over the values' keys, 8 bits a pass from the top, for up to
+// kMedDims coordinates at a time (a histogram of the next digit among the
+// members whose key matches the prefix found so far); an empty cluster keeps
+// its centre.  The members are read in the label order the scatter produced.
+constexpr int kMedDims = 16;
+__global__ __launch_bounds__(256) void k_km_median(KmeansPass k) {
+    __shared__ uint32_t hist[kMedDims][256];
+    __shared__ uint32_t pre[kMedDims], rank[kMedDims];
+    const int c = blockIdx.x, g = blockIdx.y, t = threadIdx.x;
+    const HalfDims hd = k.halves[g];
+    const uint32_t *cb = k.cbase + (int64_t)g * (k.sk + 1);
+    const uint32_t s0 = cb[c], s1 = cb[c + 1];
+    if (s1 == s0) return;
+    const uint32_t m = s1 - s0;
+    const uint32_t *ord = k.order + (int64_t)g * k.n + s0;
+    for (int j0 = 0; j0 < hd.w; j0 += kMedDims) {
+        const int nj = hd.w - j0 < kMedDims ? hd.w - j0 : kMedDims;
+        if (t < kMedDims) { pre[t] = 0u; rank[t] = (m + 1) / 2; }      // 1-based rank of the lower median
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int e = t; e < kMedDims * 256; e += 256) (&hist[0][0])[e] = 0u;
+            __syncthreads();
+            const uint32_t hmask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+            for (uint32_t r = t; r < m; r += 256) {
+                const float *xr = k.X + (int64_t)ord[r] * k.d + hd.dim0 + j0;
+                for (int j = 0; j < nj; ++j) {
+                    const uint32_t key = float_key(xr[j]);
+                    if ((key & hmask) == (pre[j] & hmask)) atomicAdd(&hist[j][(key >> shift) & 255u], 1u);
+                }
+            }
+            __syncthreads();
+            if (t < nj) {
+                uint32_t run = 0;
+                const uint32_t rk = rank[t];
+                int b = 0;
+                for (; b < 255; ++b) {
+                    const uint32_t h = hist[t][b];
+                    if (run + h >= rk) break;
+                    run += h;
+                }
+                pre[t] |= (uint32_t)b << shift;
+                rank[t] = rk - run;
+            }
+            __syncthreads();
+        }
+        if (t < nj) k.cent64[(int64_t)k.sk * hd.dim0 + (int64_t)c * hd.w + j0 + t] = (double)key_float(pre[t]);
+        __syncthreads();
+    }
+}
+
 
 // One wave per (tile, subspace): counting sort of the tile's ids by cell,
 // stable (ids ascending inside each cell), written tile-major.
@@ -272,7 +375,10 @@ hipError_t launch_km_assign(const KmeansPass &k, bool with_hist, hipStream_t s) 
 }
 
 hipError_t launch_km_scan(const KmeansPass &k, hipStream_t s) {
-    hipLaunchKernelGGL(k_km_scan, dim3((unsigned)(2 * k.ns)), dim3(128), 0, s, k);
+    hipLaunchKernelGGL(k_km_scan, dim3((unsigned)k.sk, (unsigned)(2 * k.ns)), dim3(256), 0, s, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_km_bases, dim3((unsigned)(2 * k.ns)), dim3(1), 0, s, k);
     return hipGetLastError();
 }
 
@@ -282,8 +388,12 @@ hipError_t launch_km_scatter(const KmeansPass &k, hipStream_t s) {
 }
 
 hipError_t launch_km_update(const KmeansPass &k, hipStream_t s) {
-    const unsigned bx = (unsigned)((k.sk * k.wmax + 255) / 256);
-    hipLaunchKernelGGL(k_km_update, dim3(bx, (unsigned)(2 * k.ns)), dim3(256), 0, s, k);
+    hipLaunchKernelGGL(k_km_update, dim3((unsigned)k.sk, (unsigned)(2 * k.ns)), dim3(256), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_km_median(const KmeansPass &k, hipStream_t s) {
+    hipLaunchKernelGGL(k_km_median, dim3((unsigned)k.sk, (unsigned)(2 * k.ns)), dim3(256), 0, s, k);
     return hipGetLastError();
 }
 

@@ -514,6 +514,7 @@ int suco_mlp_predict(suco_mlp *p, const float *F, int64_t m, float scale, float 
 
 int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float *F, void *stream) {
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (ix->metric) return fail(SUCO_E_UNSUPPORTED, "the learned budget's features are Euclidean (not SUCO_BUILD_L1)");
     if (nq < 0 || (nq > 0 && (!Q || !F))) return fail(SUCO_E_INVAL, "Q and F must not be NULL");
     if (nq == 0) return SUCO_OK;
     DeviceGuard dg(ix->device);
@@ -547,6 +548,7 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
                                   float *dists, float *alpha_used, void *stream) {
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
     if (!mlp_ok(p)) return fail(SUCO_E_STATE, "invalid or freed model handle");
+    if (ix->metric) return fail(SUCO_E_UNSUPPORTED, "the learned budget's features are Euclidean (not SUCO_BUILD_L1)");
     if (p->n_in != 2 * ix->ns + 1) return fail(SUCO_E_INVAL, "the model's n_in must be 2*n_s + 1");
     if (!(scale > 0.f)) return fail(SUCO_E_INVAL, "scale must be positive");
     if (!(alpha_min > 0.f && alpha_min <= alpha_max && alpha_max <= 1.f))

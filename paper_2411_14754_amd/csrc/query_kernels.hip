@@ -37,6 +37,10 @@ __device__ __forceinline__ uint32_t count_A_dev(double alpha, int64_t n) {
     return (uint32_t)a;
 }
 
+// A half's smallest centre distance as exported: Euclidean (the square root of
+// the squared distance) or Manhattan.
+__device__ __forceinline__ float feat_of(float v, int metric) { return metric ? v : __fsqrt_rn(v); }
+
 // ============================================================== activate ==
 // Block of NT threads (NT >= sqrt_k) per (query, subspace).
 //
@@ -130,9 +134,102 @@ __device__ __forceinline__ bool activate_walk(const QueryPass &a, const int ql, 
     for (int j = 0; j < kWalkCols; ++j)
         if (j < ptr) out[off + j] = (uint16_t)(lane * sk + I2[j]);
     if (a.feat != nullptr && lane < 2)
-        a.feat[(int64_t)ql * 2 * ns + 2 * i + lane] = __fsqrt_rn(lane == 0 ? __uint_as_float(d1min) : D2[0]);
+        a.feat[(int64_t)ql * 2 * ns + 2 * i + lane] = feat_of(lane == 0 ? __uint_as_float(d1min) : D2[0], a.ix.metric);
     if (lane == 0) {
         a.ncells[ql * ns + i] = (int32_t)ntot;
+        a.aprime[ql * ns + i] = (int32_t)W;
+    }
+    return true;
+}
+
+// Multi-sequence (the inverted multi-index traversal Sec. 4.2 compares
+// Dynamic Activation with), for sqrt_k <= 64: a priority queue of cells
+// ordered by (key, r1, r2), seeded with (0, 0); taking a cell pushes its
+// neighbours (r1 + 1, r2) and (r1, r2 + 1) unless they were pushed before (a
+// bitmap over the rank grid), and the traversal stops once the points taken
+// reach A.  The queue is a pool of 64 x kMsSlots entries held in the wave's
+// registers, (key bits << 32 | r1 << 16 | r2) with the cell's size beside
+// it; taking the smallest is a wave minimum.  The queue holds at most one
+// entry more than the cells taken so far, so it cannot overflow before
+// 64 * kMsSlots - 1 cells are taken; a longer traversal returns false and
+// the caller takes the general path, which activates the same cells.  The
+// cells come out in retrieval order (Dynamic Activation's paths write them
+// row by row; the sets are equal).
+constexpr int kMsSlots = 8;
+
+__device__ __forceinline__ bool activate_ms(const QueryPass &a, const int ql, const int i, const float *Ds0,
+                                            const float *Ds1, const int *Ix0, const int *Ix1, const uint32_t A,
+                                            uint32_t *pushed) {
+    const int sk = a.ix.sk, K = a.ix.K, ns = a.ix.ns, lane = threadIdx.x;
+    const uint64_t kEmpty = ~0ull;
+    const uint32_t *cs = a.ix.csize + (int64_t)i * K;
+    for (int w = lane; w < (K + 31) / 32; w += kWave) pushed[w] = 0u;
+    __syncthreads();
+    uint64_t key[kMsSlots];
+    uint32_t csz[kMsSlots];
+#pragma unroll
+    for (int j = 0; j < kMsSlots; ++j) { key[j] = kEmpty; csz[j] = 0u; }
+    auto entry = [&](int r1, int r2) -> uint64_t {
+        return ((uint64_t)__float_as_uint(Ds0[r1] + Ds1[r2]) << 32) | ((uint32_t)r1 << 16) | (uint32_t)r2;
+    };
+    if (lane == 0) {
+        key[0] = entry(0, 0);
+        csz[0] = cs[Ix0[0] * sk + Ix1[0]];
+        pushed[0] = 1u;
+    }
+    __syncthreads();
+    uint16_t *out = a.cells + ((int64_t)ql * ns + i) * K;
+    uint32_t W = 0;
+    int nc = 0;
+    for (;;) {
+        uint64_t lm = key[0];
+#pragma unroll
+        for (int j = 1; j < kMsSlots; ++j) lm = key[j] < lm ? key[j] : lm;
+        const uint32_t mh = wave_min((uint32_t)(lm >> 32));
+        if (mh == 0xffffffffu) break;                            // every cell taken
+        const uint32_t ml = wave_min((uint32_t)(lm >> 32) == mh ? (uint32_t)lm : 0xffffffffu);
+        const uint64_t m = ((uint64_t)mh << 32) | ml;
+        uint32_t sz = 0u;
+        bool own = false;
+#pragma unroll
+        for (int j = 0; j < kMsSlots; ++j)
+            if (key[j] == m) { key[j] = kEmpty; sz = csz[j]; own = true; }
+        const int ol = __ffsll((unsigned long long)__ballot(own)) - 1;
+        sz = (uint32_t)__builtin_amdgcn_readlane((int)sz, ol);
+        const int r1 = (int)(ml >> 16), r2 = (int)(ml & 0xffffu);
+        if (lane == 0) out[nc] = (uint16_t)(Ix0[r1] * sk + Ix1[r2]);
+        ++nc;
+        W += sz;
+        if (W >= A) break;
+        if (nc == kWave * kMsSlots - 1) return false;            // the pool could overflow
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int n1 = r1 + e, n2 = r2 + 1 - e;
+            if (n1 >= sk || n2 >= sk) continue;
+            const int c = n1 * sk + n2;
+            const uint32_t word = pushed[c >> 5];
+            if (word & (1u << (c & 31))) continue;
+            if (lane == 0) pushed[c >> 5] = word | (1u << (c & 31));
+            bool fr = false;
+#pragma unroll
+            for (int j = 0; j < kMsSlots; ++j) fr |= key[j] == kEmpty;
+            const int fl = __ffsll((unsigned long long)__ballot(fr)) - 1;
+            if (lane == fl) {
+                bool placed = false;
+#pragma unroll
+                for (int j = 0; j < kMsSlots; ++j)
+                    if (!placed && key[j] == kEmpty) {
+                        key[j] = entry(n1, n2);
+                        csz[j] = cs[Ix0[n1] * sk + Ix1[n2]];
+                        placed = true;
+                    }
+            }
+        }
+    }
+    if (a.feat != nullptr && lane < 2)
+        a.feat[(int64_t)ql * 2 * ns + 2 * i + lane] = feat_of(lane == 0 ? Ds0[0] : Ds1[0], a.ix.metric);
+    if (lane == 0) {
+        a.ncells[ql * ns + i] = (int32_t)nc;
         a.aprime[ql * ns + i] = (int32_t)W;
     }
     return true;
@@ -174,7 +271,7 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
             for (int u = 0; u < 8; ++u) {
                 if (j0 + u < hd.w) {
                     const float t2 = qv[u] - cv[u];
-                    s = fmaf(t2, t2, s);
+                    s = dist_acc(s, t2, a.ix.metric);
                 }
             }
         }
@@ -218,14 +315,14 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
                     for (int u = 0; u < 8; ++u) {
                         if (j0 + u < w[h]) {
                             const float t2 = qv[h][u] - cv[h][u];
-                            v[h] = fmaf(t2, t2, v[h]);
+                            v[h] = dist_acc(v[h], t2, a.ix.metric);
                         }
                     }
             }
         }
         const double alpha0 = a.alpha_qd ? a.alpha_qd[ql] : (a.alpha_q ? (double)a.alpha_q[ql] : a.alpha);
         const uint32_t A0 = count_A_dev(alpha0, a.ix.n);
-        if ((uint64_t)A0 * (uint64_t)K <= (uint64_t)kWalkRatio * (uint64_t)a.ix.n &&
+        if (a.ix.act_form == 0 && (uint64_t)A0 * (uint64_t)K <= (uint64_t)kWalkRatio * (uint64_t)a.ix.n &&
             activate_walk(a, ql, i, v[0], v[1], live, A0))
             return;
 #pragma unroll
@@ -239,6 +336,11 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
                 Ds[h][r] = v[h];
                 Ix[h][r] = tid;
             }
+        }
+        if (a.ix.act_form == 1) {
+            __shared__ uint32_t pushed[kWave * kWave / 32];
+            __syncthreads();
+            if (activate_ms(a, ql, i, Ds[0], Ds[1], Ix[0], Ix[1], A0, pushed)) return;
         }
     } else {
         for (int t = tid; t < 2 * sk; t += NT) {
@@ -295,7 +397,7 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
         }
     }
     __syncthreads();
-    if (a.feat != nullptr && tid < 2) a.feat[(int64_t)ql * 2 * ns + 2 * i + tid] = __fsqrt_rn(Ds[tid][0]);
+    if (a.feat != nullptr && tid < 2) a.feat[(int64_t)ql * 2 * ns + 2 * i + tid] = feat_of(Ds[tid][0], a.ix.metric);
 
     const double alpha = a.alpha_qd ? a.alpha_qd[ql] : (a.alpha_q ? (double)a.alpha_q[ql] : a.alpha);
     const uint32_t A = count_A_dev(alpha, a.ix.n);
@@ -377,6 +479,7 @@ __device__ __forceinline__ int pass_nq(const int *nq_dev, int q_base, int nq) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_activate(QueryPass a) {
     const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * a.ix.ns;
+    if (a.ntl != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.ntl = 0;   // read after this kernel
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         activate_item<NT>(a, item);
         __syncthreads();
@@ -795,8 +898,13 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     extern __shared__ uint32_t sc[];   // TILE/4 words
     __shared__ CollideLds<NT> L;
+    // with the sparse step: only the queries it left, from its list; they are
+    // few, so each is spread over more tile groups (about 2,048 blocks' worth
+    // of items in all, as the host's choice for a full pass)
+    const int nt = a.tlist != nullptr ? *a.ntl : pass_nq(a.nq_dev, a.q_base, a.nq);
+    if (a.tlist != nullptr) a.tgroups = nt > 0 ? min(a.ix.P, max(1, (2048 + nt - 1) / nt)) : 1;
     const int S = a.tgroups;
-    const int items = pass_nq(a.nq_dev, a.q_base, a.nq) * S;
+    const int items = nt * S;
     if ((int)blockIdx.x >= items) return;
     {
         uint4 *z = reinterpret_cast<uint4 *>(sc);
@@ -812,8 +920,7 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
     const int i = threadIdx.x / RJ, jj = threadIdx.x - i * RJ;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int rq = item / S, g = item - rq * S;
-        const int ql = a.order ? a.order[rq] : rq;   // heaviest queries first
-        if (a.route != nullptr && a.route[ql] == 0) continue;   // counted by the sparse step
+        const int ql = a.tlist ? a.tlist[rq] : (a.order ? a.order[rq] : rq);   // heaviest queries first
         // this thread's subspace: activated cell count and its cell of the first batch
         const int my_nc = i < ns ? a.ncells[ql * ns + i] : 0;
         const int c_first = jj < my_nc ? (int)a.cells[((int64_t)ql * ns + i) * a.ix.K + jj] : 0;
@@ -838,8 +945,9 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 // O(alpha*n*N_s) per query, Sec. 4.3) instead of visiting every tile of the
 // id range, and everything after the id reads stays in LDS:
 //  1. the query's activated cells become runs of the cell-major id copy (one
-//     run per cell); one walk over their ids places the low 12 bits of each
-//     into cb slots of its bucket;
+//     run per cell); one walk over all their ids as a single sequence (every
+//     thread an equal share) places the low 12 bits of each into cb slots of
+//     its bucket;
 //  2. a wave takes a bucket: 4-bit scores are counted in the wave's 2 KB
 //     window (a 32-bit LDS atomic add of 1 << 4*(low & 7): an id occurs once
 //     per subspace and N_s <= 15, so no nibble carries), then every id claims
@@ -855,8 +963,8 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     with all or none of theirs copy them, and the one bucket cut inside
 //     finds its cut id by marking its level-T ids in a 4096-bit map and
 //     counting.  Candidates are appended in no particular order.
-// A query is left to the tiled steps (route 1) when N_s > 15, it has more
-// than kSpMaxRuns activated cells, a bucket receives more than cb ids, more
+// A query is left to the tiled steps (route 1) when N_s > 15, it has
+// kSpMaxRuns activated cells or more, a bucket receives more than cb ids, more
 // than kSpHCap points score 2 or more, or T = 0 (fewer than B points collide:
 // the score-0 points are the tiled selection's case); otherwise route 0, and
 // the tiled collision and selection kernels skip the query.
@@ -869,40 +977,47 @@ struct SparseLds {
     uint32_t out;                    // candidates written
     int nruns, flag, cutb;
     uint32_t cut;
+    uint32_t crun[kSpMaxChunks];     // run holding position 1024*q of the walk's sequence
 };
 
-// Every id of the query's activated cells, in runs: wave w takes runs w,
-// w + kSpWaves, ... two at a time, a run's ids read by consecutive lanes,
-// sixteen loads in flight per lane; f gets the sixteen ids, a bit mask of the
-// valid ones and a mask of the slots with a valid id in some lane (the same
-// in every lane, so f skips the others without divergence).  The loads are
-// unconditional (a slot past its run's end reads the run's first id, an empty
-// run's start is 0), so every id handed to f is a point id and none of the
-// loads waits for another.
+// Every id of the query's activated cells, as one sequence: runs[r] =
+// (start of run r in ids32, its first position in the sequence),
+// runs[nruns].y = the total, and crun[q] = the run holding position 1024*q.
+// Thread t takes positions t, t + kSpThreads, ..., 2*kSpU of them per step:
+// position p lies in chunk p / 1024, the same for every thread of the step, so
+// its run is found from that chunk's first run in a step or two, independently
+// of the step's other positions; then the loads are issued together.
+// Consecutive threads read consecutive ids of a run.  The loads are
+// unconditional (a position past the end reads the first slot of run 0), so
+// none waits for another; f gets the ids, a bit mask of the valid ones and a
+// mask of the slots valid in some thread of the block.
 constexpr int kSpU = 8;
+static_assert(kSpThreads == 1024, "a step's positions are one per 1024-position chunk");
 template <class F>
-__device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, int nruns, F &&f) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    for (int r = w; r < nruns; r += 2 * kSpWaves) {
-        const uint2 r0 = runs[r];
-        const uint2 r1 = r + kSpWaves < nruns ? runs[r + kSpWaves] : make_uint2(0u, 0u);
-        const uint32_t *s0 = a.ix.ids32 + r0.x, *s1 = a.ix.ids32 + r1.x;
-        const uint32_t len = r0.y > r1.y ? r0.y : r1.y;
-        for (uint32_t m0 = 0; m0 < len; m0 += (uint32_t)(kSpU * kWave)) {
-            const uint32_t m = m0 + (uint32_t)lane;
-            uint32_t id[2 * kSpU], vm = 0u, um = 0u;
+__device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, const uint32_t *crun,
+                                        uint32_t total, F &&f) {
+    constexpr int U = 2 * kSpU;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t base = 0; base < total; base += (uint32_t)(U * kSpThreads)) {
+        uint32_t at[U], vm = 0u, um = 0u;
 #pragma unroll
-            for (int u = 0; u < kSpU; ++u) {
-                const uint32_t mm = m + (uint32_t)(u * kWave), mb = m0 + (uint32_t)(u * kWave);
-                id[u] = s0[mm < r0.y ? mm : 0u];
-                id[kSpU + u] = s1[mm < r1.y ? mm : 0u];
-                vm |= (mm < r0.y ? 1u : 0u) << u;
-                vm |= (mm < r1.y ? 1u : 0u) << (kSpU + u);
-                um |= (mb < r0.y ? 1u : 0u) << u;
-                um |= (mb < r1.y ? 1u : 0u) << (kSpU + u);
+        for (int u = 0; u < U; ++u) {
+            const uint32_t p = base + tid + (uint32_t)(u * kSpThreads);
+            const bool v = p < total;
+            int r = 0;
+            if (v) {
+                r = (int)crun[(base >> 10) + (uint32_t)u];
+                while (runs[r + 1].y <= p) ++r;
             }
-            f(id, vm, um);
+            const uint2 rr = runs[r];
+            at[u] = v ? rr.x + (p - rr.y) : rr.x;
+            vm |= (v ? 1u : 0u) << u;
+            um |= (base + (uint32_t)(u * kSpThreads) < total ? 1u : 0u) << u;
         }
+        uint32_t id[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) id[u] = a.ix.ids32[at[u]];
+        f(id, vm, um);
     }
 }
 
@@ -915,12 +1030,16 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
                                               uint32_t *H, uint32_t *sink) {
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int UQ = 4;
+    // a bucket of at most UQ*64 ids (the common case) is read once: the claims
+    // reuse the counting pass's registers
+    uint32_t u0[UQ];
     for (uint32_t j0 = 0; j0 < len; j0 += (uint32_t)(UQ * kWave)) {
         uint32_t u[UQ];
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
             const uint32_t j = j0 + (uint32_t)(q * kWave + lane);
             u[q] = seg[j < len ? j : 0u];
+            u0[q] = u[q];
         }
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
@@ -929,6 +1048,7 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
             atomicAdd(v ? &win[u[q] >> 3] : &sink[lane], v ? 1u << ((u[q] & 7u) << 2) : 0u);
         }
     }
+    const bool one = len <= (uint32_t)(UQ * kWave);
     if (a.scores != nullptr) {
         // dense scores on request (parity tests): lane l writes ids 64l .. 64l + 63 below n
         uint8_t *row = a.scores + (int64_t)ql * a.ix.P * a.ix.TILE;
@@ -950,7 +1070,7 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
             const uint32_t j = j0 + (uint32_t)(q * kWave + lane);
-            u[q] = seg[j < len ? j : 0u];
+            u[q] = one ? u0[q] : seg[j < len ? j : 0u];
         }
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
@@ -1030,13 +1150,19 @@ __device__ __forceinline__ void sp_emit(bool t, uint32_t id, uint32_t *cq, uint3
     if (t && at < B) cq[at] = id;
 }
 
+// A query the sparse step leaves: route 1 and appended to the tiled steps' list.
+__device__ __forceinline__ void leave_to_tiled(const QueryPass &a, const int ql) {
+    a.route[ql] = 1;
+    a.tlist[atomicAdd(a.ntl, 1)] = ql;
+}
+
 __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
     extern __shared__ uint4 sp_dyn[];
     __shared__ SparseLds S;
     const int NB = a.ix.NB, ns = a.ix.ns, K = a.ix.K;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int NBp = sp_nb_padded(NB);
-    uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, length)
+    uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, first position)
     uint32_t *bfill = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);     // [NB] ids per bucket
     uint32_t *bx = bfill + NBp;                                            // [NB] points of score 1, then level-T points
     uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
@@ -1060,7 +1186,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
             if (lane == 0) {
                 S.nruns = (int)nr;
-                S.flag = (ns > kSpMaxNs || nr > (uint32_t)kSpMaxRuns || cb == 0u) ? 1 : 0;
+                S.flag = (ns > kSpMaxNs || nr >= (uint32_t)kSpMaxRuns || cb == 0u) ? 1 : 0;
                 S.nh = 0u;
                 S.out = 0u;
             }
@@ -1069,26 +1195,38 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         for (int b = tid; b < NB; b += kSpThreads) bfill[b] = 0u;
         __syncthreads();
         if (S.flag) {
-            if (tid == 0) a.route[ql] = 1;
+            if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;
         }
-        // ---- runs of the activated cells
+        // ---- runs of the activated cells (a thread per run, nruns < kSpThreads)
+        // and their first positions in the sequence of all activated ids
         const int nruns = S.nruns;
-        for (int r = tid; r < nruns; r += kSpThreads) {
+        uint32_t rstart = 0u, rlen = 0u;
+        if (tid < nruns) {
             int i = 0;
-            while (i + 1 < ns && S.cpre[i + 1] <= (uint32_t)r) ++i;
-            const int j = r - (int)S.cpre[i];
+            while (i + 1 < ns && S.cpre[i + 1] <= (uint32_t)tid) ++i;
+            const int j = tid - (int)S.cpre[i];
             const int c = a.cells[((int64_t)ql * ns + i) * K + j];
             const uint32_t *co = a.ix.coffs + (int64_t)i * (K + 1);
-            const uint32_t st = co[c], len = co[c + 1] - st;
-            runs[r] = make_uint2(len ? (uint32_t)((int64_t)i * a.ix.n) + st : 0u, len);
+            rstart = co[c];
+            rlen = co[c + 1] - rstart;
+            rstart = rlen ? (uint32_t)((int64_t)i * a.ix.n) + rstart : 0u;   // an empty run points at id 0's slot
         }
+        uint32_t total;
+        const uint32_t rpos = block_excl_scan<kSpThreads>(rlen, S.red, &total);
+        if (total > (uint32_t)NB * cb) {              // more ids than the slots hold: some bucket overflows
+            if (tid == 0) leave_to_tiled(a, ql);
+            __syncthreads();
+            continue;
+        }
+        if (tid <= nruns) runs[tid] = make_uint2(tid < nruns ? rstart : 0u, tid < nruns ? rpos : total);
+        for (uint32_t q = (rpos + 1023u) >> 10; rlen && (q << 10) < rpos + rlen; ++q) S.crun[q] = (uint32_t)tid;
         __syncthreads();
         // ---- 1. one walk into cb slots per bucket (every id is counted; the
         // query is left to the tiled steps if a bucket overflows); all sixteen
         // atomics of a step are issued before the stores they place
-        sp_walk(a, runs, nruns, [&](const uint32_t (&id)[2 * kSpU], uint32_t vm, uint32_t um) {
+        sp_walk(a, runs, S.crun, total, [&](const uint32_t (&id)[2 * kSpU], uint32_t vm, uint32_t um) {
             uint32_t pos[2 * kSpU];
 #pragma unroll
             for (int u = 0; u < 2 * kSpU; ++u) {
@@ -1105,7 +1243,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         bool over = false;
         for (int b = b0t; b < b1t; ++b) over |= bfill[b] > cb;
         if (__syncthreads_or(over)) {
-            if (tid == 0) a.route[ql] = 1;
+            if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;
         }
@@ -1134,7 +1272,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         }
         const uint32_t nhl = S.nh;
         if (T == 0 || nhl > (uint32_t)kSpHCap) {
-            if (tid == 0) a.route[ql] = 1;
+            if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;
         }
@@ -1222,6 +1360,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
 // Points in the activated cells of every (query, subspace): one wave each.
 __global__ __launch_bounds__(kWave) void k_cell_points(SizesPass a) {
     const int item = blockIdx.x, q = item / a.ix.ns, i = item - q * a.ix.ns;
+    if (a.ntl != nullptr && item == 0 && threadIdx.x == 0) *a.ntl = 0;
     if (q >= a.nq) return;
     const int nc = a.ncells[item];
     const uint16_t *cl = a.cells + (int64_t)item * a.ix.K;
@@ -1492,14 +1631,13 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
     extern __shared__ uint32_t bm[];       // per wave: a bitmap of TILE bits
     __shared__ uint32_t sum[(NT / kWave) * 64];    // per wave: its summary (bit w of word s = bitmap word 32s + w non-zero)
-    const int items = pass_nq(a.nq_dev, a.q_base, a.nq);
+    const int items = a.tlist != nullptr ? *a.ntl : pass_nq(a.nq_dev, a.q_base, a.nq);
     if ((int)blockIdx.x >= items) return;
     for (int w = threadIdx.x; w < (NT / kWave) * (a.ix.TILE >> 5); w += NT) bm[w] = 0u;
     for (int w = threadIdx.x; w < (NT / kWave) * 64; w += NT) sum[w] = 0u;
     __syncthreads();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        if (a.route != nullptr && a.route[item] == 0) continue;   // selected by the sparse step
-        select_item<NT>(a, item, bm, sum);
+        select_item<NT>(a, a.tlist != nullptr ? a.tlist[item] : item, bm, sum);
         __syncthreads();
     }
 }
@@ -1628,7 +1766,7 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
     };
     bool int_path = false;
     if constexpr (ROWS8) {
-        if ((r.d & 15) == 0 && r.d <= 256) {
+        if (r.metric == 0 && (r.d & 15) == 0 && r.d <= 256) {
             const float *qf = r.Q + (int64_t)ql * r.d;
             bool ok = true;
             for (int t = threadIdx.x; t < r.d; t += NT) {
@@ -1717,11 +1855,10 @@ __device__ __forceinline__ void rerank_item(const RerankPass &r, const int item)
                             } else {
                                 xv = x[g][u];
                             }
-                            float t;
-                            t = xv.x - qr[u].x; acc = fmaf(t, t, acc);
-                            t = xv.y - qr[u].y; acc = fmaf(t, t, acc);
-                            t = xv.z - qr[u].z; acc = fmaf(t, t, acc);
-                            t = xv.w - qr[u].w; acc = fmaf(t, t, acc);
+                            acc = dist_acc(acc, xv.x - qr[u].x, r.metric);
+                            acc = dist_acc(acc, xv.y - qr[u].y, r.metric);
+                            acc = dist_acc(acc, xv.z - qr[u].z, r.metric);
+                            acc = dist_acc(acc, xv.w - qr[u].w, r.metric);
                         }
                     }
                     for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
@@ -1763,7 +1900,7 @@ __global__ __launch_bounds__(NT) void k_rerank(RerankPass r) {
     }
 }
 
-// One wave per query: merge the parts' lists, write ids and Euclidean distances.
+// One wave per query: merge the parts' lists, write ids and distances.
 __device__ __forceinline__ void merge_item(const RerankPass &r, const int ql) {
     const int lane = threadIdx.x, k = r.k;
     const uint64_t *pk = r.part_keys + (int64_t)ql * r.parts * k;
@@ -1778,8 +1915,10 @@ __device__ __forceinline__ void merge_item(const RerankPass &r, const int ql) {
     }
     if (lane < k) {
         r.ids[(int64_t)ql * k + lane] = (int32_t)(uint32_t)(best & 0xffffffffu);
-        // Euclidean distance: FP64 square root of the FP32 squared distance, rounded once
-        r.dists[(int64_t)ql * k + lane] = (float)sqrt((double)__uint_as_float((uint32_t)(best >> 32)));
+        // Euclidean distance: FP64 square root of the FP32 squared distance, rounded
+        // once; Manhattan distance (SuCo-L1): the FP32 sum itself
+        const float v = __uint_as_float((uint32_t)(best >> 32));
+        r.dists[(int64_t)ql * k + lane] = r.metric ? v : (float)sqrt((double)v);
     }
 }
 
@@ -1839,9 +1978,17 @@ Launch plan_activate(const QueryPass &p, int cap) {
     return L;
 }
 
+// With the sparse step on, the tiled steps take only the queries it leaves,
+// counted on the device: their grids are capped at this many blocks, which
+// stride over the listed queries (few or none in the common case, where a
+// grid sized for every query's tile groups would spend its time dispatching
+// idle blocks; all of them when every query has too many activated points).
+constexpr int kTiledGrid = 8192;
+
 Launch plan_collide(const QueryPass &p, int cap) {
     Launch L;
     L.lds = (size_t)p.ix.TILE;
+    if (p.tlist != nullptr && cap == 0) cap = kTiledGrid;
     const int64_t items = (int64_t)p.nq * p.tgroups;
     L.grid = dim3(grid_for(items, cap));
     L.block = dim3(512);
@@ -1881,6 +2028,7 @@ constexpr int kSelectThreads = 128;
 
 Launch plan_select(const QueryPass &p, int cap) {
     Launch L;
+    if (p.tlist != nullptr && cap == 0) cap = kTiledGrid;
     L.lds = (size_t)(kSelectThreads / kWave) * (p.ix.TILE / 8);
     L.grid = dim3(grid_for(p.nq, cap));
     L.block = dim3(kSelectThreads);

@@ -57,6 +57,8 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
         return fail(SUCO_E_UNSUPPORTED, "the device has too little LDS per work-group for this shape");
     if (p && (p->flags & SUCO_BUILD_BF16) && d % 8)
         return fail(SUCO_E_UNSUPPORTED, "SUCO_BUILD_BF16 needs d to be a multiple of 8");
+    if (p && (p->flags & SUCO_BUILD_BF16) && (p->flags & SUCO_BUILD_L1))
+        return fail(SUCO_E_UNSUPPORTED, "the split-precision form is Euclidean only (no SUCO_BUILD_L1)");
     suco_index *ix = new (std::nothrow) suco_index();
     if (!ix) return fail(SUCO_E_NOMEM, "host allocation failed");
     ix->device = dev;
@@ -64,6 +66,7 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     ix->no_byte_rows = p && (p->flags & SUCO_BUILD_NO_BYTE_ROWS);
     ix->no_sparse = p && (p->flags & SUCO_BUILD_NO_SPARSE);
     ix->want_bf16 = p && (p->flags & SUCO_BUILD_BF16);
+    ix->metric = p && (p->flags & SUCO_BUILD_L1) ? 1 : 0;
     ix->tile_req = p ? p->tile_max : 0;
     ix->chunk_req = p ? std::max(0, p->query_chunk) : 0;
     // The sparse collision step: one work-group per CU (160 KB of LDS per CU on
@@ -74,7 +77,7 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
         if (sps < 0) { delete ix; return fail(SUCO_E_HIP, "cannot query the sparse collision kernel's attributes"); }
         const int64_t budget = std::min<int64_t>(max_lds, 160 * 1024) - sps;
         const int64_t cap = (budget - (int64_t)sp_lds_bytes(ix->NB, 0)) / 2 / 8 * 8;
-        ix->sp_cap = cap >= 4096 ? (int)std::min<int64_t>(cap, 1 << 20) : 0;
+        ix->sp_cap = cap >= 4096 ? (int)std::min<int64_t>(cap, (int64_t)kSpMaxChunks * 1024) : 0;
     }
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
     const int64_t per = (n + P0 - 1) / P0;
@@ -208,7 +211,7 @@ int run_kmeans(suco_index *ix, int iters, uint64_t seed, hipStream_t st) {
 
     KmeansPass kp{};
     kp.X = ix->X; kp.n = n; kp.d = d; kp.ns = ns; kp.sk = sk; kp.nb = (int)((n + 255) / 256); kp.wmax = wmax;
-    kp.halves = ix->halves; kp.assign = ix->assign;
+    kp.halves = ix->halves; kp.assign = ix->assign; kp.metric = ix->metric;
     double *cent64 = nullptr;
     uint32_t *bh = nullptr, *cbase = nullptr, *order = nullptr;
     if ((rc = dev_alloc(&cent64, (size_t)sk * d)) || (rc = dev_alloc(&bh, (size_t)2 * ns * kp.nb * sk)) ||
@@ -223,7 +226,7 @@ int run_kmeans(suco_index *ix, int iters, uint64_t seed, hipStream_t st) {
         if (it == iters || e != hipSuccess) break;
         if ((e = launch_km_scan(kp, st)) != hipSuccess) break;
         if ((e = launch_km_scatter(kp, st)) != hipSuccess) break;
-        e = launch_km_update(kp, st);
+        e = kp.metric ? launch_km_median(kp, st) : launch_km_update(kp, st);
     }
     if (e == hipSuccess) e = launch_cent_to_f32(cent64, ix->cent, (int64_t)sk * d, st);
     if (e == hipSuccess) e = hipMemcpyAsync(c64.data(), cent64, sizeof(double) * sk * d, hipMemcpyDeviceToHost, st);
@@ -320,7 +323,7 @@ int save_index(const suco_index *ix, const char *path) {
     h.version = 1; h.header_bytes = sizeof(FileHeader);
     h.n = ix->n; h.d = ix->d; h.ns = ix->ns; h.sk = ix->sk;
     h.flags = (ix->no_byte_rows ? SUCO_BUILD_NO_BYTE_ROWS : 0) | (ix->want_bf16 ? SUCO_BUILD_BF16 : 0) |
-              (ix->no_sparse ? SUCO_BUILD_NO_SPARSE : 0);
+              (ix->no_sparse ? SUCO_BUILD_NO_SPARSE : 0) | (ix->metric ? SUCO_BUILD_L1 : 0);
     h.tile_max = ix->tile_req; h.query_chunk = ix->chunk_req;
     if (std::fwrite(&h, sizeof h, 1, out.f) != 1) return fail(SUCO_E_INVAL, "write failed: " + tmp);
     WordHash hs;
@@ -388,6 +391,7 @@ int load_index(const char *path, const suco_build_params *pin, hipStream_t st, s
     suco_build_params p{};
     if (pin) p = *pin;
     else { p.flags = h.flags; p.tile_max = h.tile_max; p.query_chunk = h.query_chunk; }
+    p.flags = (p.flags & ~SUCO_BUILD_L1) | (h.flags & SUCO_BUILD_L1);   // the metric the centres were built for
     suco_index *ix = nullptr;
     if ((rc = index_common(nullptr, h.n, h.d, h.ns, h.sk, &p, st, &ix))) return rc;
     auto drop = [&](int code) {
@@ -444,7 +448,7 @@ Work carve(const suco_index *ix, char *base, size_t C, int64_t B, int k, int par
     w.scores = dense ? c.take<uint8_t>(C * (size_t)ix->P * ix->TILE) : nullptr;
     w.cand = c.take<uint32_t>(C * (size_t)B);
     w.order = c.take<int32_t>(C);
-    w.route = c.take<int32_t>(C);
+    w.route = c.take<int32_t>(2 * C + 1);   // route, then the tiled list and its count
     w.part_keys = c.take<uint64_t>(C * (size_t)parts * k);
     if (bytes) *bytes = c.off;
     return w;
@@ -564,6 +568,8 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         qp.feat = (dbg && dbg->feat) ? dbg->feat + c0 * 2 * ix->ns : nullptr;
         qp.hist = w.hist; qp.lvl = w.lvl; qp.scores = w.scores; qp.cand = w.cand;
         qp.route = ix->sp_cap ? w.route : nullptr;
+        qp.tlist = qp.route ? w.route + C : nullptr;
+        qp.ntl = qp.route ? w.route + 2 * C : nullptr;
         qp.sp_cap = ix->sp_cap;
         if (bo && (bo->flags & SUCO_BF16_S1)) {
             CentreBf16Pass cp{};
@@ -586,6 +592,7 @@ int run_query(const suco_index *cix, const float *Q, int64_t nq, int32_t k, cons
         HIPCHECK(T(kSelect, [&] { return launch_select(qp, st); }));
         RerankPass rp{};
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = qp.Q; rp.cand = w.cand; rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn;
+        rp.metric = ix->metric;
         rp.parts = c32.parts; rp.rows_per_part = c32.rpp; rp.G = c32.G; rp.U = c32.U;
         rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
         if (bo) {
@@ -761,7 +768,17 @@ int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, 
 int suco_index_flags(const suco_index *ix, int32_t *flags) {
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
     if (!flags) return fail(SUCO_E_INVAL, "flags must not be NULL");
-    *flags = (ix->X8 ? SUCO_INDEX_BYTE_ROWS : 0) | (ix->Xb ? SUCO_INDEX_BF16 : 0);
+    *flags = (ix->X8 ? SUCO_INDEX_BYTE_ROWS : 0) | (ix->Xb ? SUCO_INDEX_BF16 : 0) | (ix->metric ? SUCO_INDEX_L1 : 0);
+    return SUCO_OK;
+}
+
+int suco_index_set_activation(suco_index *ix, int32_t form) {
+    if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
+    if (form != SUCO_ACT_DYNAMIC && form != SUCO_ACT_MULTISEQ) return fail(SUCO_E_INVAL, "unknown activation rule");
+    if (form == SUCO_ACT_MULTISEQ && ix->sk > kWave)
+        return fail(SUCO_E_UNSUPPORTED, "the Multi-sequence traversal takes sqrt_k <= 64");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    ix->act_form = form;
     return SUCO_OK;
 }
 
@@ -866,10 +883,12 @@ int suco_collide_select(const suco_index *cix, int64_t nq, const uint16_t *cells
         qp.cand = reinterpret_cast<uint32_t *>(cand) + c0 * B;
         qp.aprime = w.aprime;
         qp.route = ix->sp_cap ? w.route : nullptr;
+        qp.tlist = qp.route ? w.route + C : nullptr;
+        qp.ntl = qp.route ? w.route + 2 * C : nullptr;
         qp.sp_cap = ix->sp_cap;
         if (qp.route) {
             // the sparse step reads the activated points per subspace
-            SizesPass sp{qp.ix, qp.cells, qp.ncells, cn, w.aprime};
+            SizesPass sp{qp.ix, qp.cells, qp.ncells, cn, w.aprime, qp.ntl};
             HIPCHECK(launch(plan_cell_points(sp), &sp, st));
             HIPCHECK(timed(ix, kCollideSparse, st, [&] { return launch(plan_collide_sparse(qp, 0), &qp, st); }));
         }
@@ -907,6 +926,7 @@ int suco_rerank(const suco_index *cix, const float *Q, int64_t nq, const int32_t
         const int cn = (int)std::min<int64_t>((int64_t)C, nq - c0);
         RerankPass rp{};
         rp.X = ix->X; rp.X8 = ix->X8; rp.Q = Q + c0 * ix->d; rp.cand = reinterpret_cast<const uint32_t *>(cand) + c0 * B;
+        rp.metric = ix->metric;
         rp.B = B; rp.n = ix->n; rp.d = ix->d; rp.k = k; rp.nq = cn; rp.parts = c.parts; rp.rows_per_part = c.rpp;
         rp.G = c.G; rp.U = c.U; rp.part_keys = w.part_keys; rp.ids = ids + c0 * k; rp.dists = dists + c0 * k;
         HIPCHECK(timed(ix, kRerank, st, [&] { return launch_rerank(rp, st); }));

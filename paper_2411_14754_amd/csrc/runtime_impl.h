@@ -108,6 +108,8 @@ struct suco_index {
     int NB = 0;                     // buckets of the sparse step
     int sp_cap = 0;                 // its ids per round; 0: the step is off
     bool no_sparse = false;
+    int act_form = 0;               // SUCO_ACT_* (suco_index_set_activation)
+    int metric = 0;                 // 1 with SUCO_BUILD_L1
     bool no_byte_rows = false;
     bool want_bf16 = false;
     int tile_req = 0;               // tile_max and query_chunk as the caller gave them (0 = automatic),
@@ -142,6 +144,8 @@ struct suco_index {
         v.X = X; v.cent = cent; v.halves = halves; v.toffs = toffs; v.ids16 = ids16; v.csize = csize;
         v.coffs = coffs; v.ids32 = ids32;
         v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE; v.NB = NB;
+        v.act_form = act_form;
+        v.metric = metric;
         return v;
     }
 

@@ -31,6 +31,8 @@ struct IndexView {
     int64_t n;
     int d, ns, sk, K, P, TILE;
     int NB;                  // buckets of kSpBucket consecutive ids (sparse collision step)
+    int act_form;            // activation rule: 0 Dynamic Activation, 1 Multi-sequence (sqrt_k <= 64)
+    int metric;              // 0: squared Euclidean keys and re-rank, Euclidean result; 1: Manhattan (SuCo-L1)
 };
 
 // Sparse collision step (query_kernels.hip): ids are grouped in buckets of
@@ -45,6 +47,7 @@ constexpr int kSpMaxNs = 15;        // a 4-bit score
 constexpr int kSpMaxBuckets = 4096; // n <= 2^24
 constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
 constexpr int kSpHCap = 4096;       // points of score >= 2 a query may list
+constexpr int kSpMaxChunks = 128;   // 1024-position chunks of a query's activated ids (the slots hold fewer)
 // Dynamic LDS of the sparse step for NB buckets and `cap` slots: the run
 // table, two per-bucket arrays padded to 16 bytes, the waves' score windows,
 // the list of points of score >= 2 and the slots.
@@ -83,6 +86,8 @@ struct QueryPass {
     int32_t *order_out;       // [nq] written by the ordering kernel
     int32_t *route;           // [nq] 0: scored and selected by the sparse step; 1: by the tiled
                               //   steps; null: no sparse step (every query takes the tiled steps)
+    int32_t *tlist;           // [nq] with route: the queries the sparse step leaves to the tiled
+    int32_t *ntl;             //   steps, and their count (zeroed by the kernel before the sparse step)
     int sp_cap;               // sparse step: ids per round (LDS)
 };
 
@@ -101,6 +106,7 @@ struct RerankPass {
     const int32_t *rows_dev;  // [nq] candidates per query (<= B), or null for B
     int G;                    // lanes per row (power of two)
     int U;                    // float4 slices per lane
+    int metric;               // 0: squared Euclidean, Euclidean result; 1: Manhattan
     uint64_t *part_keys;      // [nq][parts][k] (squared distance bits << 32 | id)
     int32_t *ids;             // [nq][k]
     float *dists;             // [nq][k]
@@ -130,6 +136,7 @@ struct SizesPass {
     const int32_t *ncells;    // [nq][ns]
     int nq;
     int32_t *aprime;          // [nq][ns]
+    int32_t *ntl;             // count of the tiled list, zeroed here, or null
 };
 Launch plan_cell_points(const SizesPass &p);
 constexpr int kOrderMax = 1024;   // largest pass the ordering kernel sorts
@@ -225,6 +232,7 @@ struct KmeansPass {
     uint32_t *bh;             // [2ns][nb][sk]  block histograms, then block offsets
     uint32_t *cbase;          // [2ns][sk+1]    cluster starts
     uint32_t *order;          // [2ns][n]       point ids grouped by cluster, ascending
+    int metric;               // 0: k-means (squared L2, means); 1: k-medians (L1, lower medians)
 };
 hipError_t launch_gather_rows(const float *X, int d, const int64_t *ids, int m, int dim0, int w,
                               float *out, hipStream_t s);
@@ -232,6 +240,7 @@ hipError_t launch_km_assign(const KmeansPass &k, bool with_hist, hipStream_t s);
 hipError_t launch_km_scan(const KmeansPass &k, hipStream_t s);
 hipError_t launch_km_scatter(const KmeansPass &k, hipStream_t s);
 hipError_t launch_km_update(const KmeansPass &k, hipStream_t s);
+hipError_t launch_km_median(const KmeansPass &k, hipStream_t s);
 hipError_t launch_cent_to_f32(const double *c64, float *c32, int64_t m, hipStream_t s);
 hipError_t launch_imi_build(const uint8_t *assign, int64_t n, int ns, int sk, int P, int TILE,
                             uint32_t *toffs, uint16_t *ids16, uint32_t *csize, hipStream_t s);

@@ -8,6 +8,12 @@
 
 namespace suco {
 
+// One term of a distance sum in FP32: t*t (squared Euclidean, one FMA) or |t|
+// (Manhattan, SuCo-L1).
+__device__ __forceinline__ float dist_acc(float s, float t, int metric) {
+    return metric ? s + fabsf(t) : fmaf(t, t, s);
+}
+
 // Inclusive prefix sum over the 64 lanes with DPP moves (row shifts within
 // 16-lane rows, then the row broadcasts of lanes 15 and 31); lanes a move
 // does not reach add zero.
