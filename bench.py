@@ -996,10 +996,20 @@ def main():
         m_tr = args.train_queries
         grid = learned.alpha_grid(0.0005, 0.05)
         net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
-        # the predicted alpha is clamped to [0.0005, 0.01]: above 0.01 recall barely moves (sweep) while a
-        # few very large alphas make a batch's slowest blocks much slower
-        amin, amax = grid[0], 0.01
-        scale = learned.calibrate_scale(ix, net, Qt[m_tr:], gt_t[m_tr:], k, beta, args.target_recall, amin, amax)
+        # the predicted alpha is clamped to [0.0005, amax]; amax is chosen on the held-out queries (not the
+        # evaluation ones) as the fastest of a few clamps once the scale is calibrated for each: a query
+        # whose activated points outgrow one CU's LDS leaves the sparse collision step for the slower
+        # tiled one, so a tighter clamp can pay more than the recall it costs
+        amin = grid[0]
+        Qv, gt_v = Qt[m_tr:], gt_t[m_tr:]
+        best_clamp = None
+        for amax_c in (0.0035, 0.005, 0.01):
+            sc = learned.calibrate_scale(ix, net, Qv, gt_v, k, beta, args.target_recall, amin, amax_c)
+            ms_c, _ = timed_steps(lambda: suco.query_learned(ix, net, Qv, k, beta, sc, amin, amax_c), 3, 1)
+            log(f"clamp {amax_c}: scale {sc:.3f}, {ms_c / 3:.3f} ms per {Qv.shape[0]} held-out queries")
+            if best_clamp is None or ms_c < best_clamp[0]:
+                best_clamp = (ms_c, amax_c, sc)
+        _, amax, scale = best_clamp
         train_s = time.time() - t0
         log(f"learned budget: trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, "
             f"scale {scale:.3f}")
@@ -1043,7 +1053,8 @@ def main():
         learned_info = {"plain_batched_stream_qps": round(nq * args.steps / (ms_pb / 1e3), 1),
                         "learned_one_call_qps": round(nq * args.steps / (ms_l1 / 1e3), 1),
                         "train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
-                        "scale": round(scale, 5), "mean_alpha": round(mean_alpha, 6), "train_s": round(train_s, 2),
+                        "scale": round(scale, 5), "alpha_clamp": [amin, amax], "mean_alpha": round(mean_alpha, 6),
+                        "train_s": round(train_s, 2),
                         "batch_sizes": sizes, "plain_qps_at_same_recall": None if plain_eq is None else round(plain_eq, 1),
                         "mre": learned_mre,
                         "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)]}

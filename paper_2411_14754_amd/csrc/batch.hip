@@ -216,11 +216,10 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         bk->ip.amin = b->amin;
         bk->ip.amax = b->amax;
         bk->ip.alpha64 = b->alphas;
-        const Launch Lf = plan_features(bk->size), Li = plan_mlp_infer(bk->size);
-        void *af[] = {&bk->fp};
-        void *ai[] = {&bk->ip};
-        if ((e = add_node(bk->graph, &prev, Lf.func, Lf.grid, Lf.block, Lf.lds, af)) != hipSuccess) return e;
-        if ((e = add_node(bk->graph, &prev, Li.func, Li.grid, Li.block, Li.lds, ai)) != hipSuccess) return e;
+        // features and inference in one node
+        const Launch La = plan_learned_alpha(bk->size);
+        void *aa[] = {&bk->fp, &bk->ip};
+        if ((e = add_node(bk->graph, &prev, La.func, La.grid, La.block, La.lds, aa)) != hipSuccess) return e;
     }
     const int passes = (bk->size + b->C - 1) / b->C;
     const int C = std::min(b->C, bk->size);

@@ -21,6 +21,8 @@
 // arithmetic as the sequential CPU loop that keeps a running group sum.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "suco_impl.h"
 #include "wave.h"
 
@@ -34,18 +36,32 @@ __global__ void k_gather_rows(const float *X, int d, const int64_t *ids, int m, 
     out[t] = X[ids[r] * d + dim0 + j];
 }
 
-// One point per thread.  WMAX > 0: the point's half is held in registers.
-template <int WMAX>
+// One point per thread, the halves listed in k.hsel (grid.y), all of width W
+// (W = 0: any width, read from the half).  With a fixed width the point's half
+// is loaded at once into registers and the centres, the same for the whole
+// block, are read through the scalar cache (uniform loads the compiler keeps in
+// SGPRs, operands of the FP64 arithmetic as they are): three FP64 operations
+// per dimension and centre (squared L2) or two (L1), no branches, no LDS.
+template <int W, int METRIC>
+__device__ __forceinline__ double half_dist64(const double *x, const double *__restrict__ c) {
+#pragma clang fp contract(off)
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const double dd = x[j] - c[j];
+        s = s + (METRIC ? fabs(dd) : dd * dd);
+    }
+    return s;
+}
+
+template <int W, int METRIC>
 __global__ __launch_bounds__(256) void k_km_assign(KmeansPass k, int with_hist) {
 #pragma clang fp contract(off)
-    extern __shared__ double cs[];            // [sk][w] centres of this half (WMAX > 0)
     __shared__ uint32_t hcnt[kMaxSqrtK];
-    const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+    const int g = k.hsel[blockIdx.y], b = blockIdx.x, t = threadIdx.x;
     const HalfDims hd = k.halves[g];
     const int w = hd.w, sk = k.sk;
-    const double *cg = k.cent64 + (int64_t)sk * hd.dim0;
-    if constexpr (WMAX > 0)
-        for (int e = t; e < sk * w; e += 256) cs[e] = cg[e];
+    const double *__restrict__ cg = k.cent64 + (int64_t)sk * hd.dim0;
     if (with_hist)
         for (int c = t; c < sk; c += 256) hcnt[c] = 0u;
     __syncthreads();
@@ -54,27 +70,21 @@ __global__ __launch_bounds__(256) void k_km_assign(KmeansPass k, int with_hist) 
         const float *xp = k.X + p * k.d + hd.dim0;
         int best = 0;
         double bd = 0.0;
-        if constexpr (WMAX > 0) {
-            double x[WMAX];
+        if constexpr (W > 0) {
+            double x[W];
 #pragma unroll
-            for (int j = 0; j < WMAX; ++j) x[j] = j < w ? (double)xp[j] : 0.0;
-            for (int c = 0; c < sk; ++c) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < WMAX; ++j) {
-                    if (j < w) {
-                        const double dd = x[j] - cs[c * w + j];
-                        s = s + (k.metric ? fabs(dd) : dd * dd);
-                    }
-                }
-                if (c == 0 || s < bd) { bd = s; best = c; }
+            for (int j = 0; j < W; ++j) x[j] = (double)xp[j];
+            bd = half_dist64<W, METRIC>(x, cg);
+            for (int c = 1; c < sk; ++c) {
+                const double s = half_dist64<W, METRIC>(x, cg + c * W);
+                if (s < bd) { bd = s; best = c; }        // ties keep the lower centre id
             }
         } else {
             for (int c = 0; c < sk; ++c) {
                 double s = 0.0;
                 for (int j = 0; j < w; ++j) {
                     const double dd = (double)xp[j] - cg[c * w + j];
-                    s = s + (k.metric ? fabs(dd) : dd * dd);
+                    s = s + (METRIC ? fabs(dd) : dd * dd);
                 }
                 if (c == 0 || s < bd) { bd = s; best = c; }
             }
@@ -179,9 +189,14 @@ __global__ __launch_bounds__(256) void k_km_update(KmeansPass k) {
 #pragma unroll 4
                 for (uint32_t r = r0; r < r1; ++r) {
                     const float *xr = k.X + (int64_t)ord[r] * k.d + hd.dim0 + j0;
+                    // eight loads issued together (indices past the half repeat its last
+                    // dimension, so no load is conditional), then the additions
+                    float v[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) v[j] = xr[j < nj ? j : nj - 1];
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
-                        if (j < nj) acc[j] = acc[j] + (double)xr[j];
+                        if (j < nj) acc[j] = acc[j] + (double)v[j];
                 }
             }
 #pragma unroll
@@ -238,9 +253,13 @@ __global__ __launch_bounds__(256) void k_km_median(KmeansPass k) {
             const uint32_t hmask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
             for (uint32_t r = t; r < m; r += 256) {
                 const float *xr = k.X + (int64_t)ord[r] * k.d + hd.dim0 + j0;
-                for (int j = 0; j < nj; ++j) {
-                    const uint32_t key = float_key(xr[j]);
-                    if ((key & hmask) == (pre[j] & hmask)) atomicAdd(&hist[j][(key >> shift) & 255u], 1u);
+                float v[kMedDims];
+#pragma unroll
+                for (int j = 0; j < kMedDims; ++j) v[j] = xr[j < nj ? j : nj - 1];    // unconditional loads
+#pragma unroll
+                for (int j = 0; j < kMedDims; ++j) {
+                    const uint32_t key = float_key(v[j]);
+                    if (j < nj && (key & hmask) == (pre[j] & hmask)) atomicAdd(&hist[j][(key >> shift) & 255u], 1u);
                 }
             }
             __syncthreads();
@@ -363,15 +382,39 @@ hipError_t launch_gather_rows(const float *X, int d, const int64_t *ids, int m, 
     return hipGetLastError();
 }
 
-hipError_t launch_km_assign(const KmeansPass &k, bool with_hist, hipStream_t s) {
-    const dim3 grid((unsigned)k.nb, (unsigned)(2 * k.ns));
-    if (k.wmax <= 8)
-        hipLaunchKernelGGL(k_km_assign<8>, grid, dim3(256), sizeof(double) * k.sk * 8, s, k, (int)with_hist);
-    else if (k.wmax <= 32)
-        hipLaunchKernelGGL(k_km_assign<32>, grid, dim3(256), sizeof(double) * k.sk * 32, s, k, (int)with_hist);
-    else
-        hipLaunchKernelGGL(k_km_assign<0>, grid, dim3(256), 0, s, k, (int)with_hist);
+template <int METRIC>
+hipError_t launch_assign_width(const KmeansPass &k, int w, int nsel, bool with_hist, hipStream_t s) {
+    const dim3 grid((unsigned)k.nb, (unsigned)nsel);
+    const int h = (int)with_hist;
+    switch (w) {
+    case 4: hipLaunchKernelGGL((k_km_assign<4, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 6: hipLaunchKernelGGL((k_km_assign<6, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 8: hipLaunchKernelGGL((k_km_assign<8, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 12: hipLaunchKernelGGL((k_km_assign<12, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 16: hipLaunchKernelGGL((k_km_assign<16, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 24: hipLaunchKernelGGL((k_km_assign<24, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    case 32: hipLaunchKernelGGL((k_km_assign<32, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    default: hipLaunchKernelGGL((k_km_assign<0, METRIC>), grid, dim3(256), 0, s, k, h); break;
+    }
     return hipGetLastError();
+}
+
+// One launch per distinct half width (the halves of that width in hsel).
+hipError_t launch_km_assign(const KmeansPass &k0, const HalfDims *halves_h, bool with_hist, hipStream_t s) {
+    const int nh = 2 * k0.ns;
+    std::vector<bool> done(nh, false);
+    for (int g0 = 0; g0 < nh; ++g0) {
+        if (done[g0]) continue;
+        KmeansPass k = k0;
+        const int w = halves_h[g0].w;
+        int nsel = 0;
+        for (int g = g0; g < nh; ++g)
+            if (!done[g] && halves_h[g].w == w) { k.hsel[nsel++] = (int16_t)g; done[g] = true; }
+        const hipError_t e = k.metric ? launch_assign_width<1>(k, w, nsel, with_hist, s)
+                                      : launch_assign_width<0>(k, w, nsel, with_hist, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_km_scan(const KmeansPass &k, hipStream_t s) {

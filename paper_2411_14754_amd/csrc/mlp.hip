@@ -42,90 +42,144 @@ __device__ __forceinline__ float bf16r(float x) {
 }
 
 // ------------------------------------------------------------- features --
+// The 2*n_s + 1 features of one query into out[] (global or LDS), by the
+// whole block: one (half, centre) pair per thread at a time, with the
+// activation step's arithmetic (FMA over the half's dimensions in order,
+// values loaded eight at a time), each half's minimum by an LDS atomic on the
+// bit patterns, then the query norm (lane-strided partial sums, a fixed
+// reduction order).  Ends with a barrier.
+__device__ __forceinline__ void query_features(const IndexView &ix, const float *qv, float *out, uint32_t *mins,
+                                               float *part) {
+    const int sk = ix.sk, nh = 2 * ix.ns;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    for (int g = tid; g < nh; g += blockDim.x) mins[g] = 0x7f800000u;
+    __syncthreads();
+    for (int t = tid; t < nh * sk; t += blockDim.x) {
+        const int g = t / sk, c = t - g * sk;
+        const HalfDims hd = ix.halves[g];
+        const float *qp = qv + hd.dim0;
+        const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
+        float s = 0.f;
+        for (int j0 = 0; j0 < hd.w; j0 += 8) {
+            // sixteen loads issued together (indices past the half repeat its last
+            // dimension, so none is conditional), then the FMAs in dimension order
+            float a8[8], c8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int jj = j0 + u < hd.w ? j0 + u : hd.w - 1;
+                a8[u] = qp[jj];
+                c8[u] = cp[jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u < hd.w) {
+                    const float t2 = a8[u] - c8[u];
+                    s = fmaf(t2, t2, s);
+                }
+            }
+        }
+        atomicMin(&mins[g], __float_as_uint(s));
+    }
+    float nsq = 0.f;
+    for (int j = tid; j < ix.d; j += blockDim.x) nsq = fmaf(qv[j], qv[j], nsq);
+    for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, kWave);
+    if (lane == 0) part[tid / kWave] = nsq;
+    __syncthreads();
+    for (int g = tid; g < nh; g += blockDim.x) out[g] = __fsqrt_rn(__uint_as_float(mins[g]));
+    if (tid == 0) out[nh] = __fsqrt_rn(part[0] + part[1]);
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(128) void k_features(FeatPass fp) {
     __shared__ uint32_t mins[2 * kMaxNs];   // bits of each half's smallest distance (non-negative floats)
     __shared__ float part[128 / kWave];
-    const IndexView ix = fp.ix;
     const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
-    const int sk = ix.sk, nh = 2 * ix.ns;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-        const float *qv = fp.Q + (int64_t)q * ix.d;
-        for (int g = tid; g < nh; g += blockDim.x) mins[g] = 0x7f800000u;
-        __syncthreads();
-        // one (half, centre) pair per thread at a time, with the activation
-        // step's arithmetic: FMA over the half's dimensions in order, values
-        // loaded eight at a time
-        for (int t = tid; t < nh * sk; t += blockDim.x) {
-            const int g = t / sk, c = t - g * sk;
-            const HalfDims hd = ix.halves[g];
-            const float *qp = qv + hd.dim0;
-            const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
-            float s = 0.f;
-            for (int j0 = 0; j0 < hd.w; j0 += 8) {
-                float a8[8], c8[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const bool in = j0 + u < hd.w;
-                    a8[u] = in ? qp[j0 + u] : 0.f;
-                    c8[u] = in ? cp[j0 + u] : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (j0 + u < hd.w) {
-                        const float t2 = a8[u] - c8[u];
-                        s = fmaf(t2, t2, s);
-                    }
-                }
-            }
-            atomicMin(&mins[g], __float_as_uint(s));
-        }
-        // query norm: lane-strided partial sums, then a fixed reduction order
-        float nsq = 0.f;
-        for (int j = tid; j < ix.d; j += blockDim.x) nsq = fmaf(qv[j], qv[j], nsq);
-        for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, kWave);
-        if (lane == 0) part[tid / kWave] = nsq;
-        __syncthreads();
-        float *out = fp.F + (int64_t)q * (nh + 1);
-        for (int g = tid; g < nh; g += blockDim.x) out[g] = __fsqrt_rn(__uint_as_float(mins[g]));
-        if (tid == 0) out[nh] = __fsqrt_rn(part[0] + part[1]);
-        __syncthreads();
-    }
+    const int nf = 2 * fp.ix.ns + 1;
+    for (int q = blockIdx.x; q < nq; q += gridDim.x)
+        query_features(fp.ix, fp.Q + (int64_t)q * fp.ix.d, fp.F + (int64_t)q * nf, mins, part);
 }
 
 // ---------------------------------------------------------- inference --
-// Block of H threads per row; weights are pre-rounded BF16 values in FP32.
+// Blocks of H threads, persistent over rows; weights are pre-rounded BF16
+// values in FP32.  Thread j keeps row j of the second layer's weights in
+// registers for all its rows (read once per block), so the per-row work reads
+// only the previous layer's outputs, broadcast from LDS.
+struct InferRegs {
+    float w2[kH];
+    float b1, b2, w3;
+};
+
+__device__ __forceinline__ void infer_regs(const MlpView &w, InferRegs &R) {
+    const int j = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kH; ++i) R.w2[i] = w.W2[j * kH + i];
+    R.b1 = w.b1[j];
+    R.b2 = w.b2[j];
+    R.w3 = w.W3[j];
+}
+
+// Row r of the network from its raw features fr[] (any memory): standardised
+// and rounded into x, two hidden layers, the output and its alpha.  Ends with
+// a barrier.
+__device__ __forceinline__ void infer_row(const InferPass &ip, const InferRegs &R, const float *fr, const int r,
+                                          float *x, float *h, float *red) {
+    const MlpView &w = ip.w;
+    const int j = threadIdx.x;
+    for (int i = j; i < w.n_in; i += kH) x[i] = bf16r((fr[i] - w.mu[i]) / w.sigma[i]);
+    __syncthreads();
+    float z = R.b1;
+    for (int i = 0; i < w.n_in; ++i) z = fmaf(w.W1[j * w.n_in + i], x[i], z);
+    h[j] = bf16r(gelu_f(z));
+    __syncthreads();
+    float z2 = R.b2;
+#pragma unroll
+    for (int i = 0; i < kH; ++i) z2 = fmaf(R.w2[i], h[i], z2);
+    const float h2 = bf16r(gelu_f(z2));
+    float part = R.w3 * h2;
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    if ((j & (kWave - 1)) == 0) red[j / kWave] = part;
+    __syncthreads();
+    if (j == 0) {
+        const float yv = w.b3[0] + red[0] + red[1];
+        if (ip.y) ip.y[r] = yv;
+        float a = ip.scale * expf(yv);
+        // a NaN prediction takes the largest budget, like +inf
+        a = a <= ip.amax ? (a >= ip.amin ? a : ip.amin) : ip.amax;
+        if (ip.alpha) ip.alpha[r] = a;
+        if (ip.alpha64) ip.alpha64[r] = (double)a;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kH) void k_mlp_infer(InferPass ip) {
     __shared__ float x[kMaxIn + 1];
     __shared__ float h[kH];
     __shared__ float red[kH / kWave];
-    const MlpView w = ip.w;
-    const int j = threadIdx.x;
     const int m = ip.m_dev ? *ip.m_dev : ip.m;
-    for (int r = blockIdx.x; r < m; r += gridDim.x) {
-        for (int i = j; i < w.n_in; i += kH) x[i] = bf16r((ip.F[(int64_t)r * w.n_in + i] - w.mu[i]) / w.sigma[i]);
-        __syncthreads();
-        float z = w.b1[j];
-        for (int i = 0; i < w.n_in; ++i) z = fmaf(w.W1[j * w.n_in + i], x[i], z);
-        h[j] = bf16r(gelu_f(z));
-        __syncthreads();
-        float z2 = w.b2[j];
-        for (int i = 0; i < kH; ++i) z2 = fmaf(w.W2[j * kH + i], h[i], z2);
-        const float h2 = bf16r(gelu_f(z2));
-        float part = w.W3[j] * h2;
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-        if ((j & (kWave - 1)) == 0) red[j / kWave] = part;
-        __syncthreads();
-        if (j == 0) {
-            const float yv = w.b3[0] + red[0] + red[1];
-            if (ip.y) ip.y[r] = yv;
-            float a = ip.scale * expf(yv);
-            // a NaN prediction takes the largest budget, like +inf
-            a = a <= ip.amax ? (a >= ip.amin ? a : ip.amin) : ip.amax;
-            if (ip.alpha) ip.alpha[r] = a;
-            if (ip.alpha64) ip.alpha64[r] = (double)a;
-        }
-        __syncthreads();
+    if ((int)blockIdx.x >= m) return;
+    InferRegs R;
+    infer_regs(ip.w, R);
+    for (int r = blockIdx.x; r < m; r += gridDim.x) infer_row(ip, R, ip.F + (int64_t)r * ip.w.n_in, r, x, h, red);
+}
+
+// The query path's alphas in one kernel: each query's features go straight
+// from the feature computation (LDS) into the network, the same values and
+// arithmetic as k_features followed by k_mlp_infer.
+__global__ __launch_bounds__(kH) void k_learned_alpha(FeatPass fp, InferPass ip) {
+    static_assert(kH == 128, "the feature computation is written for blocks of 128 threads");
+    __shared__ uint32_t mins[2 * kMaxNs];
+    __shared__ float part[kH / kWave];
+    __shared__ float fq[2 * kMaxNs + 1];
+    __shared__ float x[kMaxIn + 1];
+    __shared__ float h[kH];
+    __shared__ float red[kH / kWave];
+    const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
+    if ((int)blockIdx.x >= nq) return;
+    InferRegs R;
+    infer_regs(ip.w, R);
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        query_features(fp.ix, fp.Q + (int64_t)q * fp.ix.d, fq, mins, part);
+        infer_row(ip, R, fq, q, x, h, red);
     }
 }
 
@@ -343,10 +397,18 @@ Launch plan_features(int nq_cap) {
     return L;
 }
 
+Launch plan_learned_alpha(int nq_cap) {
+    Launch L;
+    L.func = reinterpret_cast<const void *>(&k_learned_alpha);
+    L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 2048)));
+    L.block = dim3(kH);
+    return L;
+}
+
 Launch plan_mlp_infer(int m_cap) {
     Launch L;
     L.func = reinterpret_cast<const void *>(&k_mlp_infer);
-    L.grid = dim3((unsigned)std::max(1, std::min(m_cap, 65536)));
+    L.grid = dim3((unsigned)std::max(1, std::min(m_cap, 2048)));
     L.block = dim3(kH);
     return L;
 }
@@ -581,11 +643,24 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
         S.cap_a = nq;
     }
     if (S.pending) HIPCHECK(hipStreamWaitEvent(st, S.done, 0));
-    int rc = suco_query_features(ix, Q, nq, S.F, stream);
-    if (rc) return rc;
-    rc = suco_mlp_predict(p, S.F, nq, scale, alpha_min, alpha_max, nullptr, S.alpha, stream);
-    if (rc) return rc;
-    rc = suco_query_alpha(ix, Q, nq, k, S.alpha, beta, ids, dists, stream);
+    {
+        std::lock_guard<std::mutex> mlock(p->mu_lock);
+        int rc = refresh_bf16(p, st);
+        if (rc) return rc;
+        // features and inference in one kernel per 65,536 queries
+        for (int64_t q0 = 0; q0 < nq; q0 += 65536) {
+            const int cn = (int)std::min<int64_t>(65536, nq - q0);
+            FeatPass fp{};
+            fp.ix = ix->view(); fp.Q = Q + q0 * ix->d; fp.nq = cn;
+            InferPass ip{};
+            ip.w = p->view(p->wb); ip.m = cn; ip.scale = scale; ip.amin = alpha_min; ip.amax = alpha_max;
+            ip.alpha = S.alpha + q0;
+            const Launch L = plan_learned_alpha(cn);
+            void *args[] = {&fp, &ip};
+            HIPCHECK(hipLaunchKernel(L.func, L.grid, L.block, args, L.lds, st));
+        }
+    }
+    int rc = suco_query_alpha(ix, Q, nq, k, S.alpha, beta, ids, dists, stream);
     if (rc) return rc;
     if (alpha_used) HIPCHECK(hipMemcpyAsync(alpha_used, S.alpha, sizeof(float) * nq, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipEventRecord(S.done, st));

@@ -263,9 +263,9 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
             float qv[8], cv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const bool in = j0 + u < hd.w;
-                qv[u] = in ? qp[j0 + u] : 0.f;
-                cv[u] = in ? cp[j0 + u] : 0.f;
+                const int jj = j0 + u < hd.w ? j0 + u : hd.w - 1;   // unconditional loads
+                qv[u] = qp[jj];
+                cv[u] = cp[jj];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -305,9 +305,10 @@ __device__ __forceinline__ void activate_item(const QueryPass &a, const int item
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        const bool in = j0 + u < w[h];
-                        qv[h][u] = in ? qp[h][j0 + u] : 0.f;
-                        cv[h][u] = in ? cp[h][j0 + u] : 0.f;
+                        // unconditional loads: indices past the half repeat its last dimension
+                        const int jj = j0 + u < w[h] ? j0 + u : w[h] - 1;
+                        qv[h][u] = qp[h][jj];
+                        cv[h][u] = cp[h][jj];
                     }
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
@@ -1072,14 +1073,19 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
             const uint32_t j = j0 + (uint32_t)(q * kWave + lane);
             u[q] = one ? u0[q] : seg[j < len ? j : 0u];
         }
+        // all UQ claims are issued before any result is used (the slots past the
+        // bucket's end claim a lane's sink word with a mask that changes nothing)
+        uint32_t old[UQ];
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
-            sv[q] = 0u;
-            if (j0 + (uint32_t)(q * kWave) >= len) continue;          // the same in every lane
             const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
             const uint32_t sh = (u[q] & 7u) << 2;
-            const uint32_t old = atomicAnd(v ? &win[u[q] >> 3] : &sink[lane], v ? ~(15u << sh) : ~0u);
-            sv[q] = v ? (old >> sh) & 15u : 0u;
+            old[q] = atomicAnd(v ? &win[u[q] >> 3] : &sink[lane], v ? ~(15u << sh) : ~0u);
+        }
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
+            sv[q] = v ? (old[q] >> ((u[q] & 7u) << 2)) & 15u : 0u;
         }
         uint64_t mh[UQ];
         uint32_t nh = 0;
@@ -1569,7 +1575,8 @@ __device__ __forceinline__ void select_tile(const QueryPass &a, const int ql, co
 }
 
 template <int NT>
-__device__ __forceinline__ void select_item(const QueryPass &a, const int ql, uint32_t *bm, uint32_t *sum) {
+__device__ __forceinline__ void select_item(const QueryPass &a, const int ql, const int g, const int S, uint32_t *bm,
+                                            uint32_t *sum) {
     __shared__ uint32_t Gt[kMaxNs + 2];
     __shared__ uint32_t red[NT / kWave + 1];
     const int P = a.ix.P, ns = a.ix.ns, TILE = a.ix.TILE, H = ns + 2;
@@ -1618,7 +1625,9 @@ __device__ __forceinline__ void select_item(const QueryPass &a, const int ql, ui
             eq_carry += totE;
             __syncthreads();
         }
-        for (int pi = wv; pi < np; pi += NT / kWave) {
+        // this block's tiles: p = g, g + S, ... (S tile groups per query)
+        const int first = ((g - p0) % S + S) % S;
+        for (int pi = first + wv * S; pi < np; pi += S * (NT / kWave)) {
             const SelectTile t{p0 + pi, pl_gt[pi], pl_E[pi], pl_take[pi], pl_base[pi]};
             if (t.gt + t.take == 0u) continue;
             select_tile(a, ql, T, t, bmw, smw, out);
@@ -1631,13 +1640,20 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_select(QueryPass a) {
     extern __shared__ uint32_t bm[];       // per wave: a bitmap of TILE bits
     __shared__ uint32_t sum[(NT / kWave) * 64];    // per wave: its summary (bit w of word s = bitmap word 32s + w non-zero)
-    const int items = a.tlist != nullptr ? *a.ntl : pass_nq(a.nq_dev, a.q_base, a.nq);
+    // the queries the sparse step left are few: each is spread over S groups
+    // of its tiles (one tile per wave at the most), each block planning all
+    // tiles from the histograms and selecting in its own
+    const int nt = a.tlist != nullptr ? *a.ntl : pass_nq(a.nq_dev, a.q_base, a.nq);
+    const int smax = (a.ix.P + NT / kWave - 1) / (NT / kWave);
+    const int S = a.tlist != nullptr && nt > 0 ? min(smax, max(1, (4096 + nt - 1) / nt)) : 1;
+    const int items = nt * S;
     if ((int)blockIdx.x >= items) return;
     for (int w = threadIdx.x; w < (NT / kWave) * (a.ix.TILE >> 5); w += NT) bm[w] = 0u;
     for (int w = threadIdx.x; w < (NT / kWave) * 64; w += NT) sum[w] = 0u;
     __syncthreads();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        select_item<NT>(a, a.tlist != nullptr ? a.tlist[item] : item, bm, sum);
+        const int rq = item / S, g = item - rq * S;
+        select_item<NT>(a, a.tlist != nullptr ? a.tlist[rq] : rq, g, S, bm, sum);
         __syncthreads();
     }
 }

@@ -222,7 +222,7 @@ int run_kmeans(suco_index *ix, int iters, uint64_t seed, hipStream_t st) {
     kp.cent64 = cent64; kp.bh = bh; kp.cbase = cbase; kp.order = order;
     hipError_t e = hipMemcpyAsync(cent64, c64.data(), sizeof(double) * sk * d, hipMemcpyHostToDevice, st);
     for (int it = 0; it <= iters && e == hipSuccess; ++it) {
-        e = launch_km_assign(kp, it < iters, st);
+        e = launch_km_assign(kp, ix->halves_h.data(), it < iters, st);
         if (it == iters || e != hipSuccess) break;
         if ((e = launch_km_scan(kp, st)) != hipSuccess) break;
         if ((e = launch_km_scatter(kp, st)) != hipSuccess) break;

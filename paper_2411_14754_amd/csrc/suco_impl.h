@@ -179,6 +179,7 @@ struct InferPass {
 };
 Launch plan_features(int nq_cap);
 Launch plan_mlp_infer(int m_cap);
+Launch plan_learned_alpha(int nq_cap);   // features and inference fused (args: FeatPass, InferPass)
 
 // BF16 split precision (bf16.hip).
 struct CentreBf16Pass {
@@ -233,10 +234,11 @@ struct KmeansPass {
     uint32_t *cbase;          // [2ns][sk+1]    cluster starts
     uint32_t *order;          // [2ns][n]       point ids grouped by cluster, ascending
     int metric;               // 0: k-means (squared L2, means); 1: k-medians (L1, lower medians)
+    int16_t hsel[2 * kMaxNs]; // assignment launches: the halves of one width, grid.y indexes them
 };
 hipError_t launch_gather_rows(const float *X, int d, const int64_t *ids, int m, int dim0, int w,
                               float *out, hipStream_t s);
-hipError_t launch_km_assign(const KmeansPass &k, bool with_hist, hipStream_t s);
+hipError_t launch_km_assign(const KmeansPass &k, const HalfDims *halves_h, bool with_hist, hipStream_t s);
 hipError_t launch_km_scan(const KmeansPass &k, hipStream_t s);
 hipError_t launch_km_scatter(const KmeansPass &k, hipStream_t s);
 hipError_t launch_km_update(const KmeansPass &k, hipStream_t s);

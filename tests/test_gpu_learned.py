@@ -221,3 +221,44 @@ def test_trained_budget_gain_sift_like(suco):
     assert r_learned >= 0.94
     assert fixed is not None and mean_alpha < fixed
     ix.free()
+
+
+def test_trained_budget_lifted_reduced(suco):
+    """The lifted generator (d = 256, N_s = 16, sqrtK = 64) at n = 1,000,000:
+    a network trained on plain-method labels and calibrated on held-out
+    queries reaches recall@10 >= 0.94 on other queries with per-query alphas
+    that vary, and its query equals the per-query-alpha path on those alphas.
+    At this size it does not beat a fixed alpha (mean alpha ~0.00105 against
+    ~0.00087 for the same recall, printed), so no gain is asserted."""
+    from paper_2411_14754_amd import learned
+    W = synth.Workload(5)
+    X = torch.from_numpy(W.data(1_000_000)).cuda()
+    print("case: learned lifted n=1e6: build", flush=True)
+    ix = suco.Index.build(X, 16, 64, iters=6)
+    import bench
+    Qt = torch.from_numpy(W.train_queries(24_000)).cuda()
+    Qe = torch.from_numpy(W.queries(4_000)).cuda()
+    gt_t = bench.exact_topk_float(X, Qt, 10)
+    gt_e = bench.exact_topk_float(X, Qe, 10)
+    grid = learned.alpha_grid(0.00005, 0.02, 1.4)
+    print("case: learned lifted: labels and training", flush=True)
+    net, info = learned.train_budget_model(ix, Qt[:20_000], gt_t[:20_000], 10, 0.003, grid, epochs=25)
+    assert info["loss"][-1] < info["loss"][0]
+    scale = learned.calibrate_scale(ix, net, Qt[20_000:], gt_t[20_000:], 10, 0.003, 0.95, grid[0], grid[-1])
+    ids, dists, au = suco.query_learned(ix, net, Qe, 10, 0.003, scale, grid[0], grid[-1])
+    r_learned = float(learned.per_query_recall(ids, gt_e).mean())
+    mean_alpha = float(au.double().mean())
+    p_ids, p_d = ix.query_alpha(Qe, 10, au, 0.003)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, p_ids) and torch.equal(dists, p_d)
+    fixed = None
+    for a in learned.alpha_grid(grid[0], grid[-1], 1.1):
+        pi, _ = ix.query(Qe, 10, a, 0.003)
+        if float(learned.per_query_recall(pi, gt_e).mean()) >= r_learned:
+            fixed = a
+            break
+    print(f"learned (lifted n=1e6): recall {r_learned:.4f} mean alpha {mean_alpha:.6f}; fixed alpha for that "
+          f"recall {fixed}", flush=True)
+    assert r_learned >= 0.94
+    assert float(au.double().std()) > 0.1 * mean_alpha
+    ix.free()
