@@ -443,10 +443,12 @@ def bench_batched_deep(args, log):
 
     W = synth.Workload(4)
     sp = W.spec
+    if args.nq:                      # a shorter stream (profiling runs that count every dispatch)
+        sp["nq"] = args.nq
     n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
     alpha = args.alpha if args.alpha is not None else sp["alpha"]
     log("generating data")
-    X, Q = W.data(), W.queries()
+    X, Q = W.data(), W.queries(nq)
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
@@ -464,7 +466,7 @@ def bench_batched_deep(args, log):
     ms_plain = timed_region(plain, args.steps, 1)
     plain_ids, plain_d = ids.clone(), dists.clone()
     rec_plain = recall_at(ids[:n_gt], gt)
-    log(f"plain: {ms_plain / args.steps:.2f} ms per 100,000 queries, recall@10={rec_plain:.4f}")
+    log(f"plain: {ms_plain / args.steps:.2f} ms per {nq:,} queries, recall@10={rec_plain:.4f}")
     if args.plain_only:
         bench_deep_plain(args, log, ix, suco, Qd, X, Q, sp, alpha, ms_plain, rec_plain, plain, build_s)
         return
@@ -497,14 +499,15 @@ def bench_batched_deep(args, log):
     sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
     stage, per_kernel = stage_profile(ix, plain, 1, sb, nq)
     dom = max(sb, key=lambda t: stage[t][0])
-    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    kern_name = {"collide_sparse": "k_collide_sparse", "collide": "k_collide", "select": "k_select",
+                 "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "deep_like")}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "100,000 queries")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, f"{nq:,} queries")
     line = {
         "metric": "QPS of a stream of uneven batches, Deep-like n=10M d=96: batched persistent SuCo on 1 GPU",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -529,16 +532,17 @@ def bench_deep_plain(args, log, ix, suco, Qd, X, Q, sp, alpha, ms_plain, rec_pla
     sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
     stage, per_kernel = stage_profile(ix, plain, 1, sb, nq)
     dom = max(sb, key=lambda t: stage[t][0])
-    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    kern_name = {"collide_sparse": "k_collide_sparse", "collide": "k_collide", "select": "k_select",
+                 "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "deep_like")}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, "100,000 queries")
+        cpu = oracle_baseline(X, Q, ns, sk, alpha, beta, k, 256, f"{nq:,} queries")
     line = {
-        "metric": "QPS of 100,000 queries in one call, Deep-like n=10M d=96: plain SuCo on 1 GPU",
+        "metric": f"QPS of {nq:,} queries in one call, Deep-like n=10M d=96: plain SuCo on 1 GPU",
         "value": round(nq * args.steps / (ms_plain / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": round(ms_plain / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -626,7 +630,8 @@ def bench_learned_lifted(args, log):
     sb = step_bytes_for(ix, suco, Qd[:64], k, alpha, beta, n, d)
     stage, per_kernel = stage_profile(ix, lambda: ix.query(Qd, k, alpha, beta, out=(ids, dists)), 1, sb, nq)
     dom = max(sb, key=lambda t: stage[t][0])
-    kern_name = {"collide": "k_collide", "select": "k_select", "rerank": "k_rerank"}[dom]
+    kern_name = {"collide_sparse": "k_collide_sparse", "collide": "k_collide", "select": "k_select",
+                 "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kern_name, "lifted256")}
@@ -653,6 +658,93 @@ def bench_learned_lifted(args, log):
     print(json.dumps(line))
     net.free()
     ix.free()
+
+
+def bench_sift_k50(args, log):
+    """The SIFT-like workload at k = 50 (its second k): the plain path over the
+    alpha grid, recall@50 against the exact top-50, and the QPS at the
+    smallest grid alpha reaching recall@50 >= 0.95 (10,000 queries a call)."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+    W = synth.Workload(2)
+    sp = W.spec
+    n, d, ns, sk, nq, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["beta"]
+    k = 50
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    gt = exact_topk(Xd, Qd, k)
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    sweep = []
+    for a in ALPHA_GRID:
+        ms_a, _ = timed_steps(lambda: ix.query(Qd, k, a, beta, out=(ids, dists)), 1, 1)
+        r = recall_at(ids, gt)
+        sweep.append({"alpha": a, "recall": round(r, 5), "qps": round(nq / (ms_a / 1e3), 1)})
+        log(f"k=50 alpha={a}: recall@50={r:.4f} qps={nq / (ms_a / 1e3):.0f}")
+    ok = [e for e in sweep if e["recall"] >= TARGET_RECALL]
+    alpha = ok[0]["alpha"] if ok else sweep[-1]["alpha"]
+    ms, per = timed_steps(lambda: ix.query(Qd, k, alpha, beta, out=(ids, dists)), args.steps, args.warmup)
+    rec = recall_at(ids, gt)
+    value = nq * args.steps / (ms / 1e3)
+    log(f"k=50 timed at alpha={alpha}: {ms / args.steps:.3f} ms/step, {value:.0f} QPS, recall@50={rec:.4f}")
+    print(json.dumps({"metric": "QPS at recall@50=0.95, n=1M d=128: plain SuCo on 1 GPU", "value": round(value, 1),
+                      "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"sift_like n={n} d={d} int 0..255, N_s={ns}, sqrtK={sk}, nq={nq}, "
+                                             f"k={k}, beta={beta}", "alpha": alpha, "recall_at_50": round(rec, 5),
+                                 "sweep": sweep}}))
+    ix.free()
+
+
+def bench_form(args, log):
+    """One form of the SIFT-like query path alone, for kernel traces of it:
+    `onecall` (10,000 queries in one plain call at alpha = 0.003), `batched`
+    (the same queries as five uneven batches through a batcher), `learned`
+    (the five batches through a batcher with the trained budget model, alpha
+    clamped to [0.0005, 0.0035]).  Prints the per-step time."""
+    import torch
+    import paper_2411_14754_amd as suco
+    import synth
+    W = synth.Workload(2)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    sizes = W.batch_sizes(nq)
+    alpha = 0.003
+    if args.form == "onecall":
+        def step():
+            ix.query(Qd, k, alpha, beta, out=(ids, dists))
+    else:
+        b = suco.Batcher(ix, 4096, k, beta)
+        if args.form == "learned":
+            from paper_2411_14754_amd import learned
+            Qt = torch.from_numpy(W.train_queries(30_000)).cuda()
+            gt_t = exact_topk(Xd, Qt, k)
+            grid = learned.alpha_grid(0.0005, 0.05)
+            net, _ = learned.train_budget_model(ix, Qt[:20_000], gt_t[:20_000], k, beta, grid, epochs=args.epochs)
+            scale = learned.calibrate_scale(ix, net, Qt[20_000:], gt_t[20_000:], k, beta, args.target_recall,
+                                            grid[0], 0.0035)
+            b.set_model(net, scale, grid[0], 0.0035)
+
+        def step():
+            s0 = 0
+            for sz in sizes:
+                if args.form == "learned":
+                    b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+                else:
+                    b.query(Qd[s0:s0 + sz], alpha=alpha, out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
+                s0 += sz
+    ms, per = timed_steps(step, args.steps, args.warmup)
+    log(f"{args.form}: {ms / args.steps:.3f} ms per step of {nq} queries")
+    print(json.dumps({"form": args.form, "ms_per_step": round(ms / args.steps, 4), "steps": args.steps,
+                      "batches": 1 if args.form == "onecall" else len(sizes)}))
 
 
 def bench_build(args, log):
@@ -798,11 +890,12 @@ def bench_sclinear(args, log):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("sift_like", "gist_like", "deep_like", "lifted256", "sclinear", "activation", "build"), default="sift_like",
+    ap.add_argument("--workload", choices=("sift_like", "sift_k50", "gist_like", "deep_like", "lifted256", "sclinear", "activation", "build"), default="sift_like",
                     help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split "
                          "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M; "
                          "sclinear: SuCo against SC-Linear on the SIFT-like data; activation: Dynamic Activation "
-                         "against Multi-sequence; build: index build time and memory")
+                         "against Multi-sequence; build: index build time and memory; sift_k50: the SIFT-like "
+                         "workload at k=50")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=10_000, help="most queries the CPU oracle is timed on")
@@ -819,6 +912,9 @@ def main():
     ap.add_argument("--lifted-train", type=int, default=200_000, help="training queries of the lifted256 mode")
     ap.add_argument("--target-recall", type=float, default=0.951)
     ap.add_argument("--build-all", action="store_true", help="build: also the 10M-point Deep-like and lifted indexes")
+    ap.add_argument("--nq", type=int, default=0, help="deep_like: queries in the stream (0: the workload's 100,000)")
+    ap.add_argument("--form", choices=("onecall", "batched", "learned"), default=None,
+                    help="sift_like: time one form of the query path alone (for kernel traces)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "
                          "scale HBM byte counters) and exit")
@@ -858,6 +954,13 @@ def main():
         return
     if args.workload == "build":
         bench_build(args, log)
+        return
+    if args.workload == "sift_k50":
+        bench_sift_k50(args, log)
+        return
+
+    if args.form:
+        bench_form(args, log)
         return
 
     import torch

@@ -435,6 +435,31 @@ hipError_t launch_km_update(const KmeansPass &k, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One block per (cell, subspace): how many of the cell's ids fall in each
+// bucket of kSpBucket consecutive ids (LDS counters, then u16 counts; a
+// bucket holds at most 4,096 ids), for the sparse collision step's exact
+// bucket sizes.
+__global__ __launch_bounds__(256) void k_cell_buckets(const uint32_t *coffs, const uint32_t *ids32, int64_t n,
+                                                      int K, int NB, uint16_t *cbh) {
+    extern __shared__ uint32_t cnt[];          // [NBp]
+    const int c = blockIdx.x, i = blockIdx.y, NBp = sp_nb_padded(NB);
+    for (int b = threadIdx.x; b < NBp; b += 256) cnt[b] = 0u;
+    __syncthreads();
+    const uint32_t *co = coffs + (int64_t)i * (K + 1);
+    const uint32_t *ids = ids32 + (int64_t)i * n;
+    for (uint32_t m = co[c] + threadIdx.x; m < co[c + 1]; m += 256) atomicAdd(&cnt[ids[m] >> kSpShift], 1u);
+    __syncthreads();
+    uint16_t *out = cbh + ((int64_t)i * K + c) * NBp;
+    for (int b = threadIdx.x; b < NBp; b += 256) out[b] = (uint16_t)cnt[b];
+}
+
+hipError_t launch_cell_buckets(const uint32_t *coffs, const uint32_t *ids32, int64_t n, int ns, int K, int NB,
+                               uint16_t *cbh, hipStream_t s) {
+    const size_t lds = sizeof(uint32_t) * (size_t)sp_nb_padded(NB);
+    hipLaunchKernelGGL(k_cell_buckets, dim3((unsigned)K, (unsigned)ns), dim3(256), lds, s, coffs, ids32, n, K, NB, cbh);
+    return hipGetLastError();
+}
+
 hipError_t launch_km_median(const KmeansPass &k, hipStream_t s) {
     hipLaunchKernelGGL(k_km_median, dim3((unsigned)k.sk, (unsigned)(2 * k.ns)), dim3(256), 0, s, k);
     return hipGetLastError();

@@ -947,8 +947,9 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 // id range, and everything after the id reads stays in LDS:
 //  1. the query's activated cells become runs of the cell-major id copy (one
 //     run per cell); one walk over all their ids as a single sequence (every
-//     thread an equal share) places the low 12 bits of each into cb slots of
-//     its bucket;
+//     thread an equal share) places the low 12 bits of each into its bucket's
+//     slots (buckets sized exactly beforehand from the index's count of each
+//     cell's ids per bucket);
 //  2. a wave takes a bucket: 4-bit scores are counted in the wave's 2 KB
 //     window (a 32-bit LDS atomic add of 1 << 4*(low & 7): an id occurs once
 //     per subspace and N_s <= 15, so no nibble carries), then every id claims
@@ -965,7 +966,7 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     finds its cut id by marking its level-T ids in a 4096-bit map and
 //     counting.  Candidates are appended in no particular order.
 // A query is left to the tiled steps (route 1) when N_s > 15, it has
-// kSpMaxRuns activated cells or more, a bucket receives more than cb ids, more
+// kSpMaxRuns activated cells or more, more activated ids than the slots, more
 // than kSpHCap points score 2 or more, or T = 0 (fewer than B points collide:
 // the score-0 points are the tiled selection's case); otherwise route 0, and
 // the tiled collision and selection kernels skip the query.
@@ -1169,13 +1170,14 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int NBp = sp_nb_padded(NB);
     uint2 *runs = reinterpret_cast<uint2 *>(sp_dyn);                      // [kSpMaxRuns] (start, first position)
-    uint32_t *bfill = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);     // [NB] ids per bucket
-    uint32_t *bx = bfill + NBp;                                            // [NB] points of score 1, then level-T points
+    uint32_t *rcell = reinterpret_cast<uint32_t *>(runs + kSpMaxRuns);     // [kSpMaxRuns] the run's cell (i*K + c)
+    uint32_t *bfill = rcell + kSpMaxRuns;                                  // [NB] the walk's cursor in each bucket
+    uint32_t *boff = bfill + NBp;                                          // [NB] first slot of each bucket
+    uint32_t *bx = boff + NBp;                                             // [NB] points of score 1, then level-T points
     uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
     uint32_t *hl = win_all + kSpWaves * kSpWords;                          // [kSpHCap] (id << 4 | score), score >= 2
-    uint16_t *raw = reinterpret_cast<uint16_t *>(hl + kSpHCap);            // [NB][cb] low ids, then score-1 points
+    uint16_t *raw = reinterpret_cast<uint16_t *>(hl + kSpHCap);            // slots: each bucket's low ids, then its score-1 points
     uint32_t *win = win_all + w * kSpWords;
-    const uint32_t cb = ((uint32_t)a.sp_cap / (uint32_t)NB) & ~1u;         // slots per bucket
     const int nq = pass_nq(a.nq_dev, a.q_base, a.nq);
     const int per = (NB + kSpThreads - 1) / kSpThreads;
     const int b0t = tid * per < NB ? tid * per : NB, b1t = b0t + per < NB ? b0t + per : NB;
@@ -1192,13 +1194,12 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
             if (lane == 0) {
                 S.nruns = (int)nr;
-                S.flag = (ns > kSpMaxNs || nr >= (uint32_t)kSpMaxRuns || cb == 0u) ? 1 : 0;
+                S.flag = (ns > kSpMaxNs || nr >= (uint32_t)kSpMaxRuns || a.sp_cap == 0) ? 1 : 0;
                 S.nh = 0u;
                 S.out = 0u;
             }
         }
         for (int t = tid; t < kSpMaxNs + 2; t += kSpThreads) S.H[t] = 0u;
-        for (int b = tid; b < NB; b += kSpThreads) bfill[b] = 0u;
         __syncthreads();
         if (S.flag) {
             if (tid == 0) leave_to_tiled(a, ql);
@@ -1218,10 +1219,11 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             rstart = co[c];
             rlen = co[c + 1] - rstart;
             rstart = rlen ? (uint32_t)((int64_t)i * a.ix.n) + rstart : 0u;   // an empty run points at id 0's slot
+            rcell[tid] = (uint32_t)(i * K + c);
         }
         uint32_t total;
         const uint32_t rpos = block_excl_scan<kSpThreads>(rlen, S.red, &total);
-        if (total > (uint32_t)NB * cb) {              // more ids than the slots hold: some bucket overflows
+        if (total > (uint32_t)a.sp_cap) {            // more activated ids than the slots hold
             if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;
@@ -1229,9 +1231,58 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         if (tid <= nruns) runs[tid] = make_uint2(tid < nruns ? rstart : 0u, tid < nruns ? rpos : total);
         for (uint32_t q = (rpos + 1023u) >> 10; rlen && (q << 10) < rpos + rlen; ++q) S.crun[q] = (uint32_t)tid;
         __syncthreads();
-        // ---- 1. one walk into cb slots per bucket (every id is counted; the
-        // query is left to the tiled steps if a bucket overflows); all sixteen
-        // atomics of a step are issued before the stores they place
+        // ---- exact bucket sizes, from the index's count of each cell's ids per
+        // bucket summed over the query's runs: a wave takes four buckets at a
+        // time, a lane per run reads their four counts (one 8-byte load, two
+        // 16-bit counts a word: a bucket's total stays below 2^16, so the packed
+        // halves add without carry) and two wave sums finish them; then the
+        // buckets' offsets in the slots
+        {
+            // a wave's four groups of four buckets j0, j0 + 16, ... at once: their
+            // loads are issued together (a group past the end reloads group j0)
+            const int nb4 = (NB + 3) >> 2;
+            for (int j0 = w; j0 < nb4; j0 += 4 * kSpWaves) {
+                uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+                for (int r = lane; r < nruns; r += kWave) {
+                    const uint16_t *row = a.ix.cbh + (size_t)rcell[r] * NBp;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = j0 + u * kSpWaves < nb4 ? j0 + u * kSpWaves : j0;
+                        const uint2 v = *reinterpret_cast<const uint2 *>(row + 4 * j);
+                        lo[u] += v.x;
+                        hi[u] += v.y;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * kSpWaves;
+                    const uint32_t l = wave_sum(lo[u]), h = wave_sum(hi[u]);
+                    if (lane == 0 && j < nb4) {
+                        bx[4 * j] = l & 0xffffu;
+                        bx[4 * j + 1] = l >> 16;
+                        bx[4 * j + 2] = h & 0xffffu;
+                        bx[4 * j + 3] = h >> 16;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        {
+            uint32_t mine = 0;
+            for (int b = b0t; b < b1t; ++b) mine += bx[b];
+            uint32_t all;
+            uint32_t off = block_excl_scan<kSpThreads>(mine, S.red, &all);
+            for (int b = b0t; b < b1t; ++b) {
+                const uint32_t f = bx[b];
+                boff[b] = off;
+                bfill[b] = off;
+                off += f;
+            }
+        }
+        __syncthreads();
+        // ---- 1. one walk into the buckets' slots (the cursor of a bucket starts
+        // at its first slot); all sixteen atomics of a step are issued before
+        // the stores they place
         sp_walk(a, runs, S.crun, total, [&](const uint32_t (&id)[2 * kSpU], uint32_t vm, uint32_t um) {
             uint32_t pos[2 * kSpU];
 #pragma unroll
@@ -1241,21 +1292,13 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
                 if ((um >> u) & 1u) pos[u] = atomicAdd(v ? &bfill[id[u] >> kSpShift] : &S.sink[lane], v ? 1u : 0u);
             }
 #pragma unroll
-            for (int u = 0; u < 2 * kSpU; ++u)
-                if (((vm >> u) & 1u) && pos[u] < cb)
-                    raw[(id[u] >> kSpShift) * cb + pos[u]] = (uint16_t)(id[u] & (kSpBucket - 1));
+            for (int u = 0; u < 2 * kSpU; ++u)    // (the sizes are exact, so pos < total <= sp_cap; kept as a guard)
+                if (((vm >> u) & 1u) && pos[u] < (uint32_t)a.sp_cap) raw[pos[u]] = (uint16_t)(id[u] & (kSpBucket - 1));
         });
         __syncthreads();
-        bool over = false;
-        for (int b = b0t; b < b1t; ++b) over |= bfill[b] > cb;
-        if (__syncthreads_or(over)) {
-            if (tid == 0) leave_to_tiled(a, ql);
-            __syncthreads();
-            continue;
-        }
         // ---- 2. every bucket
         for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t n1 = sp_bucket(a, ql, b, raw + b * cb, bfill[b], win, hl, &S.nh, S.H, S.sink);
+            const uint32_t n1 = sp_bucket(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, &S.nh, S.H, S.sink);
             if (lane == 0) bx[b] = n1;
         }
         __syncthreads();
@@ -1316,7 +1359,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             if (cutb >= 0) {
                 const uint32_t take = bfill[cutb];
                 if (T == 1) {
-                    const uint16_t *f = raw + cutb * cb;
+                    const uint16_t *f = raw + boff[cutb];
                     cut = sp_cut(bx[cutb], take, win, [&](uint32_t j) { return (uint32_t)f[j]; });
                 } else {
                     cut = sp_cut(nhl, take, win, [&](uint32_t j) {
@@ -1348,7 +1391,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             for (int b = w; b < NB; b += kSpWaves) {
                 const uint32_t take = bfill[b], n1 = bx[b];
                 if (take == 0u) continue;
-                const uint16_t *f = raw + b * cb;
+                const uint16_t *f = raw + boff[b];
                 const uint32_t id0 = (uint32_t)b << kSpShift;
                 const uint32_t lim = take == n1 ? (uint32_t)kSpBucket : cut;
                 for (uint32_t j0 = 0; j0 < n1; j0 += kWave) {

@@ -98,7 +98,8 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
         (rc = dev_alloc(&ix->ids16, (size_t)ns * span)) || (rc = dev_alloc(&ix->csize, (size_t)ns * ix->K)) ||
         (rc = dev_alloc(&ix->assign, (size_t)2 * ns * n)) ||
         (ix->sp_cap && ((rc = dev_alloc(&ix->coffs, (size_t)ns * (ix->K + 1))) ||
-                        (rc = dev_alloc(&ix->ids32, (size_t)ns * n))))) {
+                        (rc = dev_alloc(&ix->ids32, (size_t)ns * n)) ||
+                        (rc = dev_alloc(&ix->cbh, (size_t)ns * ix->K * sp_nb_padded(ix->NB)))))) {
         ix->release();
         delete ix;
         return rc;
@@ -125,9 +126,11 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
 int finish_index(suco_index *ix, hipStream_t st) {
     HIPCHECK(launch_imi_build(ix->assign, ix->n, ix->ns, ix->sk, ix->P, ix->TILE, ix->toffs, ix->ids16,
                               ix->csize, st));
-    if (ix->sp_cap)
+    if (ix->sp_cap) {
         HIPCHECK(launch_cell_major(ix->toffs, ix->ids16, ix->csize, ix->n, ix->ns, ix->K, ix->P, ix->TILE, ix->coffs,
                                    ix->ids32, st));
+        HIPCHECK(launch_cell_buckets(ix->coffs, ix->ids32, ix->n, ix->ns, ix->K, ix->NB, ix->cbh, st));
+    }
     int *bad = nullptr;
     int rc = dev_alloc(&bad, 1);
     if (rc) return rc;

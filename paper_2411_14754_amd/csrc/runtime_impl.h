@@ -105,6 +105,7 @@ struct suco_index {
     uint8_t *X8 = nullptr;          // byte copy of X when every coordinate is an integer in 0..255
     uint32_t *coffs = nullptr;      // cell-major copy of the IMI for the sparse collision step
     uint32_t *ids32 = nullptr;
+    uint16_t *cbh = nullptr;        // ids of each cell per bucket of the sparse step
     int NB = 0;                     // buckets of the sparse step
     int sp_cap = 0;                 // its ids per round; 0: the step is off
     bool no_sparse = false;
@@ -142,7 +143,7 @@ struct suco_index {
     IndexView view() const {
         IndexView v;
         v.X = X; v.cent = cent; v.halves = halves; v.toffs = toffs; v.ids16 = ids16; v.csize = csize;
-        v.coffs = coffs; v.ids32 = ids32;
+        v.coffs = coffs; v.ids32 = ids32; v.cbh = cbh;
         v.n = n; v.d = d; v.ns = ns; v.sk = sk; v.K = K; v.P = P; v.TILE = TILE; v.NB = NB;
         v.act_form = act_form;
         v.metric = metric;
@@ -164,9 +165,9 @@ struct suco_index {
         prof_used = 0;
         for (void *p : {(void *)X, (void *)cent, (void *)halves, (void *)toffs, (void *)ids16, (void *)csize,
                         (void *)assign, (void *)arena, (void *)X8, (void *)Xb, (void *)xerr, (void *)centb,
-                        (void *)cnorm2, (void *)coffs, (void *)ids32})
+                        (void *)cnorm2, (void *)coffs, (void *)ids32, (void *)cbh})
             if (p) (void)hipFree(p);
-        coffs = nullptr; ids32 = nullptr;
+        coffs = nullptr; ids32 = nullptr; cbh = nullptr;
         X = nullptr; cent = nullptr; halves = nullptr; toffs = nullptr; ids16 = nullptr; csize = nullptr;
         assign = nullptr; arena = nullptr; arena_bytes = 0; X8 = nullptr;
         Xb = nullptr; xerr = nullptr; centb = nullptr; cnorm2 = nullptr;

@@ -28,6 +28,7 @@ struct IndexView {
     const uint32_t *csize;   // [ns][K] points per cell
     const uint32_t *coffs;   // [ns][K+1] start of cell c in ids32, or null (no sparse collision step)
     const uint32_t *ids32;   // [ns][n] point ids, cell-major, ascending within a cell
+    const uint16_t *cbh;     // [ns*K][sp_nb_padded(NB)] ids of each cell per bucket of kSpBucket ids
     int64_t n;
     int d, ns, sk, K, P, TILE;
     int NB;                  // buckets of kSpBucket consecutive ids (sparse collision step)
@@ -49,11 +50,11 @@ constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
 constexpr int kSpHCap = 4096;       // points of score >= 2 a query may list
 constexpr int kSpMaxChunks = 128;   // 1024-position chunks of a query's activated ids (the slots hold fewer)
 // Dynamic LDS of the sparse step for NB buckets and `cap` slots: the run
-// table, two per-bucket arrays padded to 16 bytes, the waves' score windows,
-// the list of points of score >= 2 and the slots.
+// table and the runs' cells, three per-bucket arrays padded to 16 bytes, the
+// waves' score windows, the list of points of score >= 2 and the slots.
 __host__ __device__ inline int sp_nb_padded(int NB) { return (NB + 4) & ~3; }
 __host__ __device__ inline size_t sp_lds_bytes(int NB, int cap) {
-    return 8 * (size_t)kSpMaxRuns + 8 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
+    return 12 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
            4 * (size_t)kSpHCap + 2 * (size_t)((cap + 7) & ~7);
 }
 
@@ -248,5 +249,7 @@ hipError_t launch_imi_build(const uint8_t *assign, int64_t n, int ns, int sk, in
                             uint32_t *toffs, uint16_t *ids16, uint32_t *csize, hipStream_t s);
 hipError_t launch_cell_major(const uint32_t *toffs, const uint16_t *ids16, const uint32_t *csize, int64_t n,
                              int ns, int K, int P, int TILE, uint32_t *coffs, uint32_t *ids32, hipStream_t s);
+hipError_t launch_cell_buckets(const uint32_t *coffs, const uint32_t *ids32, int64_t n, int ns, int K, int NB,
+                               uint16_t *cbh, hipStream_t s);
 
 }  // namespace suco
