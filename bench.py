@@ -1127,7 +1127,16 @@ def main():
 
         ms_pb, _ = timed_steps(plain_stream, args.steps, max(1, args.warmup))
         log(f"plain batched stream: {ms_pb / args.steps:.3f} ms/step, {nq * args.steps / (ms_pb / 1e3):.0f} QPS")
+        # the same uneven batches handed over together: one launch for all of them
+        bt = suco.Batcher(ix, nq, k, beta)
+        starts = [sum(sizes[:j]) for j in range(len(sizes) + 1)]
+        parts = [Qd[starts[j]:starts[j + 1]] for j in range(len(sizes))]
+        outs = [(ids[starts[j]:starts[j + 1]], dists[starts[j]:starts[j + 1]]) for j in range(len(sizes))]
+        ms_pt, _ = timed_steps(lambda: bt.query_multi(parts, alpha=alpha, outs=outs), args.steps, max(1, args.warmup))
+        log(f"plain batched, {len(sizes)} batches in one launch: {ms_pt / args.steps:.3f} ms/step, "
+            f"{nq * args.steps / (ms_pt / 1e3):.0f} QPS")
         b.set_model(net, scale, amin, amax)
+        bt.set_model(net, scale, amin, amax)
 
         def stream_pass():
             s0 = 0
@@ -1135,7 +1144,12 @@ def main():
                 b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
                 s0 += sz
 
-        ms_l, per_step = timed_steps(stream_pass, args.steps, max(1, args.warmup))
+        ms_ls, _ = timed_steps(stream_pass, args.steps, max(1, args.warmup))
+        rec_stream = recall_at(ids, gt)
+        log(f"learned+batched, one launch per batch: {ms_ls / args.steps:.3f} ms/step, "
+            f"{nq * args.steps / (ms_ls / 1e3):.0f} QPS, recall@10={rec_stream:.4f}")
+        ids.zero_()
+        ms_l, per_step = timed_steps(lambda: bt.query_multi(parts, outs=outs), args.steps, max(1, args.warmup))
         value = nq * args.steps / (ms_l / 1e3)
         rec = recall_at(ids, gt)
         learned_mre = mean_relative_error(dists, exact_dists(Xd, Qd, gt))
@@ -1150,11 +1164,30 @@ def main():
             if lo["recall"] < rec <= hi["recall"]:
                 f = (rec - lo["recall"]) / (hi["recall"] - lo["recall"])
                 plain_eq = math.exp(math.log(lo["qps"]) + f * (math.log(hi["qps"]) - math.log(lo["qps"])))
-        ms, form = ms_l, "learned+batched"
+        ms, form = ms_l, f"learned+batched ({len(sizes)} uneven batches in one launch)"
         log(f"learned+batched: {ms_l / args.steps:.3f} ms/step, {value:.0f} QPS, recall@10={rec:.4f}, "
             f"mean alpha {mean_alpha:.5f}; plain at that recall {plain_eq}")
+        # a higher target: the same network with its scale calibrated for recall 0.99 on the
+        # held-out queries (clamp 0.05), against plain SuCo at the same recall
+        t99 = 0.99
+        sc99 = learned.calibrate_scale(ix, net, Qv, gt_v, k, beta, t99, amin, 0.05)
+        ms99, _ = timed_steps(lambda: suco.query_learned(ix, net, Qd, k, beta, sc99, amin, 0.05,
+                                                         out=(ids, dists)), args.steps, max(1, args.warmup))
+        rec99 = recall_at(ids, gt)
+        plain99 = None
+        for lo, hi_ in zip(sweep, sweep[1:]):
+            if lo["recall"] < rec99 <= hi_["recall"]:
+                f = (rec99 - lo["recall"]) / (hi_["recall"] - lo["recall"])
+                plain99 = math.exp(math.log(lo["qps"]) + f * (math.log(hi_["qps"]) - math.log(lo["qps"])))
+        hi99 = {"target": t99, "scale": round(sc99, 5), "qps": round(nq * args.steps / (ms99 / 1e3), 1),
+              "recall_at_10": round(rec99, 5), "plain_qps_at_same_recall": None if plain99 is None else round(plain99, 1)}
+        log(f"learned at recall {rec99:.4f} (one call): {hi99['qps']:.0f} QPS; plain at that recall {plain99}")
         learned_info = {"plain_batched_stream_qps": round(nq * args.steps / (ms_pb / 1e3), 1),
+                        "plain_batched_one_launch_qps": round(nq * args.steps / (ms_pt / 1e3), 1),
+                        "learned_batched_stream_qps": round(nq * args.steps / (ms_ls / 1e3), 1),
+                        "learned_batched_stream_recall_at_10": round(rec_stream, 5),
                         "learned_one_call_qps": round(nq * args.steps / (ms_l1 / 1e3), 1),
+                        "at_recall_0.99": hi99,
                         "train_queries": m_tr, "val_queries": args.val_queries, "epochs": args.epochs,
                         "scale": round(scale, 5), "alpha_clamp": [amin, amax], "mean_alpha": round(mean_alpha, 6),
                         "train_s": round(train_s, 2),
@@ -1162,6 +1195,7 @@ def main():
                         "mre": learned_mre,
                         "loss_first_last": [round(info["loss"][0], 4), round(info["loss"][-1], 4)]}
         b.free()
+        bt.free()
         net.free()
     ms_step = ms / args.steps
     log(f"reported: {form}, {value:.0f} QPS, recall@10={rec:.4f}")

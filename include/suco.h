@@ -352,6 +352,18 @@ SUCO_API int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_
                                  const char *tune_file, suco_batcher **out);
 SUCO_API int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float *alpha_q,
                                 double alpha, int32_t *ids, float *dists, void *stream);
+/* Several batches of uneven size in one launch: nb (1..16) batches, batch j
+ * with nq[j] >= 0 queries at Q[j] (device [nq[j]][d]), results to ids[j] and
+ * dists[j] (device [nq[j]][k]); alpha_q NULL (then `alpha` for all) or
+ * alpha_q[j] device [nq[j]] float32 for every non-empty batch.  Q, nq, alpha_q,
+ * ids and dists are host arrays of nb entries, read during the call.  The
+ * batches are placed back to back in the staging buffers and the graph of the
+ * bucket of their total (at most max_batch, else SUCO_E_INVAL) runs once; each
+ * batch's results are bitwise those of suco_batcher_query on it alone.  Same
+ * stream, ordering and lifetime rules as suco_batcher_query. */
+SUCO_API int suco_batcher_query_multi(suco_batcher *b, int32_t nb, const float *const *Q, const int64_t *nq,
+                                      const float *const *alpha_q, double alpha, int32_t *const *ids,
+                                      float *const *dists, void *stream);
 /* Tuned launch shape of a built bucket: params[3] = {re-rank rows per
  * work-group, collision grid cap, re-rank grid cap} (0 = one block per item),
  * ms = the tuned graph's time on its first batch. */

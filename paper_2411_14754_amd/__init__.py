@@ -27,7 +27,7 @@ EXPORTED = (
     "suco_mlp_set_params", "suco_mlp_forward_backward", "suco_mlp_train_epoch", "suco_mlp_predict",
     "suco_mlp_free", "suco_query_features", "suco_query_learned", "suco_batcher_set_model",
     "suco_query_bf16", "suco_query_bf16_debug", "suco_index_flags", "suco_index_save", "suco_index_load",
-    "suco_query_noalloc", "suco_query_sclinear", "suco_index_set_activation",
+    "suco_query_noalloc", "suco_query_sclinear", "suco_index_set_activation", "suco_batcher_query_multi",
 )
 
 STAGES = ("activate", "collide", "select", "rerank", "merge", "centres_bf16", "rerank_bf16", "survivors", "order",
@@ -93,6 +93,7 @@ def lib():
         L.suco_profile_read.argtypes = [P, P, P]
         L.suco_batcher_create.argtypes = [P, i32, i32, dbl, C.c_char_p, C.POINTER(P)]
         L.suco_batcher_query.argtypes = [P, P, i64, P, dbl, P, P, P]
+        L.suco_batcher_query_multi.argtypes = [P, i32, P, P, P, dbl, P, P, P]
         L.suco_batcher_tuning.argtypes = [P, i32, P, P]
         L.suco_batcher_free.argtypes = [P]
         L.suco_mlp_num_params.restype = i64
@@ -392,6 +393,30 @@ class Batcher:
         _check(lib().suco_batcher_query(self._h, pq, nq, pa, float(alpha), _dev(ids, torch.int32),
                                         _dev(dists, torch.float32), _stream(stream)))
         return ids, dists
+
+    def query_multi(self, Qs, alpha: float = 0.0, alpha_qs=None, outs=None, stream=None):
+        """Several batches (up to 16) in one launch (suco_batcher_query_multi);
+        returns [(ids, dists)] per batch."""
+        torch = _torch()
+        nb = len(Qs)
+        if outs is None:
+            outs = [self.index._out(q.shape[0], self.k) for q in Qs]
+        PA = C.c_void_p * max(1, nb)
+        pq, pa, pi, pd = PA(), PA(), PA(), PA()
+        nq = (C.c_int64 * max(1, nb))()
+        for j, Q in enumerate(Qs):
+            n = Q.shape[0]
+            nq[j] = n
+            if n == 0:
+                continue
+            pq[j] = _dev(Q, torch.float32, (n, self.index.d), "Q")
+            if alpha_qs is not None:
+                pa[j] = _dev(alpha_qs[j], torch.float32, (n,), "alpha_q")
+            pi[j] = _dev(outs[j][0], torch.int32, (n, self.k), "ids")
+            pd[j] = _dev(outs[j][1], torch.float32, (n, self.k), "dists")
+        _check(lib().suco_batcher_query_multi(self._h, nb, pq, nq, pa if alpha_qs is not None else None,
+                                              float(alpha), pi, pd, _stream(stream)))
+        return outs
 
     def set_model(self, mlp, scale: float = 1.0, alpha_min: float = 1e-4, alpha_max: float = 1.0):
         """Compute each batch's alphas with `mlp` inside the graph (None detaches)."""

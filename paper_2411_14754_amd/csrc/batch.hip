@@ -9,7 +9,11 @@
 // its items and reads the batch size on the device, so one graph, captured once,
 // serves every batch of its bucket.  Per call the host writes the caller's
 // pointers and the batch size into a device mailbox with one tiny kernel and
-// launches the graph.
+// launches the graph.  A call may also hand over several batches (up to 16) at
+// once: the stage-in kernel places them back to back in the staging rows, the
+// graph of the bucket of their total runs once, and the stage-out kernel
+// returns each batch's results to its own buffers, so batches of uneven size
+// that are ready together share one launch.
 //
 // The launch shapes of a bucket (re-rank rows per work-group, grid caps of the
 // collision and re-rank kernels) are chosen on the bucket's first use by timing
@@ -26,39 +30,63 @@
 
 namespace suco {
 
-struct Mail {
-    int nq;
-    int per_query_alpha;
-    double alpha;
+constexpr int kMailBatches = 16;   // batches one call may hand over together
+
+// One call's batches: batch j holds nq queries that take the staging rows
+// q0 .. q0 + nq - 1 (the batches in call order, back to back).
+struct MailBatch {
     const float *Q;
     const float *alpha_q;
     int32_t *ids;
     float *dists;
+    int q0, nq;
+};
+
+struct Mail {
+    int nq;                 // all the call's queries
+    int nb;                 // batches, 1 .. kMailBatches
+    int per_query_alpha;
+    double alpha;
+    MailBatch b[kMailBatches];
 };
 
 __global__ void k_set_mail(Mail *dst, Mail m) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *dst = m;
 }
 
-// Queries to staging (float4), collision ratios to FP64 staging, batch size.
+// Every batch's queries to their staging rows (float4), collision ratios to
+// FP64 staging, the total into device memory.
 __global__ __launch_bounds__(256) void k_stage_in(const Mail *mail, float4 *Qs, double *alphas, int *nq_dev,
                                                   int d4) {
-    const Mail m = *mail;
+    const Mail &m = *mail;
+    const int nb = m.nb, pqa = m.per_query_alpha;
+    const double alpha = m.alpha;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const float4 *src = reinterpret_cast<const float4 *>(m.Q);
-    for (int64_t t = t0; t < (int64_t)m.nq * d4; t += stride) Qs[t] = src[t];
-    for (int64_t t = t0; t < m.nq; t += stride) alphas[t] = m.per_query_alpha ? (double)m.alpha_q[t] : m.alpha;
+    for (int j = 0; j < nb; ++j) {
+        const MailBatch bj = m.b[j];
+        const float4 *src = reinterpret_cast<const float4 *>(bj.Q);
+        float4 *dst = Qs + (int64_t)bj.q0 * d4;
+        for (int64_t t = t0; t < (int64_t)bj.nq * d4; t += stride) dst[t] = src[t];
+        for (int64_t t = t0; t < bj.nq; t += stride) alphas[bj.q0 + t] = pqa ? (double)bj.alpha_q[t] : alpha;
+    }
     if (t0 == 0) *nq_dev = m.nq;
 }
 
+// Every batch's results from staging to its caller's buffers.
 __global__ __launch_bounds__(256) void k_stage_out(const Mail *mail, const int32_t *ids_s, const float *dists_s,
                                                    int k) {
-    const Mail m = *mail;
+    const Mail &m = *mail;
+    const int nb = m.nb;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)m.nq * k; t += stride) {
-        m.ids[t] = ids_s[t];
-        m.dists[t] = dists_s[t];
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int j = 0; j < nb; ++j) {
+        const MailBatch bj = m.b[j];
+        const int64_t o = (int64_t)bj.q0 * k;
+        for (int64_t t = t0; t < (int64_t)bj.nq * k; t += stride) {
+            bj.ids[t] = ids_s[o + t];
+            bj.dists[t] = dists_s[o + t];
+        }
     }
 }
 
@@ -363,16 +391,38 @@ int suco_batcher_create(const suco_index *ix, int32_t max_batch, int32_t k, doub
     return SUCO_OK;
 }
 
-int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float *alpha_q, double alpha,
-                       int32_t *ids, float *dists, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// The batches of one call (nb >= 1, checked by the callers) through the graph
+// of the bucket of their total.  per_query: alpha_q[j] is given for every batch.
+int batcher_run(suco_batcher *b, int nb, const float *const *Q, const int64_t *nq, const float *const *alpha_q,
+                double alpha, int32_t *const *ids, float *const *dists, void *stream) {
     if (!batcher_ok(b)) return fail(SUCO_E_STATE, "invalid or freed batcher handle");
     if (!index_ok(b->ix)) return fail(SUCO_E_STATE, "the batcher's index was freed");
-    if (nq < 0 || nq > b->maxb) return fail(SUCO_E_INVAL, "nq must be in [0, max_batch]");
-    if (!b->model && !alpha_q && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
-    if (b->model && alpha_q) return fail(SUCO_E_INVAL, "a batcher with a model takes no alpha_q");
+    const bool per_query = alpha_q != nullptr;
+    if (!b->model && !per_query && !(alpha > 0.0 && alpha <= 1.0)) return fail(SUCO_E_INVAL, "alpha must be in (0, 1]");
+    if (b->model && per_query) return fail(SUCO_E_INVAL, "a batcher with a model takes no alpha_q");
     if (b->model && !mlp_valid(b->model)) return fail(SUCO_E_STATE, "the batcher's model was freed");
-    if (nq > 0 && (!Q || !ids || !dists)) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
-    if (nq == 0) return SUCO_OK;
+    Mail m{};
+    int64_t total = 0;
+    for (int j = 0; j < nb; ++j) {
+        if (nq[j] < 0 || nq[j] > b->maxb) return fail(SUCO_E_INVAL, "nq must be in [0, max_batch]");
+        if (nq[j] > 0 && (!Q[j] || !ids[j] || !dists[j])) return fail(SUCO_E_INVAL, "Q, ids and dists must not be NULL");
+        if (nq[j] > 0 && per_query && !alpha_q[j]) return fail(SUCO_E_INVAL, "alpha_q must not be NULL");
+        MailBatch &mb = m.b[m.nb];
+        mb.Q = Q[j];
+        mb.alpha_q = per_query ? alpha_q[j] : nullptr;
+        mb.ids = ids[j];
+        mb.dists = dists[j];
+        mb.q0 = (int)total;
+        mb.nq = (int)nq[j];
+        if (nq[j] > 0) ++m.nb;          // empty batches take no entry
+        total += nq[j];
+        if (total > b->maxb) return fail(SUCO_E_INVAL, "the batches' total must be at most max_batch");
+    }
+    if (total == 0) return SUCO_OK;
     hipStream_t st = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(b->mu);
     DeviceGuard dg(b->device);
@@ -382,18 +432,14 @@ int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float 
         alpha = 1.0;
     }
     if (b->pending) HIPCHECK(hipStreamWaitEvent(st, b->done, 0));
-    Mail m{};
-    m.nq = (int)nq;
-    m.per_query_alpha = alpha_q != nullptr;
+    m.nq = (int)total;
+    m.per_query_alpha = per_query;
     m.alpha = alpha;
-    m.Q = Q;
-    m.alpha_q = alpha_q;
-    m.ids = ids;
-    m.dists = dists;
+    const int64_t nq_all = total;
     hipLaunchKernelGGL(k_set_mail, dim3(1), dim3(64), 0, st, b->mail, m);
     HIPCHECK(hipGetLastError());
     int size = 1;
-    while (size < nq) size *= 2;
+    while (size < nq_all) size *= 2;
     Bucket &bk = b->buckets[size];
     if (!bk.exec) {
         bk.size = size;
@@ -409,6 +455,24 @@ int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float 
     HIPCHECK(hipEventRecord(b->done, st));
     b->pending = true;
     return SUCO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int suco_batcher_query(suco_batcher *b, const float *Q, int64_t nq, const float *alpha_q, double alpha,
+                       int32_t *ids, float *dists, void *stream) {
+    const float *const aq[1] = {alpha_q};
+    return batcher_run(b, 1, &Q, &nq, alpha_q ? aq : nullptr, alpha, &ids, &dists, stream);
+}
+
+int suco_batcher_query_multi(suco_batcher *b, int32_t nb, const float *const *Q, const int64_t *nq,
+                             const float *const *alpha_q, double alpha, int32_t *const *ids, float *const *dists,
+                             void *stream) {
+    if (nb < 1 || nb > kMailBatches) return fail(SUCO_E_INVAL, "nb must be in [1, 16]");
+    if (!Q || !nq || !ids || !dists) return fail(SUCO_E_INVAL, "Q, nq, ids and dists must not be NULL");
+    return batcher_run(b, nb, Q, nq, alpha_q, alpha, ids, dists, stream);
 }
 
 int suco_batcher_set_model(suco_batcher *b, suco_mlp *m, float scale, float alpha_min, float alpha_max) {

@@ -19,7 +19,10 @@
 //
 // Inference (BF16): weights and layer inputs are rounded to BF16 (nearest,
 // ties to even) and products are accumulated in FP32 in index order; the
-// collision ratio is alpha = clamp(scale * exp(y), alpha_min, alpha_max).
+// collision ratio is alpha = clamp(scale * exp(y), alpha_min, alpha_max).  The
+// rounded copy the inference kernels read holds W1 and W2 transposed (W1 as
+// [n_in][H], W2 as [H][H] by column), so that hidden unit j's weights are read
+// by thread j with the loads of a wave falling on consecutive words.
 #include "runtime_impl.h"
 
 namespace suco {
@@ -112,7 +115,7 @@ struct InferRegs {
 __device__ __forceinline__ void infer_regs(const MlpView &w, InferRegs &R) {
     const int j = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < kH; ++i) R.w2[i] = w.W2[j * kH + i];
+    for (int i = 0; i < kH; ++i) R.w2[i] = w.W2[i * kH + j];   // transposed copy: W2[j][i]
     R.b1 = w.b1[j];
     R.b2 = w.b2[j];
     R.w3 = w.W3[j];
@@ -128,7 +131,7 @@ __device__ __forceinline__ void infer_row(const InferPass &ip, const InferRegs &
     for (int i = j; i < w.n_in; i += kH) x[i] = bf16r((fr[i] - w.mu[i]) / w.sigma[i]);
     __syncthreads();
     float z = R.b1;
-    for (int i = 0; i < w.n_in; ++i) z = fmaf(w.W1[j * w.n_in + i], x[i], z);
+    for (int i = 0; i < w.n_in; ++i) z = fmaf(w.W1[i * kH + j], x[i], z);   // transposed copy: W1[j][i]
     h[j] = bf16r(gelu_f(z));
     __syncthreads();
     float z2 = R.b2;
@@ -288,9 +291,19 @@ __global__ __launch_bounds__(256) void k_adam(float *w, const float *g, float *m
     w[p] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
-__global__ void k_round_bf16(const float *src, float *dst, int64_t n) {
+// The inference copy: every parameter rounded to BF16, W1 and W2 transposed.
+__global__ void k_round_bf16(const float *src, float *dst, int64_t n, int n_in) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) dst[p] = bf16r(src[p]);
+    if (p >= n) return;
+    const int64_t nW1 = (int64_t)kH * n_in, o2 = nW1 + kH;
+    int64_t at = p;
+    if (p < nW1) {
+        at = (p % n_in) * kH + p / n_in;                     // W1[j][i] -> [i][j]
+    } else if (p >= o2 && p < o2 + (int64_t)kH * kH) {
+        const int64_t e = p - o2;
+        at = o2 + (e % kH) * kH + e / kH;                    // W2[j][i] -> [i][j]
+    }
+    dst[at] = bf16r(src[p]);
 }
 
 }  // namespace suco
@@ -301,7 +314,7 @@ struct suco_mlp {
     uint64_t magic = 0x5375436f4d4c5031ULL;
     int device = 0, n_in = 0, H = kH;
     int64_t np = 0;
-    float *w = nullptr, *wb = nullptr;       // FP32 parameters, BF16-rounded copy for inference
+    float *w = nullptr, *wb = nullptr;       // FP32 parameters; BF16-rounded copy for inference (W1, W2 transposed)
     float *m1 = nullptr, *m2 = nullptr, *g = nullptr;
     float *mu = nullptr, *sigma = nullptr;
     float *loss = nullptr;
@@ -380,7 +393,8 @@ hipError_t grads_pass(suco_mlp *p, const TrainRows &a, hipStream_t st) {
 
 int refresh_bf16(suco_mlp *p, hipStream_t st) {
     if (p->wb_valid) return SUCO_OK;
-    hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, st, p->w, p->wb, p->np);
+    hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, st, p->w, p->wb, p->np,
+                       p->n_in);
     HIPCHECK(hipGetLastError());
     p->wb_valid = true;
     return SUCO_OK;

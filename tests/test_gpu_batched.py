@@ -86,6 +86,51 @@ def test_per_query_alpha_batched(suco, mixture_index):
     b.free()
 
 
+def test_multi_batches_in_one_launch(suco, mixture_index):
+    """Uneven batches (one of them empty) handed over in one call equal each
+    batch through its own call, with one alpha and with per-query alphas."""
+    ix, Q = mixture_index
+    sizes = [37, 0, 1, 700, 129, 1000, 64]
+    starts = np.cumsum([0] + sizes)
+    parts = [Q[starts[j]:starts[j + 1]] for j in range(len(sizes))]
+    aq = torch.from_numpy(np.random.default_rng(2).uniform(0.01, 0.2, int(starts[-1])).astype(np.float32)).cuda()
+    aparts = [aq[starts[j]:starts[j + 1]] for j in range(len(sizes))]
+    b = suco.Batcher(ix, 2048, 10, 0.005)
+    for per_query in (False, True):
+        print(f"case: multi per_query={per_query}", flush=True)
+        outs = b.query_multi(parts, alpha=0.05, alpha_qs=aparts if per_query else None)
+        torch.cuda.synchronize()
+        for j, q in enumerate(parts):
+            assert outs[j][0].shape == (sizes[j], 10)
+            if sizes[j] == 0:
+                continue
+            ids, d = (b.query(q, alpha_q=aparts[j]) if per_query else b.query(q, alpha=0.05))
+            torch.cuda.synchronize()
+            assert np.array_equal(outs[j][0].cpu().numpy(), ids.cpu().numpy()), j
+            assert np.array_equal(outs[j][1].cpu().numpy().view(np.uint32), d.cpu().numpy().view(np.uint32)), j
+        p_ids, p_d = plain(ix, Q[:int(starts[-1])], 10, 0.05, 0.005, alpha_q=aq if per_query else None)
+        assert np.array_equal(torch.cat([o[0] for o in outs]).cpu().numpy(), p_ids)
+    # a second call with fewer, smaller batches reuses the buffers of the first
+    outs = b.query_multi(parts[:2], alpha=0.05)
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[0][0].cpu().numpy(), plain(ix, parts[0], 10, 0.05, 0.005)[0])
+    b.free()
+
+
+def test_multi_errors(suco, mixture_index):
+    ix, Q = mixture_index
+    b = suco.Batcher(ix, 256, 10, 0.005)
+    with pytest.raises(suco.SucoError):
+        b.query_multi([Q[:1]] * 17, alpha=0.05)                    # more than 16 batches
+    with pytest.raises(suco.SucoError):
+        b.query_multi([Q[:200], Q[:100]], alpha=0.05)              # total beyond max_batch
+    with pytest.raises(suco.SucoError):
+        b.query_multi([Q[:10]], alpha=0.0)
+    outs = b.query_multi([Q[:0], Q[:0]], alpha=0.05)
+    assert outs[0][0].shape == (0, 10)
+    b.free()
+
+
 def test_tune_file_round_trip(suco, mixture_index, tmp_path):
     ix, Q = mixture_index
     path = str(tmp_path / "tune.txt")
@@ -134,6 +179,17 @@ def test_sift_like_uneven_stream_full_size(suco):
     for s in W.batch_sizes(Q.shape[0]):
         b.query(Q[start:start + s], alpha=0.003, out=(out_ids[start:start + s], out_d[start:start + s]))
         start += s
+    torch.cuda.synchronize()
+    assert np.array_equal(out_ids.cpu().numpy(), p_ids)
+    assert np.array_equal(out_d.cpu().numpy(), p_d)
+    b.free()
+    # the same uneven batches handed over together, in one launch
+    b = suco.Batcher(ix, Q.shape[0], 10, 0.005)
+    sizes = W.batch_sizes(Q.shape[0])
+    starts = np.cumsum([0] + list(sizes))
+    outs = [(out_ids[starts[j]:starts[j + 1]], out_d[starts[j]:starts[j + 1]]) for j in range(len(sizes))]
+    out_ids.zero_()
+    b.query_multi([Q[starts[j]:starts[j + 1]] for j in range(len(sizes))], alpha=0.003, outs=outs)
     torch.cuda.synchronize()
     assert np.array_equal(out_ids.cpu().numpy(), p_ids)
     assert np.array_equal(out_d.cpu().numpy(), p_d)

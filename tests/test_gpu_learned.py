@@ -179,6 +179,11 @@ def test_learned_query_equals_plain_with_its_alphas(suco):
     torch.cuda.synchronize()
     assert np.array_equal(b_ids.cpu().numpy(), ids.cpu().numpy())
     assert np.array_equal(b_d.cpu().numpy(), d.cpu().numpy())
+    # uneven batches handed over together: each query's alpha is still its own
+    outs = b.query_multi([Qd[:100], Qd[100:101], Qd[101:]])
+    torch.cuda.synchronize()
+    assert np.array_equal(torch.cat([o[0] for o in outs]).cpu().numpy(), ids.cpu().numpy())
+    assert np.array_equal(torch.cat([o[1] for o in outs]).cpu().numpy(), d.cpu().numpy())
     b.free()
     aq = au.cpu().numpy()
     g = {kk: v.cpu().numpy() if v.dtype != torch.uint16 else v.view(torch.int16).cpu().numpy().view(np.uint16)
