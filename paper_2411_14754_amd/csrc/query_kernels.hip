@@ -957,7 +957,8 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     point gets its score, later ones get 0, and the window ends clear.  The
 //     bucket's points of score 1 replace its slots' front (the slots already
 //     read), those of score s >= 2 go to one list of the work-group as
-//     (id << 4 | s) and add one to H[s] (the histogram G[t] = #{score >= t});
+//     (id << 4 | s), held in the slots past the query's own, and add one to
+//     H[s] (the histogram G[t] = #{score >= t});
 //  3. T = max{t : G[t] >= B} and R = B - G[T+1]: every listed point above T is
 //     a candidate, and of the points at T the R lowest ids.  Per bucket, its
 //     points at T (the front count when T = 1, else counted over the list); a
@@ -967,15 +968,16 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     counting.  Candidates are appended in no particular order.
 // A query is left to the tiled steps (route 1) when N_s > 15, it has
 // kSpMaxRuns activated cells or more, more activated ids than the slots, more
-// than kSpHCap points score 2 or more, or T = 0 (fewer than B points collide:
-// the score-0 points are the tiled selection's case); otherwise route 0, and
-// the tiled collision and selection kernels skip the query.
+// points of score 2 or more than the slots past its ids hold, or T = 0 (fewer
+// than B points collide: the score-0 points are the tiled selection's case);
+// otherwise route 0, and the tiled collision and selection kernels skip the
+// query.
 struct SparseLds {
     uint32_t H[kSpMaxNs + 2];        // H[s]: points of score s >= 2
     uint32_t sink[kWave];            // targets of the atomics of empty slots, one word per lane
     uint32_t red[2 * kSpWaves + 2];
     uint32_t cpre[kSpMaxNs + 1];     // activated cells of the subspaces before i
-    uint32_t nh;                     // points in the list of scores >= 2 (may pass kSpHCap)
+    uint32_t nh;                     // points in the list of scores >= 2 (may pass its capacity)
     uint32_t out;                    // candidates written
     int nruns, flag, cutb;
     uint32_t cut;
@@ -1025,11 +1027,11 @@ __device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, c
 
 // One bucket by one wave (step 2).  seg holds its len low ids and receives
 // its points of score 1 at the front; those of higher score go to the list
-// hl (capacity kSpHCap, count *hn); sink takes the atomics of empty slots.
+// hl (capacity hcap, count *hn); sink takes the atomics of empty slots.
 // Returns the number of points of score 1.
 __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, const int b, uint16_t *seg,
-                                              const uint32_t len, uint32_t *win, uint32_t *hl, uint32_t *hn,
-                                              uint32_t *H, uint32_t *sink) {
+                                              const uint32_t len, uint32_t *win, uint32_t *hl, const uint32_t hcap,
+                                              uint32_t *hn, uint32_t *H, uint32_t *sink) {
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int UQ = 4;
     // a bucket of at most UQ*64 ids (the common case) is read once: the claims
@@ -1106,7 +1108,7 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
             for (int q = 0; q < UQ; ++q) {
                 if (sv[q] >= 2u) {
                     const uint32_t at = base + lanes_below(mh[q]);
-                    if (at < (uint32_t)kSpHCap) hl[at] = ((id0 | u[q]) << 4) | sv[q];
+                    if (at < hcap) hl[at] = ((id0 | u[q]) << 4) | sv[q];
                     atomicAdd(&H[sv[q]], 1u);
                 }
                 base += (uint32_t)__popcll(mh[q]);
@@ -1175,8 +1177,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
     uint32_t *boff = bfill + NBp;                                          // [NB] first slot of each bucket
     uint32_t *bx = boff + NBp;                                             // [NB] points of score 1, then level-T points
     uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
-    uint32_t *hl = win_all + kSpWaves * kSpWords;                          // [kSpHCap] (id << 4 | score), score >= 2
-    uint16_t *raw = reinterpret_cast<uint16_t *>(hl + kSpHCap);            // slots: each bucket's low ids, then its score-1 points
+    uint16_t *raw = reinterpret_cast<uint16_t *>(win_all + kSpWaves * kSpWords);   // slots: each bucket's low ids, then its score-1 points
     uint32_t *win = win_all + w * kSpWords;
     const int nq = pass_nq(a.nq_dev, a.q_base, a.nq);
     const int per = (NB + kSpThreads - 1) / kSpThreads;
@@ -1228,6 +1229,10 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             __syncthreads();
             continue;
         }
+        // the list of points of score >= 2 takes the slots past the query's own
+        const uint32_t tot2 = (total + 1u) & ~1u;
+        uint32_t *hl = reinterpret_cast<uint32_t *>(raw + tot2);                // (id << 4 | score), score >= 2
+        const uint32_t hcap = tot2 < (uint32_t)a.sp_cap ? ((uint32_t)a.sp_cap - tot2) / 2u : 0u;
         if (tid <= nruns) runs[tid] = make_uint2(tid < nruns ? rstart : 0u, tid < nruns ? rpos : total);
         for (uint32_t q = (rpos + 1023u) >> 10; rlen && (q << 10) < rpos + rlen; ++q) S.crun[q] = (uint32_t)tid;
         __syncthreads();
@@ -1298,7 +1303,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         __syncthreads();
         // ---- 2. every bucket
         for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t n1 = sp_bucket(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, &S.nh, S.H, S.sink);
+            const uint32_t n1 = sp_bucket(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, hcap, &S.nh, S.H, S.sink);
             if (lane == 0) bx[b] = n1;
         }
         __syncthreads();
@@ -1320,7 +1325,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             }
         }
         const uint32_t nhl = S.nh;
-        if (T == 0 || nhl > (uint32_t)kSpHCap) {
+        if (T == 0 || nhl > hcap) {
             if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;

@@ -47,15 +47,15 @@ constexpr int kSpWords = kSpBucket / 8;
 constexpr int kSpMaxNs = 15;        // a 4-bit score
 constexpr int kSpMaxBuckets = 4096; // n <= 2^24
 constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
-constexpr int kSpHCap = 4096;       // points of score >= 2 a query may list
 constexpr int kSpMaxChunks = 128;   // 1024-position chunks of a query's activated ids (the slots hold fewer)
 // Dynamic LDS of the sparse step for NB buckets and `cap` slots: the run
 // table and the runs' cells, three per-bucket arrays padded to 16 bytes, the
-// waves' score windows, the list of points of score >= 2 and the slots.
+// waves' score windows and the slots (a query's activated ids, then its list
+// of points of score >= 2).
 __host__ __device__ inline int sp_nb_padded(int NB) { return (NB + 4) & ~3; }
 __host__ __device__ inline size_t sp_lds_bytes(int NB, int cap) {
     return 12 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
-           4 * (size_t)kSpHCap + 2 * (size_t)((cap + 7) & ~7);
+           2 * (size_t)((cap + 7) & ~7);
 }
 
 // One pass of the query path over a chunk of queries.
