@@ -702,9 +702,12 @@ def bench_sift_k50(args, log):
 def bench_form(args, log):
     """One form of the SIFT-like query path alone, for kernel traces of it:
     `onecall` (10,000 queries in one plain call at alpha = 0.003), `batched`
-    (the same queries as five uneven batches through a batcher), `learned`
-    (the five batches through a batcher with the trained budget model, alpha
-    clamped to [0.0005, 0.0035]).  Prints the per-step time."""
+    (the same queries as five uneven batches through a batcher, one launch
+    each), `multi` (the five batches handed over together, one launch),
+    `learned` / `learned_multi` (the five batches through a batcher with the
+    trained budget model, alpha clamped to [0.0005, 0.0035], one launch each /
+    together), `learned_onecall` (suco_query_learned on all 10,000).  Prints
+    the per-step time."""
     import torch
     import paper_2411_14754_amd as suco
     import synth
@@ -718,33 +721,40 @@ def bench_form(args, log):
     dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
     sizes = W.batch_sizes(nq)
     alpha = 0.003
+    starts = [sum(sizes[:j]) for j in range(len(sizes) + 1)]
+    parts = [Qd[starts[j]:starts[j + 1]] for j in range(len(sizes))]
+    outs = [(ids[starts[j]:starts[j + 1]], dists[starts[j]:starts[j + 1]]) for j in range(len(sizes))]
+    net = scale = None
+    if args.form.startswith("learned"):
+        from paper_2411_14754_amd import learned
+        Qt = torch.from_numpy(W.train_queries(30_000)).cuda()
+        gt_t = exact_topk(Xd, Qt, k)
+        grid = learned.alpha_grid(0.0005, 0.05)
+        net, _ = learned.train_budget_model(ix, Qt[:20_000], gt_t[:20_000], k, beta, grid, epochs=args.epochs)
+        scale = learned.calibrate_scale(ix, net, Qt[20_000:], gt_t[20_000:], k, beta, args.target_recall,
+                                        grid[0], 0.0035)
     if args.form == "onecall":
         def step():
             ix.query(Qd, k, alpha, beta, out=(ids, dists))
+    elif args.form == "learned_onecall":
+        def step():
+            suco.query_learned(ix, net, Qd, k, beta, scale, 0.0005, 0.0035, out=(ids, dists))
     else:
-        b = suco.Batcher(ix, 4096, k, beta)
-        if args.form == "learned":
-            from paper_2411_14754_amd import learned
-            Qt = torch.from_numpy(W.train_queries(30_000)).cuda()
-            gt_t = exact_topk(Xd, Qt, k)
-            grid = learned.alpha_grid(0.0005, 0.05)
-            net, _ = learned.train_budget_model(ix, Qt[:20_000], gt_t[:20_000], k, beta, grid, epochs=args.epochs)
-            scale = learned.calibrate_scale(ix, net, Qt[20_000:], gt_t[20_000:], k, beta, args.target_recall,
-                                            grid[0], 0.0035)
-            b.set_model(net, scale, grid[0], 0.0035)
+        together = args.form in ("multi", "learned_multi")
+        b = suco.Batcher(ix, nq if together else 4096, k, beta)
+        if net is not None:
+            b.set_model(net, scale, 0.0005, 0.0035)
 
         def step():
-            s0 = 0
-            for sz in sizes:
-                if args.form == "learned":
-                    b.query(Qd[s0:s0 + sz], out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
-                else:
-                    b.query(Qd[s0:s0 + sz], alpha=alpha, out=(ids[s0:s0 + sz], dists[s0:s0 + sz]))
-                s0 += sz
+            if together:
+                b.query_multi(parts, alpha=alpha, outs=outs)
+                return
+            for j, q in enumerate(parts):
+                b.query(q, alpha=alpha, out=outs[j])
     ms, per = timed_steps(step, args.steps, args.warmup)
     log(f"{args.form}: {ms / args.steps:.3f} ms per step of {nq} queries")
     print(json.dumps({"form": args.form, "ms_per_step": round(ms / args.steps, 4), "steps": args.steps,
-                      "batches": 1 if args.form == "onecall" else len(sizes)}))
+                      "launches_per_step": len(sizes) if args.form in ("batched", "learned") else 1}))
 
 
 def bench_build(args, log):
@@ -913,7 +923,8 @@ def main():
     ap.add_argument("--target-recall", type=float, default=0.951)
     ap.add_argument("--build-all", action="store_true", help="build: also the 10M-point Deep-like and lifted indexes")
     ap.add_argument("--nq", type=int, default=0, help="deep_like: queries in the stream (0: the workload's 100,000)")
-    ap.add_argument("--form", choices=("onecall", "batched", "learned"), default=None,
+    ap.add_argument("--form", choices=("onecall", "batched", "multi", "learned", "learned_multi", "learned_onecall"),
+                    default=None,
                     help="sift_like: time one form of the query path alone (for kernel traces)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy kernel of known size, used to "

@@ -45,46 +45,110 @@ __device__ __forceinline__ float bf16r(float x) {
 }
 
 // ------------------------------------------------------------- features --
-// The 2*n_s + 1 features of one query into out[] (global or LDS), by the
-// whole block: one (half, centre) pair per thread at a time, with the
-// activation step's arithmetic (FMA over the half's dimensions in order,
-// values loaded eight at a time), each half's minimum by an LDS atomic on the
-// bit patterns, then the query norm (lane-strided partial sums, a fixed
-// reduction order).  Ends with a barrier.
-__device__ __forceinline__ void query_features(const IndexView &ix, const float *qv, float *out, uint32_t *mins,
-                                               float *part) {
-    const int sk = ix.sk, nh = 2 * ix.ns;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    for (int g = tid; g < nh; g += blockDim.x) mins[g] = 0x7f800000u;
-    __syncthreads();
-    for (int t = tid; t < nh * sk; t += blockDim.x) {
-        const int g = t / sk, c = t - g * sk;
-        const HalfDims hd = ix.halves[g];
-        const float *qp = qv + hd.dim0;
-        const float *cp = ix.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
-        float s = 0.f;
-        for (int j0 = 0; j0 < hd.w; j0 += 8) {
-            // sixteen loads issued together (indices past the half repeat its last
-            // dimension, so none is conditional), then the FMAs in dimension order
-            float a8[8], c8[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int jj = j0 + u < hd.w ? j0 + u : hd.w - 1;
-                a8[u] = qp[jj];
-                c8[u] = cp[jj];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (j0 + u < hd.w) {
-                    const float t2 = a8[u] - c8[u];
-                    s = fmaf(t2, t2, s);
-                }
+// A block's copies for the feature computation, in dynamic LDS: the half
+// table, the centre table when it has at most kFeatCentMax values, and the
+// current query row when d <= kFeatQMax (otherwise those are read from HBM;
+// the values and the arithmetic are the same either way).
+constexpr int kFeatCentMax = 16384;   // values of the centre table (64 KB)
+constexpr int kFeatQMax = 4096;
+constexpr int kFeatHalfBytes = 256;    // 2*kMaxNs HalfDims, padded
+
+__host__ __device__ inline bool feat_cent_staged(int sk, int d) { return (int64_t)sk * d <= kFeatCentMax; }
+__host__ __device__ inline bool feat_q_staged(int d) { return d <= kFeatQMax; }
+inline size_t feat_lds_bytes(int sk, int d) {
+    return kFeatHalfBytes + (feat_cent_staged(sk, d) ? 4 * (size_t)sk * d : 0) + (feat_q_staged(d) ? 4 * (size_t)d : 0);
+}
+
+struct FeatSrc {
+    const HalfDims *hs;   // [2ns] in LDS
+    const float *cent;    // centre table: in LDS, half g's centre c, dimension j at sk*dim0 + j*sk + c;
+                          // in HBM (not staged) at sk*dim0 + c*w + j
+    int cstep;            // distance between a centre's consecutive dimensions (sk staged, 1 in HBM)
+    int cnext;            // distance between consecutive centres (1 staged, w in HBM; w is per half: 0 = use w)
+    float *qs;            // query row copy in LDS, or null
+};
+
+// Fill a block's copies (ends with a barrier).  The staged centre table is
+// transposed per half, so that the lanes reading one dimension of
+// consecutive centres read consecutive words.
+__device__ __forceinline__ FeatSrc feat_stage(const IndexView &ix, uint4 *dyn) {
+    const int tid = threadIdx.x, sk = ix.sk;
+    HalfDims *hs = reinterpret_cast<HalfDims *>(dyn);
+    float *cs = reinterpret_cast<float *>(reinterpret_cast<char *>(dyn) + kFeatHalfBytes);
+    const bool cst = feat_cent_staged(sk, ix.d);
+    for (int g = tid; g < 2 * ix.ns; g += blockDim.x) hs[g] = ix.halves[g];
+    if (cst) {
+        for (int g = 0; g < 2 * ix.ns; ++g) {
+            const HalfDims hd = ix.halves[g];
+            const int64_t base = (int64_t)sk * hd.dim0;
+            for (int o = tid; o < sk * hd.w; o += blockDim.x) {
+                const int c = o / hd.w, j = o - c * hd.w;
+                cs[base + (int64_t)j * sk + c] = ix.cent[base + o];
             }
         }
-        atomicMin(&mins[g], __float_as_uint(s));
     }
+    __syncthreads();
+    FeatSrc F;
+    F.hs = hs;
+    F.cent = cst ? cs : ix.cent;
+    F.cstep = cst ? sk : 1;
+    F.cnext = cst ? 1 : 0;
+    F.qs = feat_q_staged(ix.d) ? cs + (cst ? sk * ix.d : 0) : nullptr;
+    return F;
+}
+
+// The 2*n_s + 1 features of one query into out[] (global or LDS), by the
+// whole block of 128 threads: each half has a group of tph lanes (a power of
+// two, 128 / tph >= 2*n_s) that take its centres c = r, r + tph, ... with the
+// activation step's arithmetic (FMA over the half's dimensions in order,
+// values loaded eight at a time) and keep a running minimum; the group's
+// minimum comes from lane shuffles (a minimum is exact in any order); then
+// the query norm (lane-strided partial sums, a fixed reduction order).  Ends
+// with a barrier.
+__device__ __forceinline__ void query_features(const IndexView &ix, const FeatSrc &src, const float *qv, float *out,
+                                               uint32_t *mins, float *part) {
+    const int sk = ix.sk, nh = 2 * ix.ns;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    if (src.qs)
+        for (int j = tid; j < ix.d; j += blockDim.x) src.qs[j] = qv[j];
+    __syncthreads();
+    const float *q = src.qs ? src.qs : qv;
+    int tph = 64;
+    while (tph * nh > (int)blockDim.x) tph >>= 1;
+    const int g = tid / tph, r = tid - g * tph;
+    float m = __int_as_float(0x7f800000);
+    if (g < nh) {
+        const HalfDims hd = src.hs[g];
+        const float *qp = q + hd.dim0;
+        const int step = src.cstep, next = src.cnext ? src.cnext : hd.w;
+        for (int c = r; c < sk; c += tph) {
+            const float *cp = src.cent + (int64_t)sk * hd.dim0 + (int64_t)c * next;
+            float s = 0.f;
+            for (int j0 = 0; j0 < hd.w; j0 += 8) {
+                // sixteen loads issued together (indices past the half repeat its last
+                // dimension, so none is conditional), then the FMAs in dimension order
+                float a8[8], c8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int jj = j0 + u < hd.w ? j0 + u : hd.w - 1;
+                    a8[u] = qp[jj];
+                    c8[u] = cp[(int64_t)jj * step];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (j0 + u < hd.w) {
+                        const float t2 = a8[u] - c8[u];
+                        s = fmaf(t2, t2, s);
+                    }
+                }
+            }
+            m = fminf(m, s);
+        }
+    }
+    for (int o = 1; o < tph; o <<= 1) m = fminf(m, __shfl_xor(m, o, kWave));
+    if (g < nh && r == 0) mins[g] = __float_as_uint(m);
     float nsq = 0.f;
-    for (int j = tid; j < ix.d; j += blockDim.x) nsq = fmaf(qv[j], qv[j], nsq);
+    for (int j = tid; j < ix.d; j += blockDim.x) nsq = fmaf(q[j], q[j], nsq);
     for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, kWave);
     if (lane == 0) part[tid / kWave] = nsq;
     __syncthreads();
@@ -94,12 +158,15 @@ __device__ __forceinline__ void query_features(const IndexView &ix, const float 
 }
 
 __global__ __launch_bounds__(128) void k_features(FeatPass fp) {
+    extern __shared__ uint4 feat_dyn[];
     __shared__ uint32_t mins[2 * kMaxNs];   // bits of each half's smallest distance (non-negative floats)
     __shared__ float part[128 / kWave];
     const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
+    if ((int)blockIdx.x >= nq) return;
     const int nf = 2 * fp.ix.ns + 1;
+    const FeatSrc src = feat_stage(fp.ix, feat_dyn);
     for (int q = blockIdx.x; q < nq; q += gridDim.x)
-        query_features(fp.ix, fp.Q + (int64_t)q * fp.ix.d, fp.F + (int64_t)q * nf, mins, part);
+        query_features(fp.ix, src, fp.Q + (int64_t)q * fp.ix.d, fp.F + (int64_t)q * nf, mins, part);
 }
 
 // ---------------------------------------------------------- inference --
@@ -170,6 +237,7 @@ __global__ __launch_bounds__(kH) void k_mlp_infer(InferPass ip) {
 // arithmetic as k_features followed by k_mlp_infer.
 __global__ __launch_bounds__(kH) void k_learned_alpha(FeatPass fp, InferPass ip) {
     static_assert(kH == 128, "the feature computation is written for blocks of 128 threads");
+    extern __shared__ uint4 feat_dyn[];
     __shared__ uint32_t mins[2 * kMaxNs];
     __shared__ float part[kH / kWave];
     __shared__ float fq[2 * kMaxNs + 1];
@@ -180,8 +248,9 @@ __global__ __launch_bounds__(kH) void k_learned_alpha(FeatPass fp, InferPass ip)
     if ((int)blockIdx.x >= nq) return;
     InferRegs R;
     infer_regs(ip.w, R);
+    const FeatSrc src = feat_stage(fp.ix, feat_dyn);
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-        query_features(fp.ix, fp.Q + (int64_t)q * fp.ix.d, fq, mins, part);
+        query_features(fp.ix, src, fp.Q + (int64_t)q * fp.ix.d, fq, mins, part);
         infer_row(ip, R, fq, q, x, h, red);
     }
 }
@@ -403,19 +472,21 @@ int refresh_bf16(suco_mlp *p, hipStream_t st) {
 }  // namespace
 
 namespace suco {
-Launch plan_features(int nq_cap) {
+Launch plan_features(const IndexView &ix, int nq_cap) {
     Launch L;
     L.func = reinterpret_cast<const void *>(&k_features);
-    L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 65536)));
+    L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 2048)));
     L.block = dim3(128);
+    L.lds = feat_lds_bytes(ix.sk, ix.d);
     return L;
 }
 
-Launch plan_learned_alpha(int nq_cap) {
+Launch plan_learned_alpha(const IndexView &ix, int nq_cap) {
     Launch L;
     L.func = reinterpret_cast<const void *>(&k_learned_alpha);
     L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 2048)));
     L.block = dim3(kH);
+    L.lds = feat_lds_bytes(ix.sk, ix.d);
     return L;
 }
 
@@ -598,7 +669,7 @@ int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float 
         const int cn = (int)std::min<int64_t>(65536, nq - q0);
         FeatPass fp{};
         fp.ix = ix->view(); fp.Q = Q + q0 * ix->d; fp.nq = cn; fp.F = F + q0 * (2 * ix->ns + 1);
-        HIPCHECK(launch(plan_features(cn), &fp, (hipStream_t)stream));
+        HIPCHECK(launch(plan_features(fp.ix, cn), &fp, (hipStream_t)stream));
     }
     return SUCO_OK;
 }
@@ -669,7 +740,7 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
             InferPass ip{};
             ip.w = p->view(p->wb); ip.m = cn; ip.scale = scale; ip.amin = alpha_min; ip.amax = alpha_max;
             ip.alpha = S.alpha + q0;
-            const Launch L = plan_learned_alpha(cn);
+            const Launch L = plan_learned_alpha(fp.ix, cn);
             void *args[] = {&fp, &ip};
             HIPCHECK(hipLaunchKernel(L.func, L.grid, L.block, args, L.lds, st));
         }

@@ -976,6 +976,7 @@ struct SparseLds {
     uint32_t H[kSpMaxNs + 2];        // H[s]: points of score s >= 2
     uint32_t sink[kWave];            // targets of the atomics of empty slots, one word per lane
     uint32_t red[2 * kSpWaves + 2];
+    uint32_t zfree[kSpWaves];        // unmarked ids below B per bucket (fewer than B points collide)
     uint32_t cpre[kSpMaxNs + 1];     // activated cells of the subspaces before i
     uint32_t nh;                     // points in the list of scores >= 2 (may pass its capacity)
     uint32_t out;                    // candidates written
@@ -1311,6 +1312,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         const uint32_t B = (uint32_t)a.B;
         int T = 0;
         uint32_t GT1 = 0;                    // G[T + 1]
+        uint32_t R0 = 0;                     // points of score 0 to take (fewer than B collide)
         {
             uint32_t g = 0;
             for (int t = ns; t >= 2; --t) {
@@ -1322,15 +1324,17 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
                 for (int b = b0t; b < b1t; ++b) e += bx[b];
                 e = block_sum<kSpThreads>(e, S.red);
                 if (g + e >= B) { T = 1; GT1 = g; }
+                else { T = 1; GT1 = g; R0 = B - g - e; }    // every colliding point, then R0 of score 0
             }
         }
         const uint32_t nhl = S.nh;
-        if (T == 0 || nhl > hcap) {
+        const uint32_t nb0 = (B + (uint32_t)kSpBucket - 1u) >> kSpShift;   // buckets below B
+        if (nhl > hcap || (R0 > 0u && nb0 > (uint32_t)kSpWaves)) {
             if (tid == 0) leave_to_tiled(a, ql);
             __syncthreads();
             continue;
         }
-        const uint32_t R = B - GT1;
+        const uint32_t R = B - GT1 - R0;
         // level-T points per bucket: the score-1 counts, or counted over the list
         if (T > 1) {
             for (int b = b0t; b < b1t; ++b) bx[b] = 0u;
@@ -1403,6 +1407,51 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
                     const uint32_t j = j0 + (uint32_t)lane;
                     const uint32_t lo = f[j < n1 ? j : 0u];
                     sp_emit(j < n1 && lo < lim, id0 | lo, cq, B, &S.out);
+                }
+            }
+        }
+        if (R0 > 0u) {
+            // ---- fewer than B points collide: the R0 lowest ids of score 0 as well.
+            // They lie below B; the colliding ids below B are marked in bitmaps, bucket
+            // b's in wave b's window (clear), and wave b takes its bucket's share of
+            // the unmarked ids in id order
+            for (uint32_t j = (uint32_t)tid; j < nhl; j += kSpThreads) {
+                const uint32_t id = hl[j] >> 4;
+                if (id < B) atomicOr(&win_all[(id >> kSpShift) * kSpWords + ((id & (kSpBucket - 1)) >> 5)], 1u << (id & 31u));
+            }
+            if ((uint32_t)w < nb0) {
+                const uint16_t *f = raw + boff[w];
+                const uint32_t n1 = bx[w], id0 = (uint32_t)w << kSpShift;
+                for (uint32_t j = (uint32_t)lane; j < n1; j += kWave) {
+                    const uint32_t lo = f[j];
+                    if (id0 + lo < B) atomicOr(&win[lo >> 5], 1u << (lo & 31u));
+                }
+            }
+            __syncthreads();
+            uint64_t fr = 0;                 // this lane's unmarked ids below B: 64 * lane .. + 63 of the bucket
+            const uint32_t idl = ((uint32_t)w << kSpShift) + 64u * (uint32_t)lane;
+            if ((uint32_t)w < nb0) {
+                const uint64_t mk = ((uint64_t)win[2 * lane + 1] << 32) | win[2 * lane];
+                const uint32_t nv = B > idl ? (B - idl < 64u ? B - idl : 64u) : 0u;
+                fr = ~mk & (nv == 64u ? ~0ull : ((1ull << nv) - 1ull));
+                win[2 * lane] = 0u;
+                win[2 * lane + 1] = 0u;
+                const uint32_t z = wave_sum((uint32_t)__popcll(fr));
+                if (lane == 0) S.zfree[w] = z;
+            }
+            __syncthreads();
+            if ((uint32_t)w < nb0) {
+                uint32_t pre = 0;
+                for (int v = 0; v < w; ++v) pre += S.zfree[v];
+                const uint32_t take = pre >= R0 ? 0u : (R0 - pre < S.zfree[w] ? R0 - pre : S.zfree[w]);
+                if (take > 0u) {
+                    const uint32_t c = (uint32_t)__popcll(fr);
+                    uint32_t r = wave_incl_scan(c) - c;   // rank of this lane's first unmarked id
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&S.out, take);
+                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                    for (; fr != 0ull && r < take; ++r, fr &= fr - 1ull)
+                        if (base + r < B) cq[base + r] = idl + (uint32_t)__builtin_ctzll(fr);
                 }
             }
         }

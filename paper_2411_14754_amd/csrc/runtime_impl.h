@@ -291,6 +291,5 @@ MlpView mlp_infer_view(suco_mlp *p);
 int mlp_n_in(const suco_mlp *p);
 int mlp_prepare(suco_mlp *p, hipStream_t st);
 bool mlp_valid(const suco_mlp *p);
-Launch plan_features(int nq_cap);
 Launch plan_mlp_infer(int m_cap);
 }  // namespace suco

@@ -178,9 +178,9 @@ struct InferPass {
     float *alpha;             // [m] or null
     double *alpha64;          // [m] or null
 };
-Launch plan_features(int nq_cap);
+Launch plan_features(const IndexView &ix, int nq_cap);
 Launch plan_mlp_infer(int m_cap);
-Launch plan_learned_alpha(int nq_cap);   // features and inference fused (args: FeatPass, InferPass)
+Launch plan_learned_alpha(const IndexView &ix, int nq_cap);   // features and inference fused (args: FeatPass, InferPass)
 
 // BF16 split precision (bf16.hip).
 struct CentreBf16Pass {

@@ -205,13 +205,15 @@ def test_sqrt_k_above_64(suco, alpha):
 
 
 @pytest.mark.parametrize("alpha,beta", [(0.0005, 0.005), (0.003, 0.005), (0.01, 0.005), (0.05, 0.002),
-                                        (0.3, 0.01), (0.0001, 0.2)])
+                                        (0.3, 0.01), (0.0001, 0.2), (0.0002, 0.4)])
 def test_sparse_step_equals_tiled_step(suco, alpha, beta):
     """The sparse collision step (SC-scores per bucket of 4096 ids, one or
     several LDS rounds) against the tiled step on the same index: candidates,
     SC-scores and top-k bitwise.  The budgets span one round, several rounds,
-    queries left to the tiled step (too many points) and T = 0 (fewer than B
-    colliding points), all in one batch with per-query alphas around alpha."""
+    queries left to the tiled step (too many points), T = 0 (fewer than B
+    colliding points: the lowest score-0 ids fill the candidates, in the
+    sparse step when B <= 65,536, else in the tiled one), all in one batch
+    with per-query alphas around alpha."""
     W = synth.Workload(2)
     X = W.data(200_000)
     Q = W.queries(300)
