@@ -413,7 +413,8 @@ SUCO_API int suco_mlp_free(suco_mlp *m);
 SUCO_API int suco_query_features(const suco_index *ix, const float *Q, int64_t nq, float *F, void *stream);
 /* k-ANN query with the network's per-query alpha: features, BF16 inference,
  * then exactly suco_query_alpha with those alphas; alpha_used (device [nq],
- * may be NULL) receives them. */
+ * may be NULL) receives them.  The alphas equal, bit for bit, those of
+ * suco_query_features followed by suco_mlp_predict with the same arguments. */
 SUCO_API int suco_query_learned(const suco_index *ix, suco_mlp *m, const float *Q, int64_t nq, int32_t k,
                                 double beta, float scale, float alpha_min, float alpha_max, int32_t *ids,
                                 float *dists, float *alpha_used, void *stream);

@@ -245,7 +245,7 @@ hipError_t build_graph(suco_batcher *b, Bucket *bk, const Tuned &t) {
         bk->ip.amax = b->amax;
         bk->ip.alpha64 = b->alphas;
         // features and inference in one node
-        const Launch La = plan_learned_alpha(bk->fp.ix, bk->size);
+        const Launch La = plan_learned_alpha(bk->fp.ix, half_wmax(ix), bk->size);
         void *aa[] = {&bk->fp, &bk->ip};
         if ((e = add_node(bk->graph, &prev, La.func, La.grid, La.block, La.lds, aa)) != hipSuccess) return e;
     }

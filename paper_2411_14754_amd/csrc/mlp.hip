@@ -61,39 +61,36 @@ inline size_t feat_lds_bytes(int sk, int d) {
 
 struct FeatSrc {
     const HalfDims *hs;   // [2ns] in LDS
-    const float *cent;    // centre table: in LDS, half g's centre c, dimension j at sk*dim0 + j*sk + c;
-                          // in HBM (not staged) at sk*dim0 + c*w + j
-    int cstep;            // distance between a centre's consecutive dimensions (sk staged, 1 in HBM)
-    int cnext;            // distance between consecutive centres (1 staged, w in HBM; w is per half: 0 = use w)
+    const float *cent;    // centre table (LDS or HBM): half g's centre c at sk*dim0 + c*w
     float *qs;            // query row copy in LDS, or null
 };
 
-// Fill a block's copies (ends with a barrier).  The staged centre table is
-// transposed per half, so that the lanes reading one dimension of
-// consecutive centres read consecutive words.
+// Fill a block's copies (ends with a barrier), sixteen loads in flight per thread.
 __device__ __forceinline__ FeatSrc feat_stage(const IndexView &ix, uint4 *dyn) {
     const int tid = threadIdx.x, sk = ix.sk;
     HalfDims *hs = reinterpret_cast<HalfDims *>(dyn);
     float *cs = reinterpret_cast<float *>(reinterpret_cast<char *>(dyn) + kFeatHalfBytes);
     const bool cst = feat_cent_staged(sk, ix.d);
     for (int g = tid; g < 2 * ix.ns; g += blockDim.x) hs[g] = ix.halves[g];
-    if (cst) {
-        for (int g = 0; g < 2 * ix.ns; ++g) {
-            const HalfDims hd = ix.halves[g];
-            const int64_t base = (int64_t)sk * hd.dim0;
-            for (int o = tid; o < sk * hd.w; o += blockDim.x) {
-                const int c = o / hd.w, j = o - c * hd.w;
-                cs[base + (int64_t)j * sk + c] = ix.cent[base + o];
-            }
+    const int nc = cst ? sk * ix.d : 0;
+    for (int i0 = tid; i0 < nc; i0 += 16 * blockDim.x) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            v[u] = ix.cent[i < nc ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < nc) cs[i] = v[u];
         }
     }
     __syncthreads();
     FeatSrc F;
     F.hs = hs;
     F.cent = cst ? cs : ix.cent;
-    F.cstep = cst ? sk : 1;
-    F.cnext = cst ? 1 : 0;
-    F.qs = feat_q_staged(ix.d) ? cs + (cst ? sk * ix.d : 0) : nullptr;
+    F.qs = feat_q_staged(ix.d) ? cs + nc : nullptr;
     return F;
 }
 
@@ -120,9 +117,8 @@ __device__ __forceinline__ void query_features(const IndexView &ix, const FeatSr
     if (g < nh) {
         const HalfDims hd = src.hs[g];
         const float *qp = q + hd.dim0;
-        const int step = src.cstep, next = src.cnext ? src.cnext : hd.w;
         for (int c = r; c < sk; c += tph) {
-            const float *cp = src.cent + (int64_t)sk * hd.dim0 + (int64_t)c * next;
+            const float *cp = src.cent + (int64_t)sk * hd.dim0 + (int64_t)c * hd.w;
             float s = 0.f;
             for (int j0 = 0; j0 < hd.w; j0 += 8) {
                 // sixteen loads issued together (indices past the half repeat its last
@@ -132,7 +128,7 @@ __device__ __forceinline__ void query_features(const IndexView &ix, const FeatSr
                 for (int u = 0; u < 8; ++u) {
                     const int jj = j0 + u < hd.w ? j0 + u : hd.w - 1;
                     a8[u] = qp[jj];
-                    c8[u] = cp[(int64_t)jj * step];
+                    c8[u] = cp[jj];
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -252,6 +248,193 @@ __global__ __launch_bounds__(kH) void k_learned_alpha(FeatPass fp, InferPass ip)
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
         query_features(fp.ix, src, fp.Q + (int64_t)q * fp.ix.d, fq, mins, part);
         infer_row(ip, R, fq, q, x, h, red);
+    }
+}
+
+// The same computation sixteen query rows at a time (the query path's form
+// when the centre table is staged, the widest half has at most 16 dimensions
+// and the tile's rows fit in LDS): blocks of 256 threads; a thread takes one
+// (row, half) pair for the features, keeping the half of the query in
+// registers, and hidden unit j = t mod 128 of eight rows for the network.
+// Every value is computed with the arithmetic and in the order of
+// k_features and k_mlp_infer (FMA chains in index order, the norm's and the
+// output's partial sums over the same lanes and reduced with the same
+// shuffles), so the alphas equal theirs bit for bit; the latencies of a row
+// (loads, barriers, the reductions) are paid once per sixteen rows.
+constexpr int kRT = 16;            // rows per tile
+constexpr int kRTHalfW = 16;       // widest half kept in registers
+constexpr int kRTQMax = 16384;     // floats of a tile's staged rows (padded to d + 1)
+
+__host__ __device__ inline bool learned_tiles_ok(int sk, int d, int ns, int wmax) {
+    return feat_cent_staged(sk, d) && kRT * (d + 1) <= kRTQMax && wmax <= kRTHalfW && 2 * ns + 1 <= 32;
+}
+inline size_t learned_tile_lds(int sk, int d) {
+    return kFeatHalfBytes + 4 * (size_t)sk * d + 4 * (size_t)kRT * (d + 1) + 2 * (size_t)kH * kH;
+}
+
+// The smallest squared distance from a query half qp (w <= HW values) to the
+// half's sk centres (centre c at cb + c*w), the activation step's arithmetic.
+template <int HW>
+__device__ __forceinline__ float nearest_centre(const float *qp, const float *cb, const int sk, const int w) {
+    float qr[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) qr[u] = qp[u < w ? u : w - 1];
+    float m = __int_as_float(0x7f800000);
+#pragma unroll 2
+    for (int c = 0; c < sk; ++c) {
+        const float *cp = cb + c * w;
+        float cv[HW];
+#pragma unroll
+        for (int u = 0; u < HW; ++u) cv[u] = cp[u < w ? u : w - 1];
+        float s = 0.f;
+#pragma unroll
+        for (int u = 0; u < HW; ++u) {
+            if (u < w) {
+                const float t2 = qr[u] - cv[u];
+                s = fmaf(t2, t2, s);
+            }
+        }
+        m = fminf(m, s);
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_learned_alpha_tiles(FeatPass fp, InferPass ip) {
+    static_assert(kH == 128 && kRT == 16, "the tile kernel is written for 128 hidden units and 16 rows");
+    extern __shared__ uint4 feat_dyn[];
+    __shared__ float fq[kRT][33];      // raw features
+    __shared__ float xs[kRT][33];      // standardised, rounded
+    __shared__ __align__(16) float h1[kRT][kH];
+    __shared__ float red[4][kRT];
+    __shared__ float mus[32], sgs[32];
+    const IndexView &ix = fp.ix;
+    const MlpView &W = ip.w;
+    const int nq = fp.nq_dev ? *fp.nq_dev : fp.nq;
+    const int ntiles = (nq + kRT - 1) / kRT;
+    if ((int)blockIdx.x >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int j = tid & (kH - 1), rg = tid / kH;
+    const int d = ix.d, sk = ix.sk, nh = 2 * ix.ns, nin = W.n_in, ds = d + 1;
+    const float b1 = W.b1[j], b2 = W.b2[j], w3 = W.W3[j];
+    // unit j's first-layer weights (n_in <= 32), all loads in flight at once
+    float w1r[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) w1r[i] = W.W1[(i < nin ? i : nin - 1) * kH + j];   // transposed copy: W1[j][i]
+    for (int i = tid; i < nin; i += blockDim.x) { mus[i] = W.mu[i]; sgs[i] = W.sigma[i]; }
+    float *qt = reinterpret_cast<float *>(reinterpret_cast<char *>(feat_dyn) + kFeatHalfBytes) + (size_t)sk * d;
+    // the second layer in LDS as BF16 bits, unit j's weight of input i at i*kH + j
+    // (the rounded copy's values have zero low halves, so this is exact)
+    uint16_t *w2s = reinterpret_cast<uint16_t *>(qt + kRT * ds);
+    for (int e0 = tid; e0 < kH * kH; e0 += 16 * blockDim.x) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = W.W2[e0 + u * (int)blockDim.x];       // kH*kH is a multiple of 16*256
+#pragma unroll
+        for (int u = 0; u < 16; ++u) w2s[e0 + u * (int)blockDim.x] = (uint16_t)(__float_as_uint(v[u]) >> 16);
+    }
+    const FeatSrc src = feat_stage(ix, feat_dyn);          // staged centres (checked on the host); ends with a barrier
+    int wmax = 0;
+    for (int g = 0; g < nh; ++g) wmax = src.hs[g].w > wmax ? src.hs[g].w : wmax;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int r0 = tile * kRT, nr = nq - r0 < kRT ? nq - r0 : kRT;
+        // the tile's rows (rows past the last query repeat it), sixteen loads in flight
+        for (int e0 = tid; e0 < kRT * d; e0 += 16 * blockDim.x) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * (int)blockDim.x, ee = e < kRT * d ? e : 0;
+                const int r = ee / d, c = ee - r * d;
+                v[u] = fp.Q[(int64_t)(r0 + (r < nr ? r : nr - 1)) * d + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * (int)blockDim.x;
+                if (e < kRT * d) {
+                    const int r = e / d, c = e - r * d;
+                    qt[r * ds + c] = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        // each half's nearest centre: pair p = (row p mod 16, half p / 16)
+        for (int p = tid; p < kRT * nh; p += blockDim.x) {
+            const int r = p & (kRT - 1), g = p / kRT;
+            const HalfDims hd = src.hs[g];
+            const float *qp = qt + r * ds + hd.dim0;
+            const float *cb = src.cent + (int64_t)sk * hd.dim0;
+            fq[r][g] = __fsqrt_rn(wmax <= 8 ? nearest_centre<8>(qp, cb, sk, hd.w) : nearest_centre<kRTHalfW>(qp, cb, sk, hd.w));
+        }
+        // the norm of row r by wave r mod 4: the partial sums of threads t and
+        // 64 + t of a 128-thread block, each reduced over its wave, then added
+        for (int r = wv; r < kRT; r += 4) {
+            const float *q = qt + r * ds;
+            float plo = 0.f, phi = 0.f;
+            for (int jj = lane; jj < d; jj += 128) plo = fmaf(q[jj], q[jj], plo);
+            for (int jj = 64 + lane; jj < d; jj += 128) phi = fmaf(q[jj], q[jj], phi);
+            for (int o = 32; o > 0; o >>= 1) {
+                plo += __shfl_xor(plo, o, kWave);
+                phi += __shfl_xor(phi, o, kWave);
+            }
+            if (lane == 0) fq[r][nh] = __fsqrt_rn(plo + phi);
+        }
+        __syncthreads();
+        for (int e = tid; e < kRT * nin; e += blockDim.x) {
+            const int r = e / nin, i = e - r * nin;
+            xs[r][i] = bf16r((fq[r][i] - mus[i]) / sgs[i]);
+        }
+        __syncthreads();
+        // first layer: unit j of rows 8rg .. 8rg + 7
+        float z[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) z[u] = b1;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            if (i < nin) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) z[u] = fmaf(w1r[i], xs[8 * rg + u][i], z[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h1[8 * rg + u][j] = bf16r(gelu_f(z[u]));
+        __syncthreads();
+        // second layer and the output's partial sums (waves 2rg, 2rg + 1 hold units 0..63, 64..127)
+        float z2[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) z2[u] = b2;
+#pragma unroll 2
+        for (int i = 0; i < kH; i += 4) {
+            float wi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wi[v] = __uint_as_float((uint32_t)w2s[(i + v) * kH + j] << 16);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float4 hv = *reinterpret_cast<const float4 *>(&h1[8 * rg + u][i]);
+                z2[u] = fmaf(wi[0], hv.x, z2[u]);
+                z2[u] = fmaf(wi[1], hv.y, z2[u]);
+                z2[u] = fmaf(wi[2], hv.z, z2[u]);
+                z2[u] = fmaf(wi[3], hv.w, z2[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            float part = w3 * bf16r(gelu_f(z2[u]));
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+            if (lane == 0) red[wv][8 * rg + u] = part;
+        }
+        __syncthreads();
+        float yv = 0.f;
+        if (tid < nr) yv = W.b3[0] + red[2 * (tid / 8)][tid] + red[2 * (tid / 8) + 1][tid];
+        // the tile's LDS is free once red[] is read; the stores go out after the
+        // barrier, so that it does not wait for them
+        __syncthreads();
+        if (tid < nr) {
+            if (ip.y) ip.y[r0 + tid] = yv;
+            float a = ip.scale * expf(yv);
+            // a NaN prediction takes the largest budget, like +inf
+            a = a <= ip.amax ? (a >= ip.amin ? a : ip.amin) : ip.amax;
+            if (ip.alpha) ip.alpha[r0 + tid] = a;
+            if (ip.alpha64) ip.alpha64[r0 + tid] = (double)a;
+        }
     }
 }
 
@@ -481,8 +664,15 @@ Launch plan_features(const IndexView &ix, int nq_cap) {
     return L;
 }
 
-Launch plan_learned_alpha(const IndexView &ix, int nq_cap) {
+Launch plan_learned_alpha(const IndexView &ix, int wmax, int nq_cap) {
     Launch L;
+    if (learned_tiles_ok(ix.sk, ix.d, ix.ns, wmax)) {
+        L.func = reinterpret_cast<const void *>(&k_learned_alpha_tiles);
+        L.grid = dim3((unsigned)std::max(1, std::min((nq_cap + kRT - 1) / kRT, 2048)));
+        L.block = dim3(256);
+        L.lds = learned_tile_lds(ix.sk, ix.d);
+        return L;
+    }
     L.func = reinterpret_cast<const void *>(&k_learned_alpha);
     L.grid = dim3((unsigned)std::max(1, std::min(nq_cap, 2048)));
     L.block = dim3(kH);
@@ -740,7 +930,7 @@ extern "C" int suco_query_learned(const suco_index *ix, suco_mlp *p, const float
             InferPass ip{};
             ip.w = p->view(p->wb); ip.m = cn; ip.scale = scale; ip.amin = alpha_min; ip.amax = alpha_max;
             ip.alpha = S.alpha + q0;
-            const Launch L = plan_learned_alpha(fp.ix, cn);
+            const Launch L = plan_learned_alpha(fp.ix, half_wmax(ix), cn);
             void *args[] = {&fp, &ip};
             HIPCHECK(hipLaunchKernel(L.func, L.grid, L.block, args, L.lds, st));
         }

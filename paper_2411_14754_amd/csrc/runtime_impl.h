@@ -179,6 +179,12 @@ namespace suco {
 
 
 inline bool index_ok(const suco_index *ix) { return ix != nullptr && ix->magic == kMagic; }
+// The widest half of the index's subspaces.
+inline int half_wmax(const suco_index *ix) {
+    int w = 0;
+    for (const auto &h : ix->halves_h) w = h.w > w ? h.w : w;
+    return w;
+}
 
 enum Stage {
     kActivate = 0, kCollide, kSelect, kRerank, kMerge, kCentresBf16, kRerankBf16, kSurvivors, kOrder, kCollideSparse,

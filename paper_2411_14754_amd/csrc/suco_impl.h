@@ -180,7 +180,8 @@ struct InferPass {
 };
 Launch plan_features(const IndexView &ix, int nq_cap);
 Launch plan_mlp_infer(int m_cap);
-Launch plan_learned_alpha(const IndexView &ix, int nq_cap);   // features and inference fused (args: FeatPass, InferPass)
+Launch plan_learned_alpha(const IndexView &ix, int wmax, int nq_cap);   // features and inference fused (args: FeatPass,
+                                                                        // InferPass); wmax: widest half
 
 // BF16 split precision (bf16.hip).
 struct CentreBf16Pass {

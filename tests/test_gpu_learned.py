@@ -155,6 +155,29 @@ def test_features_match_oracle(suco):
     ix.free()
 
 
+@pytest.mark.parametrize("d,ns,sk,nq", [(128, 8, 16, 300), (96, 8, 20, 33), (256, 4, 12, 50), (28, 3, 9, 16)])
+def test_fused_alphas_equal_features_then_predict(suco, d, ns, sk, nq):
+    """The query path's fused kernel (sixteen rows at a time when the widest
+    half has at most 16 dimensions, else row by row) gives exactly the alphas
+    of suco_query_features followed by suco_mlp_predict."""
+    rng = np.random.default_rng(d + nq)
+    X = rng.integers(0, 256, size=(3000, d)).astype(np.float32)
+    Q = rng.integers(0, 256, size=(nq, d)).astype(np.float32)
+    _, c32, asg, _ = oracle.build_index(X, ns, sk, iters=3)
+    ix = suco.Index.from_index(torch.from_numpy(X).cuda(), ns, sk, c32, asg)
+    Qd = torch.from_numpy(Q).cuda()
+    net = suco.MLP(2 * ns + 1, seed=5)
+    F = suco.query_features(ix, Qd)
+    net.set_norm(F.mean(dim=0).cpu().numpy(), (F.std(dim=0) + 1.0).cpu().numpy())
+    print(f"case: fused alphas d={d} ns={ns} sk={sk} nq={nq}", flush=True)
+    _, a_ref = net.predict(F, 0.02, 0.001, 0.5)
+    _, _, au = suco.query_learned(ix, net, Qd, 10, 0.01, 0.02, 0.001, 0.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(au.cpu().numpy().view(np.uint32), a_ref.cpu().numpy().view(np.uint32))
+    net.free()
+    ix.free()
+
+
 def test_learned_query_equals_plain_with_its_alphas(suco):
     """suco_query_learned = features + inference + the per-query-alpha path, exactly;
     and the batcher with the model attached gives the same results; and the oracle
