@@ -1075,7 +1075,10 @@ def main():
         avg_ms = tms / cnt
         ent = {"avg_ms": round(avg_ms, 5), "launches": cnt,
                "share": round(tms / max(1e-9, sum(v[0] for v in stage.values())), 4)}
-        if sname in step_bytes:
+        if sname in ("collide", "select") and stage.get("collide_sparse", (0, 0))[1]:
+            # with the sparse step these take only the few queries it leaves: no per-query byte figure
+            ent["note"] = "tiled step: only the queries the sparse step leaves"
+        elif sname in step_bytes:
             # launches cover `chunk` queries except a ragged last one: use the per-step total
             bytes_launch = step_bytes[sname] * nq / max(1, cnt // args.steps)
             ent["alg_bytes_per_launch"] = bytes_launch
@@ -1085,7 +1088,7 @@ def main():
                 ent["survey_bytes_per_launch"] = sb_launch
                 ent["survey_gbs"] = round(sb_launch / (avg_ms * 1e-3) / 1e9, 1)
         per_kernel[sname] = ent
-    dom = max((t for t in step_bytes if stage[t][1]), key=lambda t: stage[t][0])
+    dom = max((t for t in step_bytes if stage[t][1] and "gbs" in per_kernel.get(t, {})), key=lambda t: stage[t][0])
     kern_name = {"collide_sparse": "k_collide_sparse", "collide": "k_collide", "select": "k_select",
                  "rerank": "k_rerank"}[dom]
     achieved = per_kernel[dom]["gbs"]
