@@ -699,6 +699,77 @@ def bench_sift_k50(args, log):
     ix.free()
 
 
+def bench_learned_ceiling(args, log):
+    """What a per-query alpha can gain on the SIFT-like workload at best: each
+    evaluation query gets alphas read off its own ground truth (a perfect
+    predictor), and the path is timed in one call with those alphas.  Per
+    query, recall@10 over the alpha grid; the rules: `tau` (the smallest grid
+    alpha at which the query reaches tau times the recall it has at the largest
+    grid alpha) and `greedy` (all queries at the smallest alpha, then raised by
+    recall gained per alpha spent until the mean recall reaches 0.95).  Printed
+    next to plain SuCo at a few alphas."""
+    import torch
+    import numpy as np
+    import paper_2411_14754_amd as suco
+    from paper_2411_14754_amd import learned
+    import synth
+    W = synth.Workload(2)
+    sp = W.spec
+    n, d, ns, sk, nq, k, beta = sp["n"], sp["d"], sp["n_s"], sp["sqrt_k"], sp["nq"], sp["k"], sp["beta"]
+    X, Q = W.data(), W.queries()
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    ix = suco.Index.build(Xd, ns, sk, iters=25, seed=1)
+    gt = exact_topk(Xd, Qd, k)
+    grid = learned.alpha_grid(0.0005, 0.05)
+    R = torch.stack([learned.per_query_recall(ix.query(Qd, k, a, beta)[0], gt) for a in grid], 1)
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dists = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+
+    def timed(alpha=None, aq=None):
+        if aq is None:
+            fn = lambda: ix.query(Qd, k, alpha, beta, out=(ids, dists))
+        else:
+            fn = lambda: ix.query_alpha(Qd, k, aq, beta, out=(ids, dists))
+        ms, _ = timed_steps(fn, args.steps, args.warmup)
+        return ms / args.steps, recall_at(ids, gt)
+
+    rows = []
+    for a in (0.002, 0.0025, 0.003, 0.005, 0.0075, 0.01, 0.05):
+        ms, r = timed(alpha=a)
+        rows.append({"rule": "plain", "alpha": a, "ms": round(ms, 4), "recall": round(r, 5), "qps": round(nq / ms * 1e3, 1)})
+        log(f"plain alpha={a}: {ms:.3f} ms, recall {r:.4f}")
+    G = torch.tensor(grid, device="cuda", dtype=torch.float32)
+    best = R[:, -1]
+    for tau in (0.8, 0.9, 1.0):
+        first = torch.argmax((R >= (best * tau - 1e-6)[:, None]).int(), dim=1)
+        aq = G[first].contiguous()
+        ms, r = timed(aq=aq)
+        rows.append({"rule": f"tau={tau}", "mean_alpha": round(float(aq.mean()), 6), "ms": round(ms, 4),
+                     "recall": round(r, 5), "qps": round(nq / ms * 1e3, 1)})
+        log(f"perfect labels tau={tau}: mean alpha {float(aq.mean()):.5f}, {ms:.3f} ms, recall {r:.4f}")
+    Rc, Gc = R.cpu().numpy().astype(np.float64), np.array(grid)
+    gain = (Rc[:, 1:] - Rc[:, :1]) / (Gc[1:] - Gc[0])[None, :]
+    jbest = np.argmax(gain, axis=1) + 1
+    vbest = gain[np.arange(nq), jbest - 1]
+    aq = np.full(nq, grid[0], np.float32)
+    cur, target = float(Rc[:, 0].sum()), TARGET_RECALL * nq
+    for q in np.argsort(-vbest):
+        if cur >= target or vbest[q] <= 0:
+            break
+        aq[q] = grid[jbest[q]]
+        cur += Rc[q, jbest[q]] - Rc[q, 0]
+    ms, r = timed(aq=torch.from_numpy(aq).cuda())
+    rows.append({"rule": "greedy", "mean_alpha": round(float(aq.mean()), 6), "ms": round(ms, 4), "recall": round(r, 5),
+                 "qps": round(nq / ms * 1e3, 1)})
+    log(f"perfect labels greedy: mean alpha {float(aq.mean()):.5f}, {ms:.3f} ms, recall {r:.4f}")
+    print(json.dumps({"metric": "per-query alpha from the queries' own ground truth vs plain SuCo, n=1M d=128",
+                      "value": None, "unit": "see rows", "n_gpus": 1, "steps": args.steps, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": f"sift_like n={n} d={d} int 0..255, N_s={ns}, "
+                                                                   f"sqrtK={sk}, nq={nq}, k={k}, beta={beta}",
+                                                       "rows": rows}}))
+    ix.free()
+
+
 def bench_form(args, log):
     """One form of the SIFT-like query path alone, for kernel traces of it:
     `onecall` (10,000 queries in one plain call at alpha = 0.003), `batched`
@@ -900,7 +971,8 @@ def bench_sclinear(args, log):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("sift_like", "sift_k50", "gist_like", "deep_like", "lifted256", "sclinear", "activation", "build"), default="sift_like",
+    ap.add_argument("--workload", choices=("sift_like", "sift_k50", "gist_like", "deep_like", "lifted256", "sclinear",
+                                           "activation", "build", "learned_ceiling"), default="sift_like",
                     help="sift_like: the headline (plain and learned+batched SuCo); gist_like: BF16 split "
                          "precision; deep_like: batched stream at n=10M; lifted256: learned budget at n=10M; "
                          "sclinear: SuCo against SC-Linear on the SIFT-like data; activation: Dynamic Activation "
@@ -968,6 +1040,9 @@ def main():
         return
     if args.workload == "sift_k50":
         bench_sift_k50(args, log)
+        return
+    if args.workload == "learned_ceiling":
+        bench_learned_ceiling(args, log)
         return
 
     if args.form:
