@@ -265,11 +265,14 @@ constexpr int kRT = 16;            // rows per tile
 constexpr int kRTHalfW = 16;       // widest half kept in registers
 constexpr int kRTQMax = 16384;     // floats of a tile's staged rows (padded to d + 1)
 
-__host__ __device__ inline bool learned_tiles_ok(int sk, int d, int ns, int wmax) {
-    return feat_cent_staged(sk, d) && kRT * (d + 1) <= kRTQMax && wmax <= kRTHalfW && 2 * ns + 1 <= 32;
-}
-inline size_t learned_tile_lds(int sk, int d) {
+constexpr size_t kRTLdsMax = 128 * 1024;   // dynamic LDS of the tile kernel (its static arrays take ~13 KB more)
+
+__host__ __device__ inline size_t learned_tile_lds(int sk, int d) {
     return kFeatHalfBytes + 4 * (size_t)sk * d + 4 * (size_t)kRT * (d + 1) + 2 * (size_t)kH * kH;
+}
+__host__ __device__ inline bool learned_tiles_ok(int sk, int d, int ns, int wmax) {
+    return feat_cent_staged(sk, d) && kRT * (d + 1) <= kRTQMax && wmax <= kRTHalfW && 2 * ns + 1 <= 32 &&
+           learned_tile_lds(sk, d) <= kRTLdsMax;
 }
 
 // The smallest squared distance from a query half qp (w <= HW values) to the

@@ -155,7 +155,8 @@ def test_features_match_oracle(suco):
     ix.free()
 
 
-@pytest.mark.parametrize("d,ns,sk,nq", [(128, 8, 16, 300), (96, 8, 20, 33), (256, 4, 12, 50), (28, 3, 9, 16)])
+@pytest.mark.parametrize("d,ns,sk,nq", [(128, 8, 16, 300), (96, 8, 20, 33), (256, 4, 12, 50), (28, 3, 9, 16),
+                                        (480, 15, 34, 40)])
 def test_fused_alphas_equal_features_then_predict(suco, d, ns, sk, nq):
     """The query path's fused kernel (sixteen rows at a time when the widest
     half has at most 16 dimensions, else row by row) gives exactly the alphas
