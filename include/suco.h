@@ -147,6 +147,8 @@ SUCO_API int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32
 #define SUCO_INDEX_BYTE_ROWS 1
 #define SUCO_INDEX_BF16 2
 #define SUCO_INDEX_L1 4       /* built with SUCO_BUILD_L1: the Manhattan distance throughout */
+#define SUCO_INDEX_SPARSE 8   /* queries may take the sparse collision step (N_s <= 31, n <= 2^24, not
+                                 SUCO_BUILD_NO_SPARSE, and the device's LDS holds its tables) */
 SUCO_API int suco_index_flags(const suco_index *ix, int32_t *flags);
 
 /* Activation rule of step 2 for the queries that follow on this index (each

@@ -50,7 +50,7 @@ BUILD_BF16 = 2
 BUILD_NO_SPARSE = 4
 BUILD_L1 = 8
 BF16_S1 = 1
-INDEX_BYTE_ROWS, INDEX_BF16, INDEX_L1 = 1, 2, 4
+INDEX_BYTE_ROWS, INDEX_BF16, INDEX_L1, INDEX_SPARSE = 1, 2, 4, 8
 ACT_DYNAMIC, ACT_MULTISEQ = 0, 1
 
 
@@ -235,7 +235,7 @@ class Index:
         return {s: (float(ms[j]), int(cnt[j])) for j, s in enumerate(STAGES)}
 
     def flags(self) -> int:
-        """INDEX_BYTE_ROWS | INDEX_BF16 bits (see suco_index_flags)."""
+        """INDEX_BYTE_ROWS | INDEX_BF16 | INDEX_L1 | INDEX_SPARSE bits (see suco_index_flags)."""
         f = C.c_int32(0)
         _check(lib().suco_index_flags(self._h, C.byref(f)))
         return int(f.value)

@@ -950,10 +950,11 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     thread an equal share) places the low 12 bits of each into its bucket's
 //     slots (buckets sized exactly beforehand from the index's count of each
 //     cell's ids per bucket);
-//  2. a wave takes a bucket: 4-bit scores are counted in the wave's 2 KB
-//     window (a 32-bit LDS atomic add of 1 << 4*(low & 7): an id occurs once
-//     per subspace and N_s <= 15, so no nibble carries), then every id claims
-//     its nibble with an atomic AND that clears it: the first claimant of a
+//  2. a wave takes a bucket: its scores are counted in the wave's window, 4
+//     bits an id (8 ids a word, 2 KB, for N_s <= 15) or 5 bits (6 a word,
+//     2.7 KB, for N_s <= 31), with 32-bit LDS atomic adds of 1 at the id's
+//     field (an id occurs once per subspace, so no field carries), then
+//     every id claims its field with an atomic AND that clears it: the first claimant of a
 //     point gets its score, later ones get 0, and the window ends clear.  The
 //     bucket's points of score 1 replace its slots' front (the slots already
 //     read), those of score s >= 2 go to one list of the work-group as
@@ -966,18 +967,18 @@ __global__ __launch_bounds__(NT) void k_collide(QueryPass a) {
 //     with all or none of theirs copy them, and the one bucket cut inside
 //     finds its cut id by marking its level-T ids in a 4096-bit map and
 //     counting.  Candidates are appended in no particular order.
-// A query is left to the tiled steps (route 1) when N_s > 15, it has
+// A query is left to the tiled steps (route 1) when N_s > 31, it has
 // kSpMaxRuns activated cells or more, more activated ids than the slots, more
 // points of score 2 or more than the slots past its ids hold, or T = 0 (fewer
 // than B points collide: the score-0 points are the tiled selection's case);
 // otherwise route 0, and the tiled collision and selection kernels skip the
 // query.
 struct SparseLds {
-    uint32_t H[kSpMaxNs + 2];        // H[s]: points of score s >= 2
+    uint32_t H[kSpMaxNs5 + 2];       // H[s]: points of score s >= 2
     uint32_t sink[kWave];            // targets of the atomics of empty slots, one word per lane
     uint32_t red[2 * kSpWaves + 2];
     uint32_t zfree[kSpWaves];        // unmarked ids below B per bucket (fewer than B points collide)
-    uint32_t cpre[kSpMaxNs + 1];     // activated cells of the subspaces before i
+    uint32_t cpre[kSpMaxNs5 + 1];    // activated cells of the subspaces before i
     uint32_t nh;                     // points in the list of scores >= 2 (may pass its capacity)
     uint32_t out;                    // candidates written
     int nruns, flag, cutb;
@@ -1026,13 +1027,23 @@ __device__ __forceinline__ void sp_walk(const QueryPass &a, const uint2 *runs, c
     }
 }
 
+// A wave's score window for SB-bit scores: the word of low id lo and the
+// position of its field (8 ids a word at 4 bits, 6 at 5 bits; a field never
+// carries: an id occurs once per subspace and N_s < 2^SB).
+template <int SB>
+__device__ __forceinline__ uint32_t sp_word(uint32_t lo) { return SB == 4 ? lo >> 3 : lo / 6u; }
+template <int SB>
+__device__ __forceinline__ uint32_t sp_shift(uint32_t lo) { return SB == 4 ? (lo & 7u) << 2 : (lo - 6u * (lo / 6u)) * 5u; }
+
 // One bucket by one wave (step 2).  seg holds its len low ids and receives
 // its points of score 1 at the front; those of higher score go to the list
 // hl (capacity hcap, count *hn); sink takes the atomics of empty slots.
 // Returns the number of points of score 1.
+template <int SB>
 __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, const int b, uint16_t *seg,
                                               const uint32_t len, uint32_t *win, uint32_t *hl, const uint32_t hcap,
                                               uint32_t *hn, uint32_t *H, uint32_t *sink) {
+    constexpr uint32_t SM = (1u << SB) - 1u;
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int UQ = 4;
     // a bucket of at most UQ*64 ids (the common case) is read once: the claims
@@ -1050,20 +1061,17 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
         for (int q = 0; q < UQ; ++q) {
             if (j0 + (uint32_t)(q * kWave) >= len) break;             // the same in every lane
             const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
-            atomicAdd(v ? &win[u[q] >> 3] : &sink[lane], v ? 1u << ((u[q] & 7u) << 2) : 0u);
+            atomicAdd(v ? &win[sp_word<SB>(u[q])] : &sink[lane], v ? 1u << sp_shift<SB>(u[q]) : 0u);
         }
     }
     const bool one = len <= (uint32_t)(UQ * kWave);
     if (a.scores != nullptr) {
         // dense scores on request (parity tests): lane l writes ids 64l .. 64l + 63 below n
         uint8_t *row = a.scores + (int64_t)ql * a.ix.P * a.ix.TILE;
-        const int64_t id0 = (int64_t)b * kSpBucket + 64 * lane;
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t x = win[8 * lane + k];
-            for (int nib = 0; nib < 8; ++nib) {
-                const int64_t id = id0 + 8 * k + nib;
-                if (id < a.ix.n) row[id] = (uint8_t)((x >> (4 * nib)) & 15u);
-            }
+        const int64_t id0 = (int64_t)b * kSpBucket;
+        for (int k = 0; k < 64; ++k) {
+            const uint32_t lo = 64u * (uint32_t)lane + (uint32_t)k;
+            if (id0 + lo < a.ix.n) row[id0 + lo] = (uint8_t)((win[sp_word<SB>(lo)] >> sp_shift<SB>(lo)) & SM);
         }
     }
     // claims; the front entries written in a step lie below the step's end,
@@ -1083,13 +1091,13 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
             const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
-            const uint32_t sh = (u[q] & 7u) << 2;
-            old[q] = atomicAnd(v ? &win[u[q] >> 3] : &sink[lane], v ? ~(15u << sh) : ~0u);
+            const uint32_t sh = sp_shift<SB>(u[q]);
+            old[q] = atomicAnd(v ? &win[sp_word<SB>(u[q])] : &sink[lane], v ? ~(SM << sh) : ~0u);
         }
 #pragma unroll
         for (int q = 0; q < UQ; ++q) {
             const bool v = j0 + (uint32_t)(q * kWave + lane) < len;
-            sv[q] = v ? (old[q] >> ((u[q] & 7u) << 2)) & 15u : 0u;
+            sv[q] = v ? (old[q] >> sp_shift<SB>(u[q])) & SM : 0u;
         }
         uint64_t mh[UQ];
         uint32_t nh = 0;
@@ -1109,7 +1117,7 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
             for (int q = 0; q < UQ; ++q) {
                 if (sv[q] >= 2u) {
                     const uint32_t at = base + lanes_below(mh[q]);
-                    if (at < hcap) hl[at] = ((id0 | u[q]) << 4) | sv[q];
+                    if (at < hcap) hl[at] = ((id0 | u[q]) << SB) | sv[q];
                     atomicAdd(&H[sv[q]], 1u);
                 }
                 base += (uint32_t)__popcll(mh[q]);
@@ -1166,7 +1174,11 @@ __device__ __forceinline__ void leave_to_tiled(const QueryPass &a, const int ql)
     a.tlist[atomicAdd(a.ntl, 1)] = ql;
 }
 
+template <int SB>
 __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
+    constexpr uint32_t SM = (1u << SB) - 1u;
+    constexpr int WW = sp_win_words(SB);
+    constexpr int kMaxNsSB = SB == 4 ? kSpMaxNs : kSpMaxNs5;
     extern __shared__ uint4 sp_dyn[];
     __shared__ SparseLds S;
     const int NB = a.ix.NB, ns = a.ix.ns, K = a.ix.K;
@@ -1177,31 +1189,31 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
     uint32_t *bfill = rcell + kSpMaxRuns;                                  // [NB] the walk's cursor in each bucket
     uint32_t *boff = bfill + NBp;                                          // [NB] first slot of each bucket
     uint32_t *bx = boff + NBp;                                             // [NB] points of score 1, then level-T points
-    uint32_t *win_all = bx + NBp;                                          // [kSpWaves][kSpWords], 16-byte aligned
-    uint16_t *raw = reinterpret_cast<uint16_t *>(win_all + kSpWaves * kSpWords);   // slots: each bucket's low ids, then its score-1 points
-    uint32_t *win = win_all + w * kSpWords;
+    uint32_t *win_all = bx + NBp;                                          // [kSpWaves][WW], 16-byte aligned
+    uint16_t *raw = reinterpret_cast<uint16_t *>(win_all + kSpWaves * WW); // slots: each bucket's low ids, then its score-1 points
+    uint32_t *win = win_all + w * WW;
     const int nq = pass_nq(a.nq_dev, a.q_base, a.nq);
     const int per = (NB + kSpThreads - 1) / kSpThreads;
     const int b0t = tid * per < NB ? tid * per : NB, b1t = b0t + per < NB ? b0t + per : NB;
-    for (int j = tid; j < kSpWaves * kSpWords; j += kSpThreads) win_all[j] = 0u;
+    for (int j = tid; j < kSpWaves * WW; j += kSpThreads) win_all[j] = 0u;
     for (int j = tid; j < kWave; j += kSpThreads) S.sink[j] = 0u;
     for (int rq = blockIdx.x; rq < nq; rq += gridDim.x) {
         const int ql = a.order ? a.order[rq] : rq;
         // ---- the query's size: activated cells (wave 0, a lane per subspace)
         if (w == 0) {
-            const bool on = lane < ns && ns <= kSpMaxNs;
+            const bool on = lane < ns && ns <= kMaxNsSB;
             const uint32_t c = on ? (uint32_t)a.ncells[ql * ns + lane] : 0u;
             const uint32_t ci = wave_incl_scan(c);
-            if (lane <= kSpMaxNs) S.cpre[lane] = ci - c;
+            if (lane <= kMaxNsSB) S.cpre[lane] = ci - c;
             const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
             if (lane == 0) {
                 S.nruns = (int)nr;
-                S.flag = (ns > kSpMaxNs || nr >= (uint32_t)kSpMaxRuns || a.sp_cap == 0) ? 1 : 0;
+                S.flag = (ns > kMaxNsSB || nr >= (uint32_t)kSpMaxRuns || a.sp_cap == 0) ? 1 : 0;
                 S.nh = 0u;
                 S.out = 0u;
             }
         }
-        for (int t = tid; t < kSpMaxNs + 2; t += kSpThreads) S.H[t] = 0u;
+        for (int t = tid; t < kMaxNsSB + 2; t += kSpThreads) S.H[t] = 0u;
         __syncthreads();
         if (S.flag) {
             if (tid == 0) leave_to_tiled(a, ql);
@@ -1232,7 +1244,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         }
         // the list of points of score >= 2 takes the slots past the query's own
         const uint32_t tot2 = (total + 1u) & ~1u;
-        uint32_t *hl = reinterpret_cast<uint32_t *>(raw + tot2);                // (id << 4 | score), score >= 2
+        uint32_t *hl = reinterpret_cast<uint32_t *>(raw + tot2);                // (id << SB | score), score >= 2
         const uint32_t hcap = tot2 < (uint32_t)a.sp_cap ? ((uint32_t)a.sp_cap - tot2) / 2u : 0u;
         if (tid <= nruns) runs[tid] = make_uint2(tid < nruns ? rstart : 0u, tid < nruns ? rpos : total);
         for (uint32_t q = (rpos + 1023u) >> 10; rlen && (q << 10) < rpos + rlen; ++q) S.crun[q] = (uint32_t)tid;
@@ -1304,7 +1316,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         __syncthreads();
         // ---- 2. every bucket
         for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t n1 = sp_bucket(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, hcap, &S.nh, S.H, S.sink);
+            const uint32_t n1 = sp_bucket<SB>(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, hcap, &S.nh, S.H, S.sink);
             if (lane == 0) bx[b] = n1;
         }
         __syncthreads();
@@ -1340,7 +1352,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             for (int b = b0t; b < b1t; ++b) bx[b] = 0u;
             __syncthreads();
             for (uint32_t j = (uint32_t)tid; j < nhl; j += kSpThreads)
-                if ((hl[j] & 15u) == (uint32_t)T) atomicAdd(&bx[hl[j] >> (4 + kSpShift)], 1u);
+                if ((hl[j] & SM) == (uint32_t)T) atomicAdd(&bx[hl[j] >> (SB + kSpShift)], 1u);
             __syncthreads();
         }
         // each bucket's share of the R lowest level-T ids (bfill: take), and the cut bucket
@@ -1373,8 +1385,8 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
                 } else {
                     cut = sp_cut(nhl, take, win, [&](uint32_t j) {
                         const uint32_t e = hl[j];
-                        return ((e & 15u) == (uint32_t)T && (int)(e >> (4 + kSpShift)) == cutb)
-                                   ? (e >> 4) & (kSpBucket - 1) : (uint32_t)kSpBucket;
+                        return ((e & SM) == (uint32_t)T && (int)(e >> (SB + kSpShift)) == cutb)
+                                   ? (e >> SB) & (kSpBucket - 1) : (uint32_t)kSpBucket;
                     });
                 }
             }
@@ -1392,7 +1404,7 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         for (uint32_t j0 = (uint32_t)(w * kWave); j0 < nhl; j0 += (uint32_t)kSpThreads) {
             const uint32_t j = j0 + (uint32_t)lane;
             const uint32_t e = hl[j < nhl ? j : 0u];
-            const uint32_t sv = e & 15u, id = e >> 4;
+            const uint32_t sv = e & SM, id = e >> SB;
             const bool t = j < nhl && (sv > (uint32_t)T || (sv == (uint32_t)T && take_t(id)));
             sp_emit(t, id, cq, B, &S.out);
         }
@@ -1416,8 +1428,8 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             // b's in wave b's window (clear), and wave b takes its bucket's share of
             // the unmarked ids in id order
             for (uint32_t j = (uint32_t)tid; j < nhl; j += kSpThreads) {
-                const uint32_t id = hl[j] >> 4;
-                if (id < B) atomicOr(&win_all[(id >> kSpShift) * kSpWords + ((id & (kSpBucket - 1)) >> 5)], 1u << (id & 31u));
+                const uint32_t id = hl[j] >> SB;
+                if (id < B) atomicOr(&win_all[(id >> kSpShift) * WW + ((id & (kSpBucket - 1)) >> 5)], 1u << (id & 31u));
             }
             if ((uint32_t)w < nb0) {
                 const uint16_t *f = raw + boff[w];
@@ -2111,10 +2123,12 @@ Launch plan_collide(const QueryPass &p, int cap) {
 
 Launch plan_collide_sparse(const QueryPass &p, int cap) {
     Launch L;
-    L.lds = sp_lds_bytes(p.ix.NB, p.sp_cap);
+    const int sb = sp_score_bits(p.ix.ns);
+    L.lds = sp_lds_bytes(p.ix.NB, p.sp_cap, sb);
     L.grid = dim3(grid_for(p.nq, cap));
     L.block = dim3(kSpThreads);
-    L.func = reinterpret_cast<const void *>(&k_collide_sparse);
+    L.func = sb == 4 ? reinterpret_cast<const void *>(&k_collide_sparse<4>)
+                     : reinterpret_cast<const void *>(&k_collide_sparse<5>);
     return L;
 }
 
@@ -2181,8 +2195,11 @@ hipError_t launch(const Launch &L, void *arg, hipStream_t s) {
 
 int sparse_static_lds() {
     hipFuncAttributes at{};
-    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_collide_sparse)) != hipSuccess) return -1;
-    return (int)at.sharedSizeBytes;
+    hipFuncAttributes at5{};
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_collide_sparse<4>)) != hipSuccess ||
+        hipFuncGetAttributes(&at5, reinterpret_cast<const void *>(&k_collide_sparse<5>)) != hipSuccess)
+        return -1;
+    return (int)std::max(at.sharedSizeBytes, at5.sharedSizeBytes);
 }
 
 int collide_static_lds() {

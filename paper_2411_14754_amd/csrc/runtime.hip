@@ -72,11 +72,11 @@ int index_common(const float *D, int64_t n, int d, int ns, int sk, const suco_bu
     // The sparse collision step: one work-group per CU (160 KB of LDS per CU on
     // gfx950) with its tables, windows and as many ids as fit.
     ix->NB = (int)((n + kSpBucket - 1) / kSpBucket);
-    if (!ix->no_sparse && ns <= kSpMaxNs && ix->NB <= kSpMaxBuckets) {
+    if (!ix->no_sparse && ns <= kSpMaxNs5 && ix->NB <= kSpMaxBuckets) {
         const int sps = sparse_static_lds();
         if (sps < 0) { delete ix; return fail(SUCO_E_HIP, "cannot query the sparse collision kernel's attributes"); }
         const int64_t budget = std::min<int64_t>(max_lds, 160 * 1024) - sps;
-        const int64_t cap = (budget - (int64_t)sp_lds_bytes(ix->NB, 0)) / 2 / 8 * 8;
+        const int64_t cap = (budget - (int64_t)sp_lds_bytes(ix->NB, 0, sp_score_bits(ns))) / 2 / 8 * 8;
         ix->sp_cap = cap >= 4096 ? (int)std::min<int64_t>(cap, (int64_t)kSpMaxChunks * 1024) : 0;
     }
     const int64_t P0 = 8 * ((n + 8LL * tile_max - 1) / (8LL * tile_max));
@@ -771,7 +771,8 @@ int suco_index_info(const suco_index *ix, int64_t *n, int32_t *d, int32_t *n_s, 
 int suco_index_flags(const suco_index *ix, int32_t *flags) {
     if (!index_ok(ix)) return fail(SUCO_E_STATE, "invalid or freed index handle");
     if (!flags) return fail(SUCO_E_INVAL, "flags must not be NULL");
-    *flags = (ix->X8 ? SUCO_INDEX_BYTE_ROWS : 0) | (ix->Xb ? SUCO_INDEX_BF16 : 0) | (ix->metric ? SUCO_INDEX_L1 : 0);
+    *flags = (ix->X8 ? SUCO_INDEX_BYTE_ROWS : 0) | (ix->Xb ? SUCO_INDEX_BF16 : 0) | (ix->metric ? SUCO_INDEX_L1 : 0) |
+             (ix->sp_cap ? SUCO_INDEX_SPARSE : 0);
     return SUCO_OK;
 }
 

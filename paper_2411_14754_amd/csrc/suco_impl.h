@@ -43,8 +43,11 @@ constexpr int kSpShift = 12;
 constexpr int kSpBucket = 1 << kSpShift;
 constexpr int kSpThreads = 1024;
 constexpr int kSpWaves = kSpThreads / kWave;
-constexpr int kSpWords = kSpBucket / 8;
-constexpr int kSpMaxNs = 15;        // a 4-bit score
+constexpr int kSpMaxNs = 15;        // 4-bit scores, 8 ids a window word
+constexpr int kSpMaxNs5 = 31;       // 5-bit scores, 6 ids a window word (N_s of 16 to 31)
+__host__ __device__ constexpr int sp_score_bits(int ns) { return ns <= kSpMaxNs ? 4 : 5; }
+// words of one wave's score window: 4096 ids at 8 a word, or at 6 a word (683, padded to 16 bytes)
+__host__ __device__ constexpr int sp_win_words(int sb) { return sb == 4 ? kSpBucket / 8 : 688; }
 constexpr int kSpMaxBuckets = 4096; // n <= 2^24
 constexpr int kSpMaxRuns = 1024;    // activated cells of a query, all subspaces
 constexpr int kSpMaxChunks = 128;   // 1024-position chunks of a query's activated ids (the slots hold fewer)
@@ -53,8 +56,8 @@ constexpr int kSpMaxChunks = 128;   // 1024-position chunks of a query's activat
 // waves' score windows and the slots (a query's activated ids, then its list
 // of points of score >= 2).
 __host__ __device__ inline int sp_nb_padded(int NB) { return (NB + 4) & ~3; }
-__host__ __device__ inline size_t sp_lds_bytes(int NB, int cap) {
-    return 12 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * kSpWords +
+__host__ __device__ inline size_t sp_lds_bytes(int NB, int cap, int sb) {
+    return 12 * (size_t)kSpMaxRuns + 12 * (size_t)sp_nb_padded(NB) + 4 * (size_t)kSpWaves * sp_win_words(sb) +
            2 * (size_t)((cap + 7) & ~7);
 }
 

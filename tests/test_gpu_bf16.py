@@ -79,7 +79,7 @@ def test_bf16_rerank_equals_plain_bitwise(suco, k):
     X, Q = W.data(), W.queries()
     print(f"case: mixture128 bf16 re-rank k={k}", flush=True)
     oix, gix, _ = make(suco, X, 8, 16)
-    assert gix.flags() == suco.INDEX_BF16                  # real-valued data: no byte rows
+    assert gix.flags() & ~suco.INDEX_SPARSE == suco.INDEX_BF16   # real-valued data: no byte rows
     beta = 0.005 if k < 64 else 0.01
     ids, dists = gix.query(torch.from_numpy(Q).cuda(), k, 0.05, beta)
     b = query_all(gix, Q, k, 0.05, beta)

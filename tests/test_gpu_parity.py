@@ -236,6 +236,39 @@ def test_sparse_step_equals_tiled_step(suco, alpha, beta):
     td.free()
 
 
+@pytest.mark.parametrize("ns,alpha,beta", [(16, 0.003, 0.005), (16, 0.0005, 0.02), (20, 0.01, 0.005),
+                                           (31, 0.002, 0.01)])
+def test_sparse_step_five_bit_scores(suco, ns, alpha, beta):
+    """N_s of 16 to 31: the sparse step keeps 5-bit scores (six ids a window
+    word) and equals the tiled step bitwise: candidates, SC-scores, top-k."""
+    W = synth.Workload(2)
+    X = W.data(100_000)
+    Q = W.queries(200)
+    _, c32, asg, _ = oracle.build_index(X, ns, 16, iters=2, seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    sp = suco.Index.from_index(Xd, ns, 16, c32, asg)
+    td = suco.Index.from_index(Xd, ns, 16, c32, asg, flags=suco.BUILD_NO_SPARSE)
+    assert sp.flags() & suco.INDEX_SPARSE and not td.flags() & suco.INDEX_SPARSE
+    aq = (alpha * np.exp(np.random.default_rng(2).uniform(-1.0, 1.0, Q.shape[0]))).astype(np.float32)
+    print(f"case: five-bit sparse vs tiled ns={ns} alpha~{alpha} beta={beta}", flush=True)
+    a = debug(sp, Q, 10, 0.0, beta, alpha_q=aq)
+    b = debug(td, Q, 10, 0.0, beta, alpha_q=aq)
+    for key in ("ids", "dists", "cand", "scores", "ncells", "aprime"):
+        assert np.array_equal(a[key], b[key]), key
+    # the sparse step took the queries: the tiled collision step had little left to do
+    Qd, aqd = torch.from_numpy(Q).cuda(), torch.from_numpy(aq).cuda()
+    prof = {}
+    for name, ix in (("sparse", sp), ("tiled", td)):
+        ix.profile(True)
+        ix.profile_read()
+        ix.query_alpha(Qd, 10, aqd, beta)
+        prof[name] = ix.profile_read()
+        ix.profile(False)
+    assert prof["sparse"]["collide"][0] < 0.5 * prof["tiled"]["collide"][0]
+    sp.free()
+    td.free()
+
+
 def test_per_query_alpha(suco):
     W = synth.Workload(1)
     X, Q = W.data(8000), W.queries(25)
@@ -294,7 +327,7 @@ def test_save_load_round_trip(suco, tmp_path):
     bpath = str(tmp_path / "bf16.suco")
     bix.save(bpath)
     blix = suco.Index.load(bpath)
-    assert blix.flags() == bix.flags() == suco.INDEX_BYTE_ROWS | suco.INDEX_BF16
+    assert blix.flags() == bix.flags() == suco.INDEX_BYTE_ROWS | suco.INDEX_BF16 | suco.INDEX_SPARSE
     Qi = torch.from_numpy(synth.Workload(2).queries(32)).cuda()
     s0 = bix.query_bf16(Qi, 10, 0.02, 0.01)
     s1 = blix.query_bf16(Qi, 10, 0.02, 0.01)
@@ -548,7 +581,7 @@ def test_byte_rows_equal_fp32_rows(suco):
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     a = suco.Index.from_index(Xd, 8, 20, c32, asg)
     b = suco.Index.from_index(Xd, 8, 20, c32, asg, flags=suco.BUILD_NO_BYTE_ROWS)
-    assert a.flags() == suco.INDEX_BYTE_ROWS and b.flags() == 0
+    assert a.flags() & ~suco.INDEX_SPARSE == suco.INDEX_BYTE_ROWS and b.flags() & ~suco.INDEX_SPARSE == 0
     ra = a.query(Qd, 10, 0.02, 0.01)
     rb = b.query(Qd, 10, 0.02, 0.01)
     torch.cuda.synchronize()
