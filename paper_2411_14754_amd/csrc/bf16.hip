@@ -1,7 +1,7 @@
 // BF16 split precision: the query path with BF16 arithmetic where it is safe.
 //
 // Centre distances (step 1) on the matrix cores.  For 16 queries and 16 centres
-// of one subspace half, q.c comes from the 16x16x16 BF16 MFMA with FP32
+// of one subspace half, q.c comes from the 16x16x32 BF16 MFMA with FP32
 // accumulation over the half's dimensions (zero-padded to a multiple of 16),
 // and D = |q^|^2 + |c^|^2 - 2 q^.c^ (clamped at 0), where ^ is rounding to BF16.
 //
@@ -28,7 +28,7 @@
 
 namespace suco {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // Round to nearest even, FP32 -> BF16 bits (finite inputs; inf and nan kept).
@@ -89,37 +89,37 @@ __global__ __launch_bounds__(256) void k_bf16_centres(const float *cent, const H
 }
 
 // --------------------------------------------------- centre distances --
-// Block (16 queries, one half); wave w takes centres 16w .. 16w+15.  Operand
-// layout of the 16x16x16 BF16 MFMA on a 64-lane wave: lane l supplies
-// A[l % 16][4(l/16) .. 4(l/16)+3] and B[4(l/16) .. +3][l % 16] and receives
-// D[4(l/16) .. +3][l % 16].
+// Block (16 queries, one half); wave w takes centres 16w .. 16w+15, with
+// gfx950's 16x16x32 BF16 MFMA: lane l supplies row l % 16 of A and column
+// l % 16 of B, eight K positions each (the same eight for A and B: 8(l/16) ..
+// 8(l/16)+7 of the step's 32), and receives D[4(l/16) .. +3][l % 16].
 __global__ __launch_bounds__(512) void k_centre_dists_bf16(CentreBf16Pass p) {
     const int g = blockIdx.y, q0 = blockIdx.x * 16;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const HalfDims hd = p.halves[g];
     const int sk = p.sk, c0 = 16 * w;
     if (c0 >= sk || q0 >= p.nq) return;
-    const int r = lane & 15, kq = 4 * (lane >> 4);
+    const int r = lane & 15, kq = 8 * (lane >> 4);
     const int qa = q0 + r, cb = c0 + r;
     const bool qok = qa < p.nq, cok = cb < sk;
     const float *qrow = p.Q + (int64_t)(qok ? qa : 0) * p.d + hd.dim0;
     const uint16_t *crow = p.centb + (int64_t)sk * hd.dim0 + (int64_t)(cok ? cb : 0) * hd.w;
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
     float qn = 0.f;   // this lane's part of |q^|^2 for query qa
-    for (int k0 = 0; k0 < hd.w; k0 += 16) {
-        bf16x4_t a, b;
+    for (int k0 = 0; k0 < hd.w; k0 += 32) {
+        bf16x8_t a, b;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < 8; ++t) {
             const int kk = k0 + kq + t;
             const bool in = kk < hd.w;
             const uint16_t qb = (in && qok) ? bf16_bits(qrow[kk]) : (uint16_t)0;
             const uint16_t cbits = (in && cok) ? crow[kk] : (uint16_t)0;
-            a[t] = (short)qb;
-            b[t] = (short)cbits;
+            a[t] = __builtin_bit_cast(__bf16, qb);
+            b[t] = __builtin_bit_cast(__bf16, cbits);
             const float qv = bf16_val(qb);
             qn = fmaf(qv, qv, qn);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
     // lanes r, r+16, r+32, r+48 hold the four k-slices of query q0 + r
     qn += __shfl_xor(qn, 16, kWave);
