@@ -1189,18 +1189,23 @@ def main():
         grid = learned.alpha_grid(0.0005, 0.05)
         net, info = learned.train_budget_model(ix, Qt[:m_tr], gt_t[:m_tr], k, beta, grid, epochs=args.epochs)
         # the predicted alpha is clamped to [0.0005, amax]; amax is chosen on the held-out queries (not the
-        # evaluation ones) as the fastest of a few clamps once the scale is calibrated for each: a query
-        # whose activated points outgrow one CU's LDS leaves the sparse collision step for the slower
-        # tiled one, so a tighter clamp can pay more than the recall it costs
+        # evaluation ones) as the fastest of a few clamps whose calibrated scale reaches the target recall
+        # there: a query whose activated points outgrow one CU's LDS leaves the sparse collision step for
+        # the slower tiled one, so a tighter clamp can pay more than the recall it costs
         amin = grid[0]
         Qv, gt_v = Qt[m_tr:], gt_t[m_tr:]
         best_clamp = None
-        for amax_c in (0.0035, 0.005, 0.01):
+        for amax_c in (0.0025, 0.003, 0.0035, 0.005, 0.01):
             sc = learned.calibrate_scale(ix, net, Qv, gt_v, k, beta, args.target_recall, amin, amax_c)
+            ids_v, _, _ = suco.query_learned(ix, net, Qv, k, beta, sc, amin, amax_c)
+            rec_v = recall_at(ids_v, gt_v)
             ms_c, _ = timed_steps(lambda: suco.query_learned(ix, net, Qv, k, beta, sc, amin, amax_c), 3, 1)
-            log(f"clamp {amax_c}: scale {sc:.3f}, {ms_c / 3:.3f} ms per {Qv.shape[0]} held-out queries")
-            if best_clamp is None or ms_c < best_clamp[0]:
+            log(f"clamp {amax_c}: scale {sc:.3f}, held-out recall@10 {rec_v:.4f}, {ms_c / 3:.3f} ms per "
+                f"{Qv.shape[0]} held-out queries")
+            if rec_v >= args.target_recall and (best_clamp is None or ms_c < best_clamp[0]):
                 best_clamp = (ms_c, amax_c, sc)
+        if best_clamp is None:      # no clamp reaches the target: the widest one
+            best_clamp = (ms_c, amax_c, sc)
         _, amax, scale = best_clamp
         train_s = time.time() - t0
         log(f"learned budget: trained in {train_s:.1f}s, loss {info['loss'][0]:.3f} -> {info['loss'][-1]:.3f}, "
