@@ -1127,6 +1127,99 @@ __device__ __forceinline__ uint32_t sp_bucket(const QueryPass &a, const int ql, 
     return n1;
 }
 
+// Two buckets by one wave, each of at most 4*64 ids, in windows win0 and
+// win1: the same steps as sp_bucket, with the loads, the counting atomics and
+// the claims of both buckets issued together, so that the wave has two
+// buckets' round trips in flight.  n1[k] receives bucket k's points of score 1.
+template <int SB>
+__device__ __forceinline__ void sp_bucket_pair(const QueryPass &a, const int ql, const int b0, const int b1,
+                                               uint16_t *seg0, const uint32_t len0, uint16_t *seg1,
+                                               const uint32_t len1, uint32_t *win0, uint32_t *win1, uint32_t *hl,
+                                               const uint32_t hcap, uint32_t *hn, uint32_t *H, uint32_t *sink,
+                                               uint32_t (&n1)[2]) {
+    constexpr uint32_t SM = (1u << SB) - 1u;
+    constexpr int UQ = 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    uint16_t *seg[2] = {seg0, seg1};
+    const uint32_t len[2] = {len0, len1};
+    uint32_t *win[2] = {win0, win1};
+    const int bb[2] = {b0, b1};
+    uint32_t u[2][UQ];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const uint32_t j = (uint32_t)(q * kWave + lane);
+            u[k][q] = seg[k][j < len[k] ? j : 0u];
+        }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            if ((uint32_t)(q * kWave) >= len[k]) continue;              // the same in every lane
+            const bool v = (uint32_t)(q * kWave + lane) < len[k];
+            atomicAdd(v ? &win[k][sp_word<SB>(u[k][q])] : &sink[lane], v ? 1u << sp_shift<SB>(u[k][q]) : 0u);
+        }
+    if (a.scores != nullptr) {
+        // dense scores on request (parity tests): lane l writes ids 64l .. 64l + 63 below n
+        uint8_t *row = a.scores + (int64_t)ql * a.ix.P * a.ix.TILE;
+        for (int k = 0; k < 2; ++k) {
+            const int64_t id0 = (int64_t)bb[k] * kSpBucket;
+            for (int e = 0; e < 64; ++e) {
+                const uint32_t lo = 64u * (uint32_t)lane + (uint32_t)e;
+                if (id0 + lo < a.ix.n) row[id0 + lo] = (uint8_t)((win[k][sp_word<SB>(lo)] >> sp_shift<SB>(lo)) & SM);
+            }
+        }
+    }
+    uint32_t old[2][UQ];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            old[k][q] = 0u;
+            if ((uint32_t)(q * kWave) >= len[k]) continue;
+            const bool v = (uint32_t)(q * kWave + lane) < len[k];
+            const uint32_t sh = sp_shift<SB>(u[k][q]);
+            old[k][q] = atomicAnd(v ? &win[k][sp_word<SB>(u[k][q])] : &sink[lane], v ? ~(SM << sh) : ~0u);
+        }
+    uint32_t sv[2][UQ];
+    uint64_t mh[2][UQ];
+    uint32_t nh = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        n1[k] = 0u;
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const bool v = (uint32_t)(q * kWave + lane) < len[k];
+            sv[k][q] = v ? (old[k][q] >> sp_shift<SB>(u[k][q])) & SM : 0u;
+            const uint64_t m1 = __ballot(sv[k][q] == 1u);
+            mh[k][q] = __ballot(sv[k][q] >= 2u);
+            nh += (uint32_t)__popcll(mh[k][q]);
+            // the front entries lie below the bucket's end, whose slots were all read above
+            if (sv[k][q] == 1u) seg[k][n1[k] + lanes_below(m1)] = (uint16_t)u[k][q];
+            n1[k] += (uint32_t)__popcll(m1);
+        }
+    }
+    if (nh) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(hn, nh);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t id0 = (uint32_t)bb[k] << kSpShift;
+#pragma unroll
+            for (int q = 0; q < UQ; ++q) {
+                if (sv[k][q] >= 2u) {
+                    const uint32_t at = base + lanes_below(mh[k][q]);
+                    if (at < hcap) hl[at] = ((id0 | u[k][q]) << SB) | sv[k][q];
+                    atomicAdd(&H[sv[k][q]], 1u);
+                }
+                base += (uint32_t)__popcll(mh[k][q]);
+            }
+        }
+    }
+}
+
 // The id below which a set's `take` lowest ids lie (its take-th lowest + 1),
 // for ids inside one bucket: one wave marks their low bits in a 4096-bit map
 // (its clear window), counts set bits in id order and clears the map.
@@ -1173,6 +1266,9 @@ __device__ __forceinline__ void leave_to_tiled(const QueryPass &a, const int ql)
     a.route[ql] = 1;
     a.tlist[atomicAdd(a.ntl, 1)] = ql;
 }
+
+constexpr int kSpPairSlots = kSpWaves * (kSpBucket / 8) * 2;   // 16-bit slots of the second 4-bit windows
+constexpr int kSpPairMinList = 4096;                             // list entries a query keeps when paired
 
 template <int SB>
 __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
@@ -1242,10 +1338,14 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
             __syncthreads();
             continue;
         }
-        // the list of points of score >= 2 takes the slots past the query's own
+        // the list of points of score >= 2 takes the slots past the query's own;
+        // when enough are left, the last kSpPairSlots of them hold a second
+        // window per wave and the buckets go two at a time
         const uint32_t tot2 = (total + 1u) & ~1u;
         uint32_t *hl = reinterpret_cast<uint32_t *>(raw + tot2);                // (id << SB | score), score >= 2
-        const uint32_t hcap = tot2 < (uint32_t)a.sp_cap ? ((uint32_t)a.sp_cap - tot2) / 2u : 0u;
+        const uint32_t hcap1 = tot2 < (uint32_t)a.sp_cap ? ((uint32_t)a.sp_cap - tot2) / 2u : 0u;
+        const bool paired = SB == 4 && hcap1 >= (uint32_t)(kSpPairSlots / 2 + kSpPairMinList);
+        const uint32_t hcap = paired ? hcap1 - (uint32_t)(kSpPairSlots / 2) : hcap1;
         if (tid <= nruns) runs[tid] = make_uint2(tid < nruns ? rstart : 0u, tid < nruns ? rpos : total);
         for (uint32_t q = (rpos + 1023u) >> 10; rlen && (q << 10) < rpos + rlen; ++q) S.crun[q] = (uint32_t)tid;
         __syncthreads();
@@ -1315,9 +1415,33 @@ __global__ __launch_bounds__(kSpThreads) void k_collide_sparse(QueryPass a) {
         });
         __syncthreads();
         // ---- 2. every bucket
-        for (int b = w; b < NB; b += kSpWaves) {
-            const uint32_t n1 = sp_bucket<SB>(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, hcap, &S.nh, S.H, S.sink);
-            if (lane == 0) bx[b] = n1;
+        if (paired) {
+            uint32_t *win2all = reinterpret_cast<uint32_t *>(raw + a.sp_cap - kSpPairSlots);
+            uint4 *z = reinterpret_cast<uint4 *>(win2all);          // slots of earlier queries: cleared
+            for (int j = tid; j < kSpPairSlots / 8; j += kSpThreads) z[j] = make_uint4(0u, 0u, 0u, 0u);
+            __syncthreads();
+            uint32_t *win2 = win2all + w * WW;
+            for (int b = w; b < NB; b += 2 * kSpWaves) {
+                const int b1 = b + kSpWaves;
+                const uint32_t l0 = bfill[b] - boff[b], l1 = b1 < NB ? bfill[b1] - boff[b1] : 0u;
+                uint32_t n1[2] = {0u, 0u};
+                if (b1 < NB && l0 <= 4u * kWave && l1 <= 4u * kWave) {
+                    sp_bucket_pair<SB>(a, ql, b, b1, raw + boff[b], l0, raw + boff[b1], l1, win, win2, hl, hcap, &S.nh,
+                                       S.H, S.sink, n1);
+                } else {
+                    n1[0] = sp_bucket<SB>(a, ql, b, raw + boff[b], l0, win, hl, hcap, &S.nh, S.H, S.sink);
+                    if (b1 < NB) n1[1] = sp_bucket<SB>(a, ql, b1, raw + boff[b1], l1, win2, hl, hcap, &S.nh, S.H, S.sink);
+                }
+                if (lane == 0) {
+                    bx[b] = n1[0];
+                    if (b1 < NB) bx[b1] = n1[1];
+                }
+            }
+        } else {
+            for (int b = w; b < NB; b += kSpWaves) {
+                const uint32_t n1 = sp_bucket<SB>(a, ql, b, raw + boff[b], bfill[b] - boff[b], win, hl, hcap, &S.nh, S.H, S.sink);
+                if (lane == 0) bx[b] = n1;
+            }
         }
         __syncthreads();
         // ---- 3. threshold: G[t] = sum of H[s] for s >= t >= 2; G[1] adds the score-1 points
